@@ -1,0 +1,221 @@
+"""Plain FP64 CPU oracle of the dynamical-core substep (ctypes binding of
+liboracle.so).  TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke
+check and the CPU-baseline leg of the benchmark, never by the product."""
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_LIB = None
+_GRID_PTRS = ("cell_edges", "cell_verts", "cell_cells", "cell_sign", "edge_cells", "edge_verts",
+              "vert_edges", "vert_cells", "vert_sign", "vert_valence", "cell_x", "cell_area",
+              "edge_x", "edge_normal", "edge_tangent", "edge_length", "dual_length", "vert_x",
+              "vert_area")
+
+
+class OrGrid(C.Structure):
+    _fields_ = [("nc", C.c_int64), ("ne", C.c_int64), ("nv", C.c_int64), ("radius", C.c_double)] + [
+        (n, C.c_void_p) for n in _GRID_PTRS]
+
+
+class OrParams(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("radius", "omega", "grav", "rd", "cpd", "p00", "beta",
+                                          "wgt_corr", "extrap", "div_damp")]
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(_build.SO):
+            _build.build()
+        L = C.CDLL(_build.SO)
+        vp, d, i = C.c_void_p, C.c_double, C.c_int
+        L.or_create.restype = vp
+        L.or_create.argtypes = [vp, i, vp, vp, vp, vp]
+        L.or_free.argtypes = [vp]
+        L.or_free.restype = None
+        L.or_set_state.argtypes = [vp] * 7
+        L.or_get_state.argtypes = [vp] * 7
+        L.or_get_flux.argtypes = [vp] * 3
+        L.or_step.argtypes = [vp, d, i]
+        L.or_vt.argtypes = [vp] * 7
+        L.or_pgrad.argtypes = [vp] * 3
+        L.or_diag.argtypes = [vp] * 3
+        for f in ("or_op_div", "or_op_grad", "or_op_tgrad", "or_op_curl", "or_op_cell_avg",
+                  "or_op_vert_avg"):
+            getattr(L, f).argtypes = [vp, vp, vp]
+            getattr(L, f).restype = None
+        L.or_op_perot.argtypes = [vp] * 7
+        L.or_op_perot.restype = None
+        L.or_thomas.argtypes = [i] + [vp] * 5
+        L.or_column.argtypes = [i, d] + [vp] * 19
+        _LIB = L
+    return _LIB
+
+
+def _p(a):
+    if a is None:
+        return None
+    assert isinstance(a, np.ndarray) and a.flags.c_contiguous, "array must be C-contiguous"
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class _GridHandle:
+    """Keeps the numpy arrays alive behind an or_grid struct."""
+
+    def __init__(self, grid):
+        self.arrays = {}
+        for n in _GRID_PTRS:
+            a = np.ascontiguousarray(getattr(grid, n))
+            self.arrays[n] = a
+        self.s = OrGrid(grid.n_cells, grid.n_edges, grid.n_verts, grid.radius,
+                        *[_p(self.arrays[n]) for n in _GRID_PTRS])
+
+    @property
+    def ref(self):
+        return C.byref(self.s)
+
+
+def params_struct(p):
+    return OrParams(p.radius, p.omega, p.grav, p.rd, p.cpd, p.p00, p.beta, p.wgt_corr, p.extrap,
+                    p.div_damp)
+
+
+class Model:
+    """The oracle's model of one case: metrics from the case's heights, state
+    from the case (or set later)."""
+
+    def __init__(self, case, params=None):
+        self.grid = case.grid
+        self.N = case.n_lev
+        self.params = params if params is not None else case.params
+        self._g = _GridHandle(case.grid)
+        self._pp = params_struct(self.params)
+        self._keep = [_f64(case.zh), _f64(case.pi_ref), _f64(case.theta_ref)]
+        self.pi_ref = self._keep[1]
+        self.h = lib().or_create(self._g.ref, self.N, *[_p(a) for a in self._keep],
+                                 C.byref(self._pp))
+        if not self.h:
+            raise RuntimeError("or_create failed")
+        self.set_state(case.vn, case.w, case.rho, case.pi, case.theta_v)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().or_free(self.h)
+            self.h = None
+
+    def set_state(self, vn, w, rho, pi, theta_v, pi_prev=None):
+        arrs = [_f64(a) for a in (vn, w, rho, pi, theta_v)]
+        pp = _f64(pi_prev) if pi_prev is not None else None
+        rc = lib().or_set_state(self.h, *[_p(a) for a in arrs], _p(pp))
+        if rc != 0:
+            raise RuntimeError("or_set_state failed")
+
+    def state(self):
+        nc, ne, N = self.grid.n_cells, self.grid.n_edges, self.N
+        out = dict(vn=np.empty((N, ne)), w=np.empty((N + 1, nc)), rho=np.empty((N, nc)),
+                   pi=np.empty((N, nc)), theta_v=np.empty((N, nc)), pi_prev=np.empty((N, nc)))
+        lib().or_get_state(self.h, *[_p(out[k]) for k in ("vn", "w", "rho", "pi", "theta_v",
+                                                           "pi_prev")])
+        return out
+
+    def flux(self):
+        nc, ne, N = self.grid.n_cells, self.grid.n_edges, self.N
+        facc, wacc = np.empty((N, ne)), np.empty((N + 1, nc))
+        lib().or_get_flux(self.h, _p(facc), _p(wacc))
+        return facc, wacc
+
+    def step(self, dt, nsub):
+        rc = lib().or_step(self.h, float(dt), int(nsub))
+        if rc != 0:
+            raise RuntimeError("or_step failed")
+
+    def vt(self, vn, w):
+        nc, ne, N = self.grid.n_cells, self.grid.n_edges, self.N
+        tvn, tw, wcc, vt = np.empty((N, ne)), np.empty((N + 1, nc)), np.empty((N + 1, nc)), \
+            np.empty((N, ne))
+        vn, w = _f64(vn), _f64(w)
+        lib().or_vt(self.h, _p(vn), _p(w), _p(tvn), _p(tw), _p(wcc), _p(vt))
+        return tvn, tw, wcc, vt
+
+    def pgrad(self, p):
+        out = np.empty((self.N, self.grid.n_edges))
+        p = _f64(p)
+        lib().or_pgrad(self.h, _p(p), _p(out))
+        return out
+
+    def diag(self):
+        m, rt = C.c_double(), C.c_double()
+        lib().or_diag(self.h, C.byref(m), C.byref(rt))
+        return m.value, rt.value
+
+
+# ---- single-level operators -------------------------------------------------
+
+def _op(name, grid, x, n_out):
+    h = _GridHandle(grid)
+    x = _f64(x)
+    out = np.empty(n_out)
+    getattr(lib(), name)(h.ref, _p(x), _p(out))
+    return out
+
+
+def div(grid, f):
+    return _op("or_op_div", grid, f, grid.n_cells)
+
+
+def grad(grid, p):
+    return _op("or_op_grad", grid, p, grid.n_edges)
+
+
+def tgrad(grid, q):
+    return _op("or_op_tgrad", grid, q, grid.n_edges)
+
+
+def curl(grid, u):
+    return _op("or_op_curl", grid, u, grid.n_verts)
+
+
+def cell_avg(grid, q):
+    return _op("or_op_cell_avg", grid, q, grid.n_cells)
+
+
+def vert_avg(grid, p):
+    return _op("or_op_vert_avg", grid, p, grid.n_verts)
+
+
+def perot(grid, pos_c, pos_e, radial_c, u):
+    h = _GridHandle(grid)
+    pos_c, pos_e, radial_c, u = (_f64(a) for a in (pos_c, pos_e, radial_c, u))
+    vc, vt = np.empty((3, grid.n_cells)), np.empty(grid.n_edges)
+    lib().or_op_perot(h.ref, _p(pos_c), _p(pos_e), _p(radial_c), _p(u), _p(vc), _p(vt))
+    return vc, vt
+
+
+def thomas(a, b, c, r):
+    a, b, c, r = (_f64(x) for x in (a, b, c, r))
+    x = np.empty_like(r)
+    rc = lib().or_thomas(int(r.size), _p(a), _p(b), _p(c), _p(r), _p(x))
+    if rc != 0:
+        raise RuntimeError("or_thomas failed")
+    return x
+
+
+def column(params, dt, zh, pi_ref, theta_ref, pi_n, rho_n, thv_n, rho_i, thv_i, w_n, tw, wcc,
+           div_rho, div_th):
+    N = len(pi_ref)
+    ins = [_f64(a) for a in (zh, pi_ref, theta_ref, pi_n, rho_n, thv_n, rho_i, thv_i, w_n, tw, wcc,
+                             div_rho, div_th)]
+    w, rho, pi, thv, fl = np.empty(N + 1), np.empty(N), np.empty(N), np.empty(N), np.empty(N + 1)
+    pp = params_struct(params)
+    rc = lib().or_column(N, float(dt), C.byref(pp), *[_p(a) for a in ins], _p(w), _p(rho), _p(pi),
+                         _p(thv), _p(fl))
+    if rc != 0:
+        raise RuntimeError("or_column failed")
+    return dict(w=w, rho=rho, pi=pi, theta_v=thv, vflux=fl)

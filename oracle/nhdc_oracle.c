@@ -1,0 +1,695 @@
+/*
+ * nhdc_oracle.c -- plain FP64 CPU oracle of the dynamical-core substep.
+ * TEST INFRASTRUCTURE ONLY (see nhdc_oracle.h for what it computes and who
+ * may call it).  Plain loops, one formula per statement, sums in slot order,
+ * no fused multiply-add (built with -ffp-contract=off), OpenMP over entities.
+ *
+ * Index conventions: full level k = 0..N-1 top to bottom; half level i =
+ * 0..N, half level i is the top interface of full level i, i = N the ground.
+ */
+#include "nhdc_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+struct or_model {
+    or_grid g;
+    or_params p;
+    int N;
+    /* metrics */
+    double *zh, *pi_ref, *theta_ref; /* [N+1][nc], [N][nc] x2 */
+    double *z, *dz;                  /* [N][nc] */
+    double *dzh, *gw, *dref;         /* [N+1][nc], interior half levels only */
+    double *dz_e;                    /* [N][ne] */
+    double *gw_e;                    /* [N+1][ne] */
+    double *sn;                      /* [N][ne] slope of full levels */
+    double *snh, *sth;               /* [N+1][ne] normal / tangential slope of half levels */
+    double *fe;                      /* [ne] Coriolis parameter */
+    /* state */
+    double *vn, *w, *rho, *pi, *thv, *pi_prev;
+    double *facc, *wacc;
+    /* work */
+    double *vt, *vnh, *vth, *kc, *zv, *omega, *wv, *pcx, *pcy, *pcz, *ke, *ae;
+    double *tvn0, *tw0, *wcc0, *tvn1, *tw1, *wcc1;
+    double *gp, *dpz, *pix, *the, *rhoe, *flx, *hfl, *divr, *divt, *vns, *dvs;
+    double *ws, *rhos, *pis, *thvs, *vnn, *vflux, *rho_i, *thv_i, *twm;
+};
+
+#define AT(a, k, n, i) ((a)[(int64_t)(k) * (n) + (i)])
+
+static double *alloc(int64_t n) { return (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double)); }
+
+/* ------------------------------------------------------------------------ */
+/* single-level operators                                                    */
+/* ------------------------------------------------------------------------ */
+
+void or_op_div(const or_grid *g, const double *f, double *out) {
+    const int64_t nc = g->nc;
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < nc; ++c) {
+        double s = 0.0;
+        for (int j = 0; j < 3; ++j) {
+            int64_t e = g->cell_edges[j * nc + c];
+            s += g->cell_sign[j * nc + c] * g->edge_length[e] * f[e];
+        }
+        out[c] = s / g->cell_area[c];
+    }
+}
+
+void or_op_grad(const or_grid *g, const double *p, double *out) {
+    const int64_t ne = g->ne;
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < ne; ++e)
+        out[e] = (p[g->edge_cells[ne + e]] - p[g->edge_cells[e]]) / g->dual_length[e];
+}
+
+void or_op_tgrad(const or_grid *g, const double *q, double *out) {
+    const int64_t ne = g->ne;
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < ne; ++e)
+        out[e] = (q[g->edge_verts[ne + e]] - q[g->edge_verts[e]]) / g->edge_length[e];
+}
+
+void or_op_curl(const or_grid *g, const double *u, double *out) {
+    const int64_t nv = g->nv;
+#pragma omp parallel for schedule(static)
+    for (int64_t v = 0; v < nv; ++v) {
+        double s = 0.0;
+        for (int j = 0; j < g->vert_valence[v]; ++j) {
+            int64_t e = g->vert_edges[j * nv + v];
+            s += g->vert_sign[j * nv + v] * g->dual_length[e] * u[e];
+        }
+        out[v] = s / g->vert_area[v];
+    }
+}
+
+void or_op_cell_avg(const or_grid *g, const double *q, double *out) {
+    const int64_t nc = g->nc;
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < nc; ++c) {
+        double s = 0.0;
+        for (int j = 0; j < 3; ++j) s += q[g->cell_edges[j * nc + c]];
+        out[c] = s / 3.0;
+    }
+}
+
+void or_op_vert_avg(const or_grid *g, const double *p, double *out) {
+    const int64_t nv = g->nv;
+#pragma omp parallel for schedule(static)
+    for (int64_t v = 0; v < nv; ++v) {
+        double s = 0.0;
+        for (int j = 0; j < g->vert_valence[v]; ++j) s += p[g->vert_cells[j * nv + v]];
+        out[v] = s / g->vert_valence[v];
+    }
+}
+
+void or_op_perot(const or_grid *g, const double *pc, const double *pe, const double *rc,
+                 const double *u, double *vc, double *vt) {
+    const int64_t nc = g->nc, ne = g->ne;
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < nc; ++c) {
+        double v[3] = {0.0, 0.0, 0.0};
+        for (int j = 0; j < 3; ++j) {
+            int64_t e = g->cell_edges[j * nc + c];
+            double wgt = g->cell_sign[j * nc + c] * g->edge_length[e] * u[e];
+            for (int d = 0; d < 3; ++d) v[d] += wgt * (pe[d * ne + e] - pc[d * nc + c]);
+        }
+        for (int d = 0; d < 3; ++d) v[d] = v[d] / g->cell_area[c];
+        double r = v[0] * rc[c] + v[1] * rc[nc + c] + v[2] * rc[2 * nc + c];
+        for (int d = 0; d < 3; ++d) vc[d * nc + c] = v[d] - r * rc[d * nc + c];
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < ne; ++e) {
+        int64_t c1 = g->edge_cells[e], c2 = g->edge_cells[ne + e];
+        double s = 0.0;
+        for (int d = 0; d < 3; ++d)
+            s += 0.5 * (vc[d * nc + c1] + vc[d * nc + c2]) * g->edge_tangent[d * ne + e];
+        vt[e] = s;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* model set-up: metrics derived from the half-level heights                  */
+/* ------------------------------------------------------------------------ */
+
+or_model *or_create(const or_grid *g, int N, const double *zh, const double *pi_ref,
+                    const double *theta_ref, const or_params *p) {
+    if (!g || !zh || !pi_ref || !theta_ref || !p || N < 2 || N > OR_MAX_LEV) return NULL;
+    or_model *m = (or_model *)calloc(1, sizeof(or_model));
+    if (!m) return NULL;
+    m->g = *g;
+    m->p = *p;
+    m->N = N;
+    const int64_t nc = g->nc, ne = g->ne, nv = g->nv;
+    const int64_t NC = (int64_t)N * nc, NC1 = (int64_t)(N + 1) * nc;
+    const int64_t NE = (int64_t)N * ne, NE1 = (int64_t)(N + 1) * ne;
+    const int64_t NV = (int64_t)N * nv, NV1 = (int64_t)(N + 1) * nv;
+    double **cells[] = {&m->pi_ref, &m->theta_ref, &m->z, &m->dz, &m->rho, &m->pi, &m->thv,
+                        &m->pi_prev, &m->kc, &m->dpz, &m->pix, &m->divr, &m->divt, &m->dvs,
+                        &m->rhos, &m->pis, &m->thvs, &m->rho_i, &m->thv_i, &m->pcx, &m->pcy,
+                        &m->pcz};
+    double **cells1[] = {&m->zh, &m->dzh, &m->gw, &m->dref, &m->w, &m->wacc, &m->omega,
+                         &m->tw0, &m->wcc0, &m->tw1, &m->wcc1, &m->ws, &m->vflux, &m->twm};
+    double **edges[] = {&m->dz_e, &m->sn, &m->vn, &m->facc, &m->vt, &m->ke, &m->tvn0, &m->tvn1,
+                        &m->gp, &m->the, &m->rhoe, &m->flx, &m->hfl, &m->vns, &m->vnn};
+    double **edges1[] = {&m->gw_e, &m->snh, &m->sth, &m->vnh, &m->vth, &m->ae};
+    int ok = 1;
+    for (size_t i = 0; i < sizeof(cells) / sizeof(*cells); ++i) ok &= (*cells[i] = alloc(NC)) != NULL;
+    for (size_t i = 0; i < sizeof(cells1) / sizeof(*cells1); ++i) ok &= (*cells1[i] = alloc(NC1)) != NULL;
+    for (size_t i = 0; i < sizeof(edges) / sizeof(*edges); ++i) ok &= (*edges[i] = alloc(NE)) != NULL;
+    for (size_t i = 0; i < sizeof(edges1) / sizeof(*edges1); ++i) ok &= (*edges1[i] = alloc(NE1)) != NULL;
+    ok &= (m->zv = alloc(NV)) != NULL;
+    ok &= (m->wv = alloc(NV1)) != NULL;
+    ok &= (m->fe = alloc(ne)) != NULL;
+    if (!ok) {
+        or_free(m);
+        return NULL;
+    }
+    memcpy(m->zh, zh, sizeof(double) * NC1);
+    memcpy(m->pi_ref, pi_ref, sizeof(double) * NC);
+    memcpy(m->theta_ref, theta_ref, sizeof(double) * NC);
+
+    /* cell metrics */
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < nc; ++c) {
+        for (int k = 0; k < N; ++k) {
+            AT(m->z, k, nc, c) = 0.5 * (AT(m->zh, k, nc, c) + AT(m->zh, k + 1, nc, c));
+            AT(m->dz, k, nc, c) = AT(m->zh, k, nc, c) - AT(m->zh, k + 1, nc, c);
+        }
+        for (int i = 1; i < N; ++i) {
+            double za = AT(m->z, i - 1, nc, c), zb = AT(m->z, i, nc, c);
+            AT(m->dzh, i, nc, c) = za - zb;
+            AT(m->gw, i, nc, c) = (za - AT(m->zh, i, nc, c)) / (za - zb);
+            double g = AT(m->gw, i, nc, c);
+            double threfh = g * AT(m->theta_ref, i, nc, c) + (1.0 - g) * AT(m->theta_ref, i - 1, nc, c);
+            AT(m->dref, i, nc, c) = -p->grav / (p->cpd * threfh);
+        }
+    }
+    /* vertex-averaged half-level heights (temporary, in wv) */
+    for (int i = 0; i <= N; ++i) or_op_vert_avg(g, m->zh + (int64_t)i * nc, m->wv + (int64_t)i * nv);
+    /* edge metrics */
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < ne; ++e) {
+        int64_t c1 = g->edge_cells[e], c2 = g->edge_cells[ne + e];
+        int64_t v1 = g->edge_verts[e], v2 = g->edge_verts[ne + e];
+        for (int k = 0; k < N; ++k) {
+            AT(m->dz_e, k, ne, e) = 0.5 * (AT(m->dz, k, nc, c1) + AT(m->dz, k, nc, c2));
+            AT(m->sn, k, ne, e) = (AT(m->z, k, nc, c2) - AT(m->z, k, nc, c1)) / g->dual_length[e];
+        }
+        for (int i = 0; i <= N; ++i) {
+            if (i > 0 && i < N) AT(m->gw_e, i, ne, e) = 0.5 * (AT(m->gw, i, nc, c1) + AT(m->gw, i, nc, c2));
+            AT(m->snh, i, ne, e) = (AT(m->zh, i, nc, c2) - AT(m->zh, i, nc, c1)) / g->dual_length[e];
+            AT(m->sth, i, ne, e) = (AT(m->wv, i, nv, v2) - AT(m->wv, i, nv, v1)) / g->edge_length[e];
+        }
+        m->fe[e] = 2.0 * p->omega * g->edge_x[2 * ne + e];
+    }
+    memset(m->wv, 0, sizeof(double) * NV1);
+    return m;
+}
+
+void or_free(or_model *m) {
+    if (!m) return;
+    double *all[] = {m->zh, m->pi_ref, m->theta_ref, m->z, m->dz, m->dzh, m->gw, m->dref,
+                     m->dz_e, m->gw_e, m->sn, m->snh, m->sth, m->fe, m->vn, m->w, m->rho, m->pi,
+                     m->thv, m->pi_prev, m->facc, m->wacc, m->vt, m->vnh, m->vth, m->kc, m->zv,
+                     m->omega, m->wv, m->pcx, m->pcy, m->pcz, m->ke, m->ae, m->tvn0, m->tw0,
+                     m->wcc0, m->tvn1, m->tw1, m->wcc1, m->gp, m->dpz, m->pix, m->the, m->rhoe,
+                     m->flx, m->hfl, m->divr, m->divt, m->vns, m->dvs, m->ws, m->rhos, m->pis,
+                     m->thvs, m->vnn, m->vflux, m->rho_i, m->thv_i, m->twm};
+    for (size_t i = 0; i < sizeof(all) / sizeof(*all); ++i) free(all[i]);
+    free(m);
+}
+
+int or_set_state(or_model *m, const double *vn, const double *w, const double *rho,
+                 const double *pi, const double *thv, const double *pi_prev) {
+    if (!m || !vn || !w || !rho || !pi || !thv) return -1;
+    const int64_t nc = m->g.nc, ne = m->g.ne, N = m->N;
+    memcpy(m->vn, vn, sizeof(double) * N * ne);
+    memcpy(m->w, w, sizeof(double) * (N + 1) * nc);
+    memcpy(m->rho, rho, sizeof(double) * N * nc);
+    memcpy(m->pi, pi, sizeof(double) * N * nc);
+    memcpy(m->thv, thv, sizeof(double) * N * nc);
+    if (pi_prev) memcpy(m->pi_prev, pi_prev, sizeof(double) * N * nc);
+    else
+        for (int64_t i = 0; i < N * nc; ++i) m->pi_prev[i] = m->pi[i] - m->pi_ref[i];
+    memset(m->facc, 0, sizeof(double) * N * ne);
+    memset(m->wacc, 0, sizeof(double) * (N + 1) * nc);
+    return 0;
+}
+
+int or_get_state(const or_model *m, double *vn, double *w, double *rho, double *pi, double *thv,
+                 double *pi_prev) {
+    if (!m) return -1;
+    const int64_t nc = m->g.nc, ne = m->g.ne, N = m->N;
+    if (vn) memcpy(vn, m->vn, sizeof(double) * N * ne);
+    if (w) memcpy(w, m->w, sizeof(double) * (N + 1) * nc);
+    if (rho) memcpy(rho, m->rho, sizeof(double) * N * nc);
+    if (pi) memcpy(pi, m->pi, sizeof(double) * N * nc);
+    if (thv) memcpy(thv, m->thv, sizeof(double) * N * nc);
+    if (pi_prev) memcpy(pi_prev, m->pi_prev, sizeof(double) * N * nc);
+    return 0;
+}
+
+int or_get_flux(const or_model *m, double *facc, double *wacc) {
+    if (!m) return -1;
+    const int64_t nc = m->g.nc, ne = m->g.ne, N = m->N;
+    if (facc) memcpy(facc, m->facc, sizeof(double) * N * ne);
+    if (wacc) memcpy(wacc, m->wacc, sizeof(double) * (N + 1) * nc);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* velocity tendencies                                                       */
+/* ------------------------------------------------------------------------ */
+
+static void vt_phase(or_model *m, const double *vn, const double *w, double *tvn, double *tw,
+                     double *wcc) {
+    const or_grid *g = &m->g;
+    const int64_t nc = g->nc, ne = g->ne, nv = g->nv;
+    const int N = m->N;
+    const double a = g->radius;
+
+    /* 1. tangential velocity from the Perot reconstruction, level by level */
+    for (int k = 0; k < N; ++k) {
+        const double *u = vn + (int64_t)k * ne;
+#pragma omp parallel for schedule(static)
+        for (int64_t c = 0; c < nc; ++c) {
+            double v[3] = {0.0, 0.0, 0.0};
+            const double xc[3] = {g->cell_x[c], g->cell_x[nc + c], g->cell_x[2 * nc + c]};
+            for (int j = 0; j < 3; ++j) {
+                int64_t e = g->cell_edges[j * nc + c];
+                double wgt = g->cell_sign[j * nc + c] * g->edge_length[e] * u[e];
+                for (int d = 0; d < 3; ++d) v[d] += wgt * (a * (g->edge_x[d * ne + e] - xc[d]));
+            }
+            for (int d = 0; d < 3; ++d) v[d] = v[d] / g->cell_area[c];
+            double r = v[0] * xc[0] + v[1] * xc[1] + v[2] * xc[2];
+            AT(m->pcx, k, nc, c) = v[0] - r * xc[0];
+            AT(m->pcy, k, nc, c) = v[1] - r * xc[1];
+            AT(m->pcz, k, nc, c) = v[2] - r * xc[2];
+        }
+#pragma omp parallel for schedule(static)
+        for (int64_t e = 0; e < ne; ++e) {
+            int64_t c1 = g->edge_cells[e], c2 = g->edge_cells[ne + e];
+            double vx = 0.5 * (AT(m->pcx, k, nc, c1) + AT(m->pcx, k, nc, c2));
+            double vy = 0.5 * (AT(m->pcy, k, nc, c1) + AT(m->pcy, k, nc, c2));
+            double vz = 0.5 * (AT(m->pcz, k, nc, c1) + AT(m->pcz, k, nc, c2));
+            AT(m->vt, k, ne, e) = vx * g->edge_tangent[e] + vy * g->edge_tangent[ne + e] +
+                                  vz * g->edge_tangent[2 * ne + e];
+        }
+    }
+    /* 2. vn and vt at half levels; kinetic energy at edges */
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < ne; ++e) {
+        for (int i = 0; i <= N; ++i) {
+            double hn, ht;
+            if (i == 0) {
+                hn = AT(vn, 0, ne, e);
+                ht = AT(m->vt, 0, ne, e);
+            } else if (i == N) {
+                hn = AT(vn, N - 1, ne, e);
+                ht = AT(m->vt, N - 1, ne, e);
+            } else {
+                double gg = AT(m->gw_e, i, ne, e);
+                hn = gg * AT(vn, i, ne, e) + (1.0 - gg) * AT(vn, i - 1, ne, e);
+                ht = gg * AT(m->vt, i, ne, e) + (1.0 - gg) * AT(m->vt, i - 1, ne, e);
+            }
+            AT(m->vnh, i, ne, e) = hn;
+            AT(m->vth, i, ne, e) = ht;
+        }
+        for (int k = 0; k < N; ++k) {
+            double un = AT(vn, k, ne, e), ut = AT(m->vt, k, ne, e);
+            AT(m->ke, k, ne, e) = 0.5 * (un * un + ut * ut);
+        }
+    }
+    /* 3. kinetic energy at cells; 4. vorticity at vertices */
+    for (int k = 0; k < N; ++k) {
+        or_op_cell_avg(g, m->ke + (int64_t)k * ne, m->kc + (int64_t)k * nc);
+        or_op_curl(g, vn + (int64_t)k * ne, m->zv + (int64_t)k * nv);
+    }
+    /* 5. contravariant correction at half levels 1..N (cell average of edge values) */
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < ne; ++e)
+        for (int i = 1; i <= N; ++i)
+            AT(m->ae, i, ne, e) = AT(m->vnh, i, ne, e) * AT(m->snh, i, ne, e) +
+                                  AT(m->vth, i, ne, e) * AT(m->sth, i, ne, e);
+    for (int64_t c = 0; c < nc; ++c) wcc[c] = 0.0;
+    for (int i = 1; i <= N; ++i) or_op_cell_avg(g, m->ae + (int64_t)i * ne, wcc + (int64_t)i * nc);
+    /* 6. contravariant vertical velocity, zero at top and ground */
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < nc; ++c) {
+        AT(m->omega, 0, nc, c) = 0.0;
+        AT(m->omega, N, nc, c) = 0.0;
+        for (int i = 1; i < N; ++i) AT(m->omega, i, nc, c) = AT(w, i, nc, c) - AT(wcc, i, nc, c);
+    }
+    /* 7. normal-velocity tendency */
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < ne; ++e) {
+        int64_t c1 = g->edge_cells[e], c2 = g->edge_cells[ne + e];
+        int64_t v1 = g->edge_verts[e], v2 = g->edge_verts[ne + e];
+        for (int k = 0; k < N; ++k) {
+            double gradk = (AT(m->kc, k, nc, c2) - AT(m->kc, k, nc, c1)) / g->dual_length[e];
+            double zeta_e = 0.5 * (AT(m->zv, k, nv, v1) + AT(m->zv, k, nv, v2));
+            double of1 = 0.5 * (AT(m->omega, k, nc, c1) + AT(m->omega, k + 1, nc, c1));
+            double of2 = 0.5 * (AT(m->omega, k, nc, c2) + AT(m->omega, k + 1, nc, c2));
+            double obar = 0.5 * (of1 + of2);
+            double dvdz = (AT(m->vnh, k, ne, e) - AT(m->vnh, k + 1, ne, e)) / AT(m->dz_e, k, ne, e);
+            AT(tvn, k, ne, e) = -gradk + (zeta_e + m->fe[e]) * AT(m->vt, k, ne, e) - obar * dvdz;
+        }
+    }
+    /* 8. w tendency at interior half levels */
+    for (int i = 1; i < N; ++i) or_op_vert_avg(g, w + (int64_t)i * nc, m->wv + (int64_t)i * nv);
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < ne; ++e) {
+        int64_t c1 = g->edge_cells[e], c2 = g->edge_cells[ne + e];
+        int64_t v1 = g->edge_verts[e], v2 = g->edge_verts[ne + e];
+        for (int i = 1; i < N; ++i) {
+            double gw_ = (AT(w, i, nc, c2) - AT(w, i, nc, c1)) / g->dual_length[e];
+            double tw_ = (AT(m->wv, i, nv, v2) - AT(m->wv, i, nv, v1)) / g->edge_length[e];
+            AT(m->ae, i, ne, e) = AT(m->vnh, i, ne, e) * gw_ + AT(m->vth, i, ne, e) * tw_;
+        }
+    }
+    for (int i = 1; i < N; ++i) or_op_cell_avg(g, m->ae + (int64_t)i * ne, tw + (int64_t)i * nc);
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < nc; ++c) {
+        AT(tw, 0, nc, c) = 0.0;
+        AT(tw, N, nc, c) = 0.0;
+        for (int i = 1; i < N; ++i) {
+            double hadv = AT(tw, i, nc, c);
+            double dwdz = (AT(w, i - 1, nc, c) - AT(w, i + 1, nc, c)) /
+                          (AT(m->zh, i - 1, nc, c) - AT(m->zh, i + 1, nc, c));
+            AT(tw, i, nc, c) = -hadv - AT(m->omega, i, nc, c) * dwdz;
+        }
+    }
+}
+
+int or_vt(or_model *m, const double *vn, const double *w, double *tvn, double *tw, double *wcc,
+          double *vt_out) {
+    if (!m || !vn || !w || !tvn || !tw || !wcc) return -1;
+    vt_phase(m, vn, w, tvn, tw, wcc);
+    if (vt_out) memcpy(vt_out, m->vt, sizeof(double) * m->N * m->g.ne);
+    return 0;
+}
+
+/* terrain-corrected normal gradient of a full-level cell field */
+static void pgrad(or_model *m, const double *px, double *gp) {
+    const or_grid *g = &m->g;
+    const int64_t nc = g->nc, ne = g->ne;
+    const int N = m->N;
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < nc; ++c)
+        for (int k = 0; k < N; ++k) {
+            int ka = k == 0 ? 0 : k - 1, kb = k == N - 1 ? N - 1 : k + 1;
+            AT(m->dpz, k, nc, c) = (AT(px, ka, nc, c) - AT(px, kb, nc, c)) /
+                                   (AT(m->z, ka, nc, c) - AT(m->z, kb, nc, c));
+        }
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < ne; ++e) {
+        int64_t c1 = g->edge_cells[e], c2 = g->edge_cells[ne + e];
+        for (int k = 0; k < N; ++k) {
+            double gl = (AT(px, k, nc, c2) - AT(px, k, nc, c1)) / g->dual_length[e];
+            double dz2 = 0.5 * (AT(m->dpz, k, nc, c1) + AT(m->dpz, k, nc, c2));
+            AT(gp, k, ne, e) = gl - AT(m->sn, k, ne, e) * dz2;
+        }
+    }
+}
+
+int or_pgrad(or_model *m, const double *p, double *gp) {
+    if (!m || !p || !gp) return -1;
+    pgrad(m, p, gp);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* column solve                                                              */
+/* ------------------------------------------------------------------------ */
+
+int or_thomas(int n, const double *a, const double *b, const double *c, const double *r,
+              double *x) {
+    if (n < 1 || n > OR_MAX_LEV + 1) return -1;
+    double cp[OR_MAX_LEV + 1], dp[OR_MAX_LEV + 1];
+    cp[0] = c[0] / b[0];
+    dp[0] = r[0] / b[0];
+    for (int i = 1; i < n; ++i) {
+        double den = b[i] - a[i] * cp[i - 1];
+        cp[i] = c[i] / den;
+        dp[i] = (r[i] - a[i] * dp[i - 1]) / den;
+    }
+    x[n - 1] = dp[n - 1];
+    for (int i = n - 2; i >= 0; --i) x[i] = dp[i] - cp[i] * x[i + 1];
+    return 0;
+}
+
+int or_column(int N, double dt, const or_params *p, const double *zh, const double *pi_ref,
+              const double *theta_ref, const double *pi_n, const double *rho_n,
+              const double *thv_n, const double *rho_i, const double *thv_i, const double *w_n,
+              const double *tw, const double *wcc, const double *div_rho, const double *div_th,
+              double *w_out, double *rho_out, double *pi_out, double *thv_out, double *vflux) {
+    if (N < 2 || N > OR_MAX_LEV) return -1;
+    const double beta = p->beta, cpd = p->cpd, rd = p->rd, cvd = p->cpd - p->rd;
+    double z[OR_MAX_LEV], dz[OR_MAX_LEV], ppn[OR_MAX_LEV], B[OR_MAX_LEV], Rh[OR_MAX_LEV],
+        Ph[OR_MAX_LEV];
+    double dzh[OR_MAX_LEV + 1], gw[OR_MAX_LEV + 1], dref[OR_MAX_LEV + 1], rhoh[OR_MAX_LEV + 1],
+        thh[OR_MAX_LEV + 1], thph[OR_MAX_LEV + 1], What[OR_MAX_LEV + 1], Fx[OR_MAX_LEV + 1],
+        Hx[OR_MAX_LEV + 1], al[OR_MAX_LEV + 1], ga[OR_MAX_LEV + 1], ta[OR_MAX_LEV + 1],
+        tb[OR_MAX_LEV + 1], tc[OR_MAX_LEV + 1], tr[OR_MAX_LEV + 1], wp[OR_MAX_LEV + 1];
+    for (int k = 0; k < N; ++k) {
+        z[k] = 0.5 * (zh[k] + zh[k + 1]);
+        dz[k] = zh[k] - zh[k + 1];
+        ppn[k] = pi_n[k] - pi_ref[k];
+    }
+    for (int i = 1; i < N; ++i) {
+        dzh[i] = z[i - 1] - z[i];
+        gw[i] = (z[i - 1] - zh[i]) / (z[i - 1] - z[i]);
+        double threfh = gw[i] * theta_ref[i] + (1.0 - gw[i]) * theta_ref[i - 1];
+        dref[i] = -p->grav / (cpd * threfh);
+        rhoh[i] = gw[i] * rho_i[i] + (1.0 - gw[i]) * rho_i[i - 1];
+        thh[i] = gw[i] * thv_i[i] + (1.0 - gw[i]) * thv_i[i - 1];
+        thph[i] = gw[i] * (thv_i[i] - theta_ref[i]) + (1.0 - gw[i]) * (thv_i[i - 1] - theta_ref[i - 1]);
+    }
+    /* explicit parts at interior half levels; rigid lid and zero ground flux */
+    Fx[0] = Fx[N] = Hx[0] = Hx[N] = al[0] = al[N] = 0.0;
+    for (int i = 1; i < N; ++i) {
+        double pterm = (1.0 - beta) * thh[i] * (ppn[i - 1] - ppn[i]) / dzh[i] + thph[i] * dref[i];
+        What[i] = w_n[i] + dt * (tw[i] - cpd * pterm);
+        Fx[i] = rhoh[i] * ((1.0 - beta) * w_n[i] - wcc[i]);
+        Hx[i] = thh[i] * Fx[i];
+        al[i] = beta * rhoh[i] * thh[i];
+        ga[i] = dt * cpd * beta * thh[i] / dzh[i];
+    }
+    for (int k = 0; k < N; ++k) {
+        Rh[k] = rho_n[k] - dt * (div_rho[k] + (Fx[k] - Fx[k + 1]) / dz[k]);
+        B[k] = dt * (rd / cvd) * pi_n[k] / (rho_n[k] * thv_n[k] * dz[k]);
+        Ph[k] = ppn[k] - B[k] * dz[k] * (div_th[k] + (Hx[k] - Hx[k + 1]) / dz[k]);
+    }
+    /* tridiagonal system in w on half levels 1..N-1 */
+    for (int i = 1; i < N; ++i) {
+        ta[i - 1] = -ga[i] * B[i - 1] * al[i - 1];
+        tb[i - 1] = 1.0 + ga[i] * al[i] * (B[i - 1] + B[i]);
+        tc[i - 1] = -ga[i] * B[i] * al[i + 1];
+        tr[i - 1] = What[i] - ga[i] * (Ph[i - 1] - Ph[i]);
+    }
+    or_thomas(N - 1, ta, tb, tc, tr, wp + 1);
+    wp[0] = 0.0;
+    wp[N] = wcc[N];
+    for (int i = 0; i <= N; ++i) w_out[i] = wp[i];
+    /* implicit vertical mass flux: zero at the lid and the ground */
+    double fl[OR_MAX_LEV + 1];
+    fl[0] = fl[N] = 0.0;
+    for (int i = 1; i < N; ++i) fl[i] = rhoh[i] * wp[i];
+    for (int k = 0; k < N; ++k) {
+        double rnew = Rh[k] - dt * beta * (fl[k] - fl[k + 1]) / dz[k];
+        double ppnew = Ph[k] - B[k] * (al[k] * wp[k] - al[k + 1] * wp[k + 1]);
+        double rt = rho_n[k] * thv_n[k];
+        rho_out[k] = rnew;
+        pi_out[k] = pi_ref[k] + ppnew;
+        thv_out[k] = (rt + (cvd / rd) * (rt / pi_n[k]) * (ppnew - ppn[k])) / rnew;
+    }
+    if (vflux) {
+        vflux[0] = vflux[N] = 0.0;
+        for (int i = 1; i < N; ++i)
+            vflux[i] = rhoh[i] * (beta * wp[i] + (1.0 - beta) * w_n[i] - wcc[i]);
+    }
+    return 0;
+}
+
+/* run or_column on every column of the model (gathers each column contiguously) */
+static void column_phase(or_model *m, double dt, const double *rho_i, const double *thv_i,
+                         const double *tw, const double *wcc, double *w_o, double *rho_o,
+                         double *pi_o, double *thv_o, double *vflux) {
+    const int64_t nc = m->g.nc;
+    const int N = m->N;
+#pragma omp parallel
+    {
+        double c_zh[OR_MAX_LEV + 1], c_pr[OR_MAX_LEV], c_tr[OR_MAX_LEV], c_pi[OR_MAX_LEV],
+            c_rho[OR_MAX_LEV], c_thv[OR_MAX_LEV], c_ri[OR_MAX_LEV], c_ti[OR_MAX_LEV],
+            c_w[OR_MAX_LEV + 1], c_tw[OR_MAX_LEV + 1], c_wcc[OR_MAX_LEV + 1], c_dr[OR_MAX_LEV],
+            c_dt[OR_MAX_LEV], o_w[OR_MAX_LEV + 1], o_rho[OR_MAX_LEV], o_pi[OR_MAX_LEV],
+            o_thv[OR_MAX_LEV], o_fl[OR_MAX_LEV + 1];
+#pragma omp for schedule(static)
+        for (int64_t c = 0; c < nc; ++c) {
+            for (int i = 0; i <= N; ++i) {
+                c_zh[i] = AT(m->zh, i, nc, c);
+                c_w[i] = AT(m->w, i, nc, c);
+                c_tw[i] = AT(tw, i, nc, c);
+                c_wcc[i] = AT(wcc, i, nc, c);
+            }
+            for (int k = 0; k < N; ++k) {
+                c_pr[k] = AT(m->pi_ref, k, nc, c);
+                c_tr[k] = AT(m->theta_ref, k, nc, c);
+                c_pi[k] = AT(m->pi, k, nc, c);
+                c_rho[k] = AT(m->rho, k, nc, c);
+                c_thv[k] = AT(m->thv, k, nc, c);
+                c_ri[k] = AT(rho_i, k, nc, c);
+                c_ti[k] = AT(thv_i, k, nc, c);
+                c_dr[k] = AT(m->divr, k, nc, c);
+                c_dt[k] = AT(m->divt, k, nc, c);
+            }
+            or_column(N, dt, &m->p, c_zh, c_pr, c_tr, c_pi, c_rho, c_thv, c_ri, c_ti, c_w, c_tw,
+                      c_wcc, c_dr, c_dt, o_w, o_rho, o_pi, o_thv, o_fl);
+            for (int i = 0; i <= N; ++i) {
+                AT(w_o, i, nc, c) = o_w[i];
+                if (vflux) AT(vflux, i, nc, c) = o_fl[i];
+            }
+            for (int k = 0; k < N; ++k) {
+                AT(rho_o, k, nc, c) = o_rho[k];
+                AT(pi_o, k, nc, c) = o_pi[k];
+                AT(thv_o, k, nc, c) = o_thv[k];
+            }
+        }
+    }
+}
+
+/* edge fluxes of mass and rho*theta_v and their cell divergences per unit height */
+static void flux_phase(or_model *m, const double *vnx) {
+    const or_grid *g = &m->g;
+    const int64_t nc = g->nc, ne = g->ne;
+    const int N = m->N;
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < ne; ++e)
+        for (int k = 0; k < N; ++k) {
+            double f = AT(m->rhoe, k, ne, e) * AT(vnx, k, ne, e) * AT(m->dz_e, k, ne, e);
+            AT(m->flx, k, ne, e) = f;
+            AT(m->hfl, k, ne, e) = AT(m->the, k, ne, e) * f;
+        }
+    for (int k = 0; k < N; ++k) {
+        or_op_div(g, m->flx + (int64_t)k * ne, m->divr + (int64_t)k * nc);
+        or_op_div(g, m->hfl + (int64_t)k * ne, m->divt + (int64_t)k * nc);
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < nc; ++c)
+        for (int k = 0; k < N; ++k) {
+            AT(m->divr, k, nc, c) = AT(m->divr, k, nc, c) / AT(m->dz, k, nc, c);
+            AT(m->divt, k, nc, c) = AT(m->divt, k, nc, c) / AT(m->dz, k, nc, c);
+        }
+}
+
+/* ------------------------------------------------------------------------ */
+/* one substep                                                               */
+/* ------------------------------------------------------------------------ */
+
+static void substep(or_model *m, double dt, int nsub) {
+    const or_grid *g = &m->g;
+    const or_params *p = &m->p;
+    const int64_t nc = g->nc, ne = g->ne;
+    const int N = m->N;
+    const int64_t NC = (int64_t)N * nc, NE = (int64_t)N * ne, NC1 = (int64_t)(N + 1) * nc;
+    const double cv = p->wgt_corr, eps = p->extrap;
+
+    /* predictor: tendencies of state n */
+    vt_phase(m, m->vn, m->w, m->tvn0, m->tw0, m->wcc0);
+    /* extrapolated Exner perturbation and its terrain-corrected gradient */
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < NC; ++i) {
+        double pp = m->pi[i] - m->pi_ref[i];
+        m->pix[i] = (1.0 + eps) * pp - eps * m->pi_prev[i];
+    }
+    pgrad(m, m->pix, m->gp);
+    /* edge values of state n, predicted normal velocity */
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < ne; ++e) {
+        int64_t c1 = g->edge_cells[e], c2 = g->edge_cells[ne + e];
+        for (int k = 0; k < N; ++k) {
+            AT(m->the, k, ne, e) = 0.5 * (AT(m->thv, k, nc, c1) + AT(m->thv, k, nc, c2));
+            AT(m->rhoe, k, ne, e) = 0.5 * (AT(m->rho, k, nc, c1) + AT(m->rho, k, nc, c2));
+            AT(m->vns, k, ne, e) = AT(m->vn, k, ne, e) +
+                                   dt * (AT(m->tvn0, k, ne, e) -
+                                         p->cpd * AT(m->the, k, ne, e) * AT(m->gp, k, ne, e));
+        }
+    }
+    flux_phase(m, m->vns);
+    column_phase(m, dt, m->rho, m->thv, m->tw0, m->wcc0, m->ws, m->rhos, m->pis, m->thvs, NULL);
+
+    /* corrector: tendencies of the predicted state */
+    vt_phase(m, m->vns, m->ws, m->tvn1, m->tw1, m->wcc1);
+    /* divergence of vn* for the damping term */
+    for (int k = 0; k < N; ++k) or_op_div(g, m->vns + (int64_t)k * ne, m->dvs + (int64_t)k * nc);
+    const double abar = 4.0 * 3.14159265358979323846 * g->radius * g->radius / (double)nc;
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < ne; ++e) {
+        int64_t c1 = g->edge_cells[e], c2 = g->edge_cells[ne + e];
+        for (int k = 0; k < N; ++k) {
+            double the_s = 0.5 * (AT(m->thvs, k, nc, c1) + AT(m->thvs, k, nc, c2));
+            double tend = (1.0 - cv) * AT(m->tvn0, k, ne, e) + cv * AT(m->tvn1, k, ne, e) -
+                          p->cpd * the_s * AT(m->gp, k, ne, e);
+            double gdiv = (AT(m->dvs, k, nc, c2) - AT(m->dvs, k, nc, c1)) / g->dual_length[e];
+            AT(m->vnn, k, ne, e) = AT(m->vn, k, ne, e) + dt * tend + p->div_damp * abar * gdiv;
+        }
+    }
+    flux_phase(m, m->vnn);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < NC; ++i) {
+        m->rho_i[i] = 0.5 * (m->rho[i] + m->rhos[i]);
+        m->thv_i[i] = 0.5 * (m->thv[i] + m->thvs[i]);
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < NC1; ++i) m->twm[i] = (1.0 - cv) * m->tw0[i] + cv * m->tw1[i];
+    /* new Exner perturbation history = pi^n - pi_ref, taken before pi is replaced */
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < NC; ++i) m->pi_prev[i] = m->pi[i] - m->pi_ref[i];
+    /* the column writes into the * buffers, then the state takes them over */
+    column_phase(m, dt, m->rho_i, m->thv_i, m->twm, m->wcc1, m->ws, m->rhos, m->pis, m->thvs,
+                 m->vflux);
+    memcpy(m->w, m->ws, sizeof(double) * NC1);
+    memcpy(m->rho, m->rhos, sizeof(double) * NC);
+    memcpy(m->pi, m->pis, sizeof(double) * NC);
+    memcpy(m->thv, m->thvs, sizeof(double) * NC);
+    memcpy(m->vn, m->vnn, sizeof(double) * NE);
+    /* FP64 mass-flux accumulation */
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < NE; ++i) m->facc[i] += m->flx[i] / nsub;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < NC1; ++i) m->wacc[i] += m->vflux[i] / nsub;
+}
+
+int or_step(or_model *m, double dt, int nsub) {
+    if (!m || !(dt > 0) || !isfinite(dt) || nsub < 1) return -1;
+    const int64_t N = m->N;
+    memset(m->facc, 0, sizeof(double) * N * m->g.ne);
+    memset(m->wacc, 0, sizeof(double) * (N + 1) * m->g.nc);
+    const double dts = dt / nsub;
+    for (int s = 0; s < nsub; ++s) substep(m, dts, nsub);
+    return 0;
+}
+
+/* compensated (Kahan) sums in fixed entity order, single thread */
+int or_diag(const or_model *m, double *mass, double *rho_theta) {
+    if (!m) return -1;
+    const int64_t nc = m->g.nc;
+    double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0;
+    for (int k = 0; k < m->N; ++k)
+        for (int64_t c = 0; c < nc; ++c) {
+            double vol = m->g.cell_area[c] * AT(m->dz, k, nc, c);
+            double x = vol * AT(m->rho, k, nc, c) - c1;
+            double t = s1 + x;
+            c1 = (t - s1) - x;
+            s1 = t;
+            double y = vol * AT(m->rho, k, nc, c) * AT(m->thv, k, nc, c) - c2;
+            double u = s2 + y;
+            c2 = (u - s2) - y;
+            s2 = u;
+        }
+    if (mass) *mass = s1;
+    if (rho_theta) *rho_theta = s2;
+    return 0;
+}

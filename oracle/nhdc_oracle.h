@@ -1,0 +1,131 @@
+/*
+ * nhdc_oracle.h -- plain, slow FP64 CPU oracle of the nonhydrostatic
+ * dynamical-core substep.  TEST INFRASTRUCTURE ONLY: the tests, the smoke
+ * check and the CPU baseline of the benchmark call it; the product library
+ * never links, loads or includes anything from this directory, and this
+ * directory includes nothing of the product.
+ *
+ * What it computes.  The paper runs ICON's nonhydrostatic atmosphere on the
+ * icosahedral-triangular C grid with a terrain-following hybrid height
+ * coordinate (Sec. 2), normal velocity on triangle edges (Table 2 counts it as
+ * 1.5 variables per cell) and indirect addressing over triangles and their
+ * hexagon/pentagon dual (Sec. 3.2).  It prints no equation of the dynamical
+ * core, so the discretisation below is this project's own specification of
+ * an ICON-style substep (vector-invariant momentum equation, Exner pressure,
+ * predictor-corrector horizontal step, vertically implicit w/Exner solve):
+ *
+ *   operators, per level, sums in slot order:
+ *     D(F)_c = sum_j s(c,e_j) l_ej F_ej / A_c          G(p)_e = (p_c2 - p_c1)/d_e
+ *     T(q)_e = (q_v2 - q_v1)/l_e                      Z(u)_v = sum_ring sigma d_e u_e / A_v
+ *     M(q)_c = sum_j q_ej / 3    E(p)_e = (p_c1+p_c2)/2    P(p)_v = sum_ring p_c / valence
+ *     Perot vector V_c = radial-free part of sum_j s l u a (x_e - x_c) / A_c,
+ *     vt_e = (V_c1 + V_c2)/2 . t_e
+ *   vertical: z_k = (zh_k + zh_k+1)/2, dz_k = zh_k - zh_k+1, linear interpolation
+ *     to half levels with g_i = (z_i-1 - zh_i)/(z_i-1 - z_i); boundary half levels
+ *     copy the adjacent full level; edge metrics average their two cells;
+ *     slopes from cell (and vertex-averaged) heights.
+ *   velocity tendencies VT(vn, w) -> (T_vn, T_w, w_cc): kinetic-energy gradient,
+ *     (vorticity + Coriolis) x tangential velocity, contravariant vertical
+ *     advection of vn; horizontal and vertical advection of w.
+ *   one substep: extrapolated Exner perturbation and its terrain-corrected
+ *     normal gradient; predictor vn*, fluxes, divergences, column solve; VT on
+ *     the predicted state; corrector vn with averaged tendencies and
+ *     divergence damping; fluxes; column solve about state n with interface
+ *     values averaged between n and *; FP64 mass-flux accumulation.
+ *   column solve: explicit parts, tridiagonal system in w on interior half
+ *     levels (Thomas, no pivoting), then rho, Exner, theta_v updates; theta_v
+ *     from the linearised equation of state so that rho*theta_v is in flux form.
+ *
+ * Every array is FP64, level-major [k][entity]; connectivity slot-major.
+ * Built with -O2 -ffp-contract=off (no fused multiply-add), OpenMP over
+ * entities within each phase only; results do not depend on thread count.
+ */
+#ifndef NHDC_ORACLE_H
+#define NHDC_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OR_MAX_LEV 512
+
+typedef struct or_grid {
+    int64_t nc, ne, nv;
+    double radius;
+    const int32_t *cell_edges, *cell_verts, *cell_cells; /* [3][nc] */
+    const int8_t *cell_sign;                             /* [3][nc] */
+    const int32_t *edge_cells, *edge_verts;              /* [2][ne] */
+    const int32_t *vert_edges, *vert_cells;              /* [6][nv] */
+    const int8_t *vert_sign;                             /* [6][nv] */
+    const int32_t *vert_valence;                         /* [nv] */
+    const double *cell_x, *cell_area;                    /* [3][nc], [nc] */
+    const double *edge_x, *edge_normal, *edge_tangent;   /* [3][ne] */
+    const double *edge_length, *dual_length;             /* [ne] */
+    const double *vert_x, *vert_area;                    /* [3][nv], [nv] */
+} or_grid;
+
+typedef struct or_params {
+    double radius, omega, grav, rd, cpd, p00;
+    double beta;      /* implicit weight of the vertical solve */
+    double wgt_corr;  /* corrector weight of the new tendency */
+    double extrap;    /* Exner-perturbation extrapolation factor */
+    double div_damp;  /* divergence damping coefficient */
+} or_params;
+
+typedef struct or_model or_model;
+
+/* The model keeps pointers to the grid arrays (caller keeps them alive) and
+ * copies zh [N+1][nc], pi_ref and theta_ref [N][nc]. NULL on bad input. */
+or_model *or_create(const or_grid *g, int nlev, const double *zh, const double *pi_ref,
+                    const double *theta_ref, const or_params *p);
+void or_free(or_model *m);
+/* pi_prev may be NULL: it is then pi - pi_ref (first extrapolation = identity). */
+int or_set_state(or_model *m, const double *vn, const double *w, const double *rho,
+                 const double *pi, const double *theta_v, const double *pi_prev);
+int or_get_state(const or_model *m, double *vn, double *w, double *rho, double *pi,
+                 double *theta_v, double *pi_prev);
+int or_get_flux(const or_model *m, double *facc, double *wacc);
+/* step(dt, nsub): nsub substeps of dt/nsub; the flux accumulators are zeroed first. */
+int or_step(or_model *m, double dt, int nsub);
+/* velocity tendencies of (vn, w) with the model's metrics; outputs [N][ne], [N+1][nc] x2.
+ * vt_out (optional, [N][ne]) receives the reconstructed tangential velocity. */
+int or_vt(or_model *m, const double *vn, const double *w, double *tvn, double *tw, double *wcc,
+          double *vt_out);
+/* terrain-corrected normal gradient of a full-level cell field [N][nc] -> [N][ne] */
+int or_pgrad(or_model *m, const double *p, double *gp);
+/* dry mass sum_c,k A_c dz_c,k rho_c,k and sum A dz rho theta_v (Kahan, fixed order) */
+int or_diag(const or_model *m, double *mass, double *rho_theta);
+
+/* Single-level operators on a grid (arrays of one level). */
+void or_op_div(const or_grid *g, const double *f_e, double *out_c);
+void or_op_grad(const or_grid *g, const double *p_c, double *out_e);
+void or_op_tgrad(const or_grid *g, const double *q_v, double *out_e);
+void or_op_curl(const or_grid *g, const double *u_e, double *out_v);
+void or_op_cell_avg(const or_grid *g, const double *q_e, double *out_c);
+void or_op_vert_avg(const or_grid *g, const double *p_c, double *out_v);
+/* Perot reconstruction with explicit positions [3][n] (metres) and cell radial
+ * unit vectors: out_vc [3][nc] cell vectors, out_vt [ne] tangential velocity. */
+void or_op_perot(const or_grid *g, const double *pos_c, const double *pos_e,
+                 const double *radial_c, const double *u_e, double *out_vc, double *out_vt);
+
+/* Tridiagonal solve without pivoting: a[i] x[i-1] + b[i] x[i] + c[i] x[i+1] = r[i]. */
+int or_thomas(int n, const double *a, const double *b, const double *c, const double *r,
+              double *x);
+
+/* One column of the vertically implicit solve (all arrays of this column,
+ * contiguous, top to bottom).  Inputs: half-level heights zh[N+1], reference
+ * pi_ref/theta_ref[N]; linearisation state pi_n, rho_n, thv_n[N]; interface
+ * state rho_i, thv_i[N]; w_n[N+1]; w tendency tw[N+1]; contravariant
+ * correction wcc[N+1]; horizontal divergences div_rho, div_th[N].  Outputs
+ * w[N+1], rho, pi, thv[N] and the vertical mass flux at half levels vflux[N+1]. */
+int or_column(int nlev, double dt, const or_params *p, const double *zh, const double *pi_ref,
+              const double *theta_ref, const double *pi_n, const double *rho_n,
+              const double *thv_n, const double *rho_i, const double *thv_i, const double *w_n,
+              const double *tw, const double *wcc, const double *div_rho, const double *div_th,
+              double *w_out, double *rho_out, double *pi_out, double *thv_out, double *vflux);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,467 @@
+"""Pins of the FP64 CPU oracle against what mathematics fixes independently of
+its code: mimetic identities of the C-grid operators, exactness of the vector
+reconstruction on a plane, closed forms of solid-body rotation, LAPACK on the
+tridiagonal solve, a dense solve of the un-substituted implicit column
+equations, the resting atmosphere, conservation of mass and rho*theta_v, the
+linear gravity-wave dispersion relation, and algebraic invariances
+(numbering, substep splitting, save/resume)."""
+import types
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2511_02021_amd.inputs import case as CS
+from paper_2511_02021_amd.inputs import grid as G
+
+A = G.EARTH_RADIUS
+
+
+@pytest.fixture(scope="module")
+def g4():
+    return G.build_grid(4, order="sfc")
+
+
+def _scale(x):
+    return np.abs(x).max()
+
+
+# ---------------------------------------------------------------------------
+# operators
+
+def test_curl_of_gradient_vanishes(g4):
+    psi = np.random.default_rng(1).standard_normal(g4.n_cells)
+    gp = oracle.grad(g4, psi)
+    z = oracle.curl(g4, gp)
+    scale = np.abs(g4.dual_length * gp).max() * 6 / g4.vert_area.min()
+    assert _scale(z) <= 1e-13 * scale
+
+
+def test_divergence_of_tangential_gradient_vanishes(g4):
+    chi = np.random.default_rng(2).standard_normal(g4.n_verts)
+    tg = oracle.tgrad(g4, chi)
+    d = oracle.div(g4, tg)
+    scale = np.abs(g4.edge_length * tg).max() * 3 / g4.cell_area.min()
+    assert _scale(d) <= 1e-13 * scale
+
+
+def test_area_weighted_divergence_sums_to_zero(g4):
+    f = np.random.default_rng(3).standard_normal(g4.n_edges)
+    d = oracle.div(g4, f)
+    tot = np.sum(g4.cell_area * d)
+    assert abs(tot) <= 1e-13 * np.sum(np.abs(g4.edge_length * f))
+
+
+def test_averages_of_constants(g4):
+    assert np.allclose(oracle.cell_avg(g4, np.full(g4.n_edges, 2.5)), 2.5, rtol=0, atol=1e-15)
+    assert np.allclose(oracle.vert_avg(g4, np.full(g4.n_cells, -1.25)), -1.25, rtol=0, atol=1e-15)
+
+
+def _planar_patch(n=12, jitter=0.08, seed=0):
+    """Jittered planar triangle lattice with circumcentres, in the oracle's grid layout."""
+    rng = np.random.default_rng(seed)
+    pts = {}
+    for j in range(n + 1):
+        for i in range(n + 1):
+            pts[(i, j)] = np.array([i + 0.5 * j, j * np.sqrt(3) / 2, 0.0]) + \
+                np.append(rng.uniform(-jitter, jitter, 2), 0.0)
+    vid = {key: k for k, key in enumerate(pts)}
+    vx = np.array([pts[key] for key in pts]).T
+    tris = []
+    for j in range(n):
+        for i in range(n):
+            if i + 1 <= n and j + 1 <= n:
+                tris.append((vid[(i, j)], vid[(i + 1, j)], vid[(i, j + 1)]))
+            if i + 1 <= n and j + 1 <= n:
+                tris.append((vid[(i + 1, j)], vid[(i + 1, j + 1)], vid[(i, j + 1)]))
+    tris = np.array(tris)
+    nc = len(tris)
+    edges, cell_edges = {}, np.zeros((3, nc), np.int32)
+    for c, t in enumerate(tris):
+        for s in range(3):
+            key = tuple(sorted((t[s], t[(s + 1) % 3])))
+            if key not in edges:
+                edges[key] = len(edges)
+            cell_edges[s, c] = edges[key]
+    ne = len(edges)
+    ev = np.array(list(edges.keys())).T
+    edge_cells = np.full((2, ne), -1, np.int32)
+    for c in range(nc):
+        for s in range(3):
+            e = cell_edges[s, c]
+            edge_cells[0 if edge_cells[0, e] < 0 else 1, e] = c
+    # circumcentres and areas
+    p0, p1, p2 = (vx[:, tris[:, s]] for s in range(3))
+    d = 2 * (p0[0] * (p1[1] - p2[1]) + p1[0] * (p2[1] - p0[1]) + p2[0] * (p0[1] - p1[1]))
+    sq = [(q ** 2).sum(0) for q in (p0, p1, p2)]
+    ux = (sq[0] * (p1[1] - p2[1]) + sq[1] * (p2[1] - p0[1]) + sq[2] * (p0[1] - p1[1])) / d
+    uy = (sq[0] * (p2[0] - p1[0]) + sq[1] * (p0[0] - p2[0]) + sq[2] * (p1[0] - p0[0])) / d
+    xc = np.stack([ux, uy, np.zeros(nc)])
+    area = 0.5 * np.abs((p1[0] - p0[0]) * (p2[1] - p0[1]) - (p2[0] - p0[0]) * (p1[1] - p0[1]))
+    xe = 0.5 * (vx[:, ev[0]] + vx[:, ev[1]])
+    chord = vx[:, ev[1]] - vx[:, ev[0]]
+    length = np.linalg.norm(chord, axis=0)
+    nrm = np.stack([chord[1], -chord[0], np.zeros(ne)]) / length
+    flip = (nrm * (xe - xc[:, edge_cells[0]])).sum(0) < 0  # point away from c1
+    nrm[:, flip] *= -1
+    tng = np.cross(np.array([0, 0, 1.0])[:, None], nrm, axis=0)
+    interior = edge_cells[1] >= 0
+    edge_cells[1, ~interior] = edge_cells[0, ~interior]
+    sign = np.where(edge_cells[0, cell_edges] == np.arange(nc), 1, -1).astype(np.int8)
+    z32 = np.zeros((6, 1), np.int32)
+    gr = types.SimpleNamespace(
+        n_cells=nc, n_edges=ne, n_verts=1, radius=1.0, cell_edges=cell_edges,
+        cell_verts=np.zeros((3, nc), np.int32), cell_cells=np.zeros((3, nc), np.int32),
+        cell_sign=sign, edge_cells=edge_cells, edge_verts=np.zeros((2, ne), np.int32),
+        vert_edges=z32, vert_cells=z32, vert_sign=np.zeros((6, 1), np.int8),
+        vert_valence=np.zeros(1, np.int32), cell_x=xc, cell_area=area, edge_x=xe,
+        edge_normal=nrm, edge_tangent=tng, edge_length=length, dual_length=np.ones(ne),
+        vert_x=np.zeros((3, 1)), vert_area=np.ones(1))
+    return gr, interior
+
+
+def test_perot_exact_for_uniform_vector_on_a_plane():
+    gr, interior = _planar_patch()
+    U = np.array([0.3, -1.2, 0.0])
+    u = U @ gr.edge_normal
+    radial = np.zeros((3, gr.n_cells))
+    radial[2] = 1.0
+    vc, vt = oracle.perot(gr, gr.cell_x, gr.edge_x, radial, u)
+    assert np.abs(vc - U[:, None]).max() < 1e-13
+    assert np.abs(vt[interior] - (U @ gr.edge_tangent)[interior]).max() < 1e-13
+
+
+def _solid_body(g, u0=20.0):
+    U = u0 * np.cross(np.array([0.0, 0.0, 1.0])[:, None], g.edge_x, axis=0)
+    return U, (U * g.edge_normal).sum(0), (U * g.edge_tangent).sum(0)
+
+
+def test_solid_body_rotation_convergence():
+    """vt, vorticity and cell kinetic energy of u = u0 cos(lat) converge to the
+    closed forms (u0 cos(lat) . t, 2 u0 sin(lat)/a, u0^2 cos^2(lat)/2)."""
+    errs = {"vt": [], "zeta": [], "ke": []}
+    u0 = 20.0
+    for k in (2, 3, 4, 5):
+        c = CS.make_case(k, 2, z_top=2000.0, sigma=0.0, order="sfc")
+        g = c.grid
+        _, vn, vt_exact = _solid_body(g, u0)
+        m = oracle.Model(c)
+        vn2 = np.tile(vn, (2, 1))
+        _, _, _, vt = m.vt(vn2, np.zeros((3, g.n_cells)))
+        zeta = oracle.curl(g, vn)
+        ke = oracle.cell_avg(g, 0.5 * (vn ** 2 + vt[0] ** 2))
+        errs["vt"].append(np.abs(vt[0] - vt_exact).max() / u0)
+        errs["zeta"].append(np.abs(zeta - 2 * u0 * g.vert_x[2] / A).max() / (2 * u0 / A))
+        cos2 = 1 - g.cell_x[2] ** 2
+        errs["ke"].append(np.abs(ke - 0.5 * u0 ** 2 * cos2).max() / (0.5 * u0 ** 2))
+    for name, e in errs.items():
+        e = np.array(e)
+        rates = np.log2(e[:-1] / e[1:])
+        assert np.all(e[1:] < e[:-1]), (name, e)
+        assert rates[-1] > 0.9, (name, e, rates)
+    assert errs["vt"][-1] < 2e-3 and errs["zeta"][-1] < 2e-2 and errs["ke"][-1] < 2e-2
+
+
+# ---------------------------------------------------------------------------
+# column solve
+
+@pytest.mark.parametrize("n", [3, 4, 5, 8, 20])
+def test_thomas_matches_lapack(n):
+    rng = np.random.default_rng(n)
+    a, c = rng.uniform(-1, 0, n), rng.uniform(-1, 0, n)
+    b = 2.5 + rng.uniform(0, 1, n)
+    a[0] = c[-1] = 0.0
+    r = rng.standard_normal(n)
+    M = np.diag(b) + np.diag(a[1:], -1) + np.diag(c[:-1], 1)
+    ref = np.linalg.solve(M, r)
+    got = oracle.thomas(a, b, c, r)
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def _random_column(N, seed):
+    rng = np.random.default_rng(seed)
+    p = CS.Params()
+    dz = rng.uniform(200.0, 900.0, N)
+    zh = np.concatenate([np.cumsum(dz[::-1])[::-1], [0.0]]) + rng.uniform(0, 500)
+    z = 0.5 * (zh[:-1] + zh[1:])
+    tref = 213.15 + 75.0 * np.exp(-z / 1e4)
+    pi_ref = np.exp(-p.grav / (p.cpd * 260.0) * z)
+    theta_ref = tref / pi_ref
+    pi_n = pi_ref * (1 + 0.01 * rng.standard_normal(N))
+    thv_n = theta_ref * (1 + 0.02 * rng.standard_normal(N))
+    rho_n = p.p00 * pi_n ** (p.cvd / p.rd) / (p.rd * thv_n)
+    rho_i = rho_n * (1 + 0.01 * rng.standard_normal(N))
+    thv_i = thv_n * (1 + 0.01 * rng.standard_normal(N))
+    w_n = 0.3 * rng.standard_normal(N + 1)
+    w_n[0] = 0.0
+    tw = 0.01 * rng.standard_normal(N + 1)
+    wcc = 0.05 * rng.standard_normal(N + 1)
+    wcc[0] = 0.0
+    div_rho = 1e-5 * rng.standard_normal(N)
+    div_th = 3e-3 * rng.standard_normal(N)
+    return p, dict(zh=zh, pi_ref=pi_ref, theta_ref=theta_ref, pi_n=pi_n, rho_n=rho_n, thv_n=thv_n,
+                   rho_i=rho_i, thv_i=thv_i, w_n=w_n, tw=tw, wcc=wcc, div_rho=div_rho,
+                   div_th=div_th)
+
+
+@pytest.mark.parametrize("N,seed", [(3, 0), (5, 1), (8, 2), (20, 3), (90, 4)])
+def test_column_matches_dense_solve_of_implicit_equations(N, seed):
+    """Solve the implicit w / mass / rho*theta_v / linearised-EOS equations as
+    one dense linear system (no substitution, no Thomas) and compare."""
+    p, col = _random_column(N, seed)
+    dt = 60.0
+    out = oracle.column(p, dt, **col)
+    zh, prf, trf = col["zh"], col["pi_ref"], col["theta_ref"]
+    z = 0.5 * (zh[:-1] + zh[1:])
+    dz = zh[:-1] - zh[1:]
+    gw = (z[:-1] - zh[1:-1]) / (z[:-1] - z[1:])
+    dzh = z[:-1] - z[1:]
+    itp = lambda f: gw * f[1:] + (1 - gw) * f[:-1]   # interior half levels 1..N-1
+    rhoh, thh = itp(col["rho_i"]), itp(col["thv_i"])
+    thph = itp(col["thv_i"] - trf)
+    dref = -p.grav / (p.cpd * itp(trf))
+    ppn = col["pi_n"] - prf
+    rtn = col["rho_n"] * col["thv_n"]
+    wn, wcc, b = col["w_n"], col["wcc"], p.beta
+    nw = N - 1
+    iw = lambda i: i - 1               # unknown index of w at interior half level i
+    ir = lambda k: nw + k
+    ix = lambda k: nw + N + k
+    iq = lambda k: nw + 2 * N + k
+    M = np.zeros((nw + 3 * N, nw + 3 * N))
+    rhs = np.zeros(nw + 3 * N)
+    for i in range(1, N):
+        r = i
+        M[r - 1, iw(i)] = 1.0
+        coef = dt * p.cpd * b * thh[i - 1] / dzh[i - 1]
+        M[r - 1, iq(i - 1)] += coef
+        M[r - 1, iq(i)] -= coef
+        rhs[r - 1] = wn[i] + dt * (col["tw"][i] - p.cpd * (
+            (1 - b) * thh[i - 1] * (ppn[i - 1] - ppn[i]) / dzh[i - 1] + thph[i - 1] * dref[i - 1]))
+    for k in range(N):
+        # mass: rho_k + dt (flux_k - flux_k+1)/dz_k = rho_n - dt div
+        M[ir(k), ir(k)] = 1.0
+        M[ix(k), ix(k)] = 1.0
+        rhs[ir(k)] = col["rho_n"][k] - dt * col["div_rho"][k]
+        rhs[ix(k)] = rtn[k] - dt * col["div_th"][k]
+        for i, sgn in ((k, 1.0), (k + 1, -1.0)):
+            if 1 <= i <= N - 1:
+                h = i - 1
+                expl = rhoh[h] * ((1 - b) * wn[i] - wcc[i])
+                M[ir(k), iw(i)] += sgn * dt * rhoh[h] * b / dz[k]
+                rhs[ir(k)] -= sgn * dt * expl / dz[k]
+                M[ix(k), iw(i)] += sgn * dt * thh[h] * rhoh[h] * b / dz[k]
+                rhs[ix(k)] -= sgn * dt * thh[h] * expl / dz[k]
+        # linearised equation of state
+        fac = (p.rd / p.cvd) * col["pi_n"][k] / rtn[k]
+        M[iq(k), iq(k)] = 1.0
+        M[iq(k), ix(k)] = -fac
+        rhs[iq(k)] = ppn[k] - fac * rtn[k]
+    sol = np.linalg.solve(M, rhs)
+    w = sol[:nw]
+    rho = sol[nw:nw + N]
+    X = sol[nw + N:nw + 2 * N]
+    q = sol[nw + 2 * N:]
+    tol = 1e-11
+    assert np.abs(out["w"][1:N] - w).max() <= tol * max(np.abs(w).max(), 1e-3)
+    assert out["w"][0] == 0.0 and out["w"][N] == wcc[N]
+    assert np.abs(out["rho"] - rho).max() <= tol * np.abs(rho).max()
+    assert np.abs(out["pi"] - (prf + q)).max() <= tol * np.abs(prf + q).max()
+    assert np.abs(out["theta_v"] - X / rho).max() <= tol * np.abs(X / rho).max()
+    # the reported vertical flux is the one the mass update used
+    fl = out["vflux"]
+    assert fl[0] == 0.0 and fl[N] == 0.0
+    rho_chk = col["rho_n"] - dt * (col["div_rho"] + (fl[:-1] - fl[1:]) / dz)
+    assert np.abs(rho_chk - out["rho"]).max() <= 1e-13 * np.abs(rho).max()
+
+
+def test_column_at_rest_in_balance_is_stationary():
+    c = CS.make_case(2, 30, z_top=75000.0, stretch=1.6, terrain_seed=[1, 9, 0], sigma=0.0)
+    j = 17
+    N = c.n_lev
+    col = dict(zh=c.zh[:, j], pi_ref=c.pi_ref[:, j], theta_ref=c.theta_ref[:, j], pi_n=c.pi[:, j],
+               rho_n=c.rho[:, j], thv_n=c.theta_v[:, j], rho_i=c.rho[:, j], thv_i=c.theta_v[:, j],
+               w_n=np.zeros(N + 1), tw=np.zeros(N + 1), wcc=np.zeros(N + 1),
+               div_rho=np.zeros(N), div_th=np.zeros(N))
+    out = oracle.column(c.params, 60.0, **col)
+    # round-off of the balance near the 75 km lid (theta ~ 5000 K) gives w ~ 1e-13 m/s
+    assert np.abs(out["w"]).max() < 1e-12
+    assert np.abs(out["rho"] / col["rho_n"] - 1).max() < 1e-14
+    assert np.abs(out["pi"] / col["pi_n"] - 1).max() < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# vertical-coordinate terms
+
+def test_terrain_corrected_gradient_of_height_only_field():
+    """A field that depends on height only has no horizontal gradient at
+    constant height; the slope term must cancel the along-level difference."""
+    errs = []
+    for k in (3, 4):
+        c = CS.config_case(2, k=k, n_lev=40)
+        m = oracle.Model(c)
+        z = 0.5 * (c.zh[:-1] + c.zh[1:])
+        f = 0.02 * np.exp(-z / 6000.0)
+        gp = m.pgrad(f)
+        along = oracle.grad(c.grid, f[-1])
+        ratio = np.abs(gp[-10:]).max() / np.abs(along).max()
+        errs.append(ratio)
+    assert errs[0] < 0.05 and errs[1] < errs[0]
+
+
+def test_contravariant_correction_over_linear_terrain():
+    """Over h = H (1 + x) (x the first unit-vector coordinate), solid-body flow
+    gives a surface contravariant correction u . grad h = -H u0 y / a."""
+    H, u0 = 1000.0, 20.0
+    errs = []
+    for k in (3, 4):
+        c = CS.make_case(k, 10, z_top=30000.0, sigma=0.0,
+                         terrain_seed=lambda gr: H * (1.0 + gr.cell_x[0]))
+        g = c.grid
+        _, vn, _ = _solid_body(g, u0)
+        m = oracle.Model(c)
+        _, _, wcc, _ = m.vt(np.tile(vn, (c.n_lev, 1)), np.zeros((c.n_lev + 1, g.n_cells)))
+        exact = -H * u0 * g.cell_x[1] / A
+        errs.append(np.abs(wcc[-1] - exact).max() / np.abs(exact).max())
+        assert np.all(wcc[0] == 0.0)
+    assert errs[0] < 0.05 and errs[1] < errs[0]
+
+
+# ---------------------------------------------------------------------------
+# integration invariants
+
+def _run(case, steps, params=None):
+    m = oracle.Model(case, params)
+    for _ in range(steps):
+        m.step(case.dt, case.nsub)
+    return m
+
+
+@pytest.mark.parametrize("k,nlev,ztop,stretch", [(4, 20, 30000.0, 1.0), (3, 30, 75000.0, 1.6)])
+def test_resting_atmosphere_stays_at_rest(k, nlev, ztop, stretch):
+    p = CS.Params(div_damp=0.0)
+    c = CS.make_case(k, nlev, z_top=ztop, stretch=stretch, sigma=0.0, dt=300.0, params=p)
+    m = _run(c, 100)
+    s = m.state()
+    assert np.abs(s["vn"]).max() <= 1e-11 and np.abs(s["w"]).max() <= 1e-11
+    for f in ("rho", "pi", "theta_v"):
+        assert np.abs(s[f] / getattr(c, f) - 1).max() <= 1e-13, f
+
+
+def test_unbalanced_rest_state_is_not_stationary():
+    """Negative control: the analytic (continuous) hydrostatic profile is not a
+    discrete equilibrium, so it must drift far above round-off."""
+    p = CS.Params(div_damp=0.0)
+    c = CS.make_case(4, 20, z_top=30000.0, sigma=0.0, dt=300.0, balanced=False, params=p)
+    s = _run(c, 3).state()
+    assert np.abs(s["rho"] / c.rho - 1).max() > 1e-6
+
+
+@pytest.mark.parametrize("which", ["flat", "terrain"])
+def test_mass_and_rho_theta_conserved(which):
+    c = CS.config_case(1) if which == "flat" else CS.config_case(2, k=3, n_lev=30)
+    m = oracle.Model(c)
+    M0, R0 = m.diag()
+    for _ in range(20):
+        m.step(c.dt, c.nsub)
+    M, R = m.diag()
+    s = m.state()
+    assert np.abs(s["vn"]).max() > 0.5          # the state moved
+    assert abs(M / M0 - 1) <= 1e-13 and abs(R / R0 - 1) <= 1e-13
+
+
+def _gravity_wave_rel_error(k, steps=300, nlev=20):
+    p = CS.Params(omega=0.0, div_damp=0.0)
+    c = CS.make_case(k, nlev, z_top=30000.0, sigma=0.0, dt=300.0, gravity_wave=(1e-5, 8),
+                     params=p)
+    m = oracle.Model(c)
+    T0, zt = CS.T0, 30000.0
+    H = p.rd * T0 / p.grav
+    mz = np.pi / zt
+    pl = CS.legendre(8, np.sin(CS.latitude(c.grid)))
+    wgt = (c.grid.cell_area * pl)[None, :] * np.exp(-c.zh / (2 * H)) * np.sin(mz * c.zh)
+    ts, ps = [0.0], [0.0]
+    for n in range(steps):
+        m.step(c.dt, c.nsub)
+        ts.append((n + 1) * c.dt)
+        ps.append(float((wgt * m.state()["w"]).sum()))
+    ts, ps = np.array(ts), np.array(ps)
+    # analytic: smaller root of w^4 - w^2 [cs^2 (k^2+m^2) + cs^2/(4H^2)] + N^2 cs^2 k^2 = 0
+    cs2 = p.cpd / p.cvd * p.rd * T0
+    n2 = p.grav ** 2 / (p.cpd * T0)
+    kh2 = 8 * 9 / p.radius ** 2
+    a = cs2 * (kh2 + mz ** 2) + cs2 / (4 * H * H)
+    om = np.sqrt((a - np.sqrt(a * a - 4 * n2 * cs2 * kh2)) / 2)
+    assert abs(om - 2.084e-4) < 1e-7
+    from scipy.optimize import curve_fit
+    f = lambda t, amp, w, ph, lam, c0: amp * np.sin(w * t + ph) * np.exp(-lam * t) + c0
+    popt, _ = curve_fit(f, ts, ps, p0=[np.abs(ps).max(), om, 0.0, 0.0, 0.0], maxfev=20000)
+    return popt[1] / om - 1
+
+
+def test_gravity_wave_frequency_r2b3():
+    err = _gravity_wave_rel_error(3)
+    assert abs(err) < 0.025
+
+
+@pytest.mark.slow
+def test_gravity_wave_frequency_converges():
+    e3, e4 = _gravity_wave_rel_error(3), _gravity_wave_rel_error(4)
+    assert abs(e4) < 0.02 and abs(e4) < abs(e3)
+
+
+def test_substep_splitting_is_exact():
+    c = CS.config_case(2, k=3, n_lev=20)
+    a = oracle.Model(c)
+    a.step(c.dt, 5)
+    b = oracle.Model(c)
+    for _ in range(5):
+        b.step(c.dt / 5, 1)
+    sa, sb = a.state(), b.state()
+    for f in sa:
+        assert np.array_equal(sa[f], sb[f]), f
+
+
+def test_numbering_invariance():
+    ref = None
+    for order, seed in (("canonical", 0), ("sfc", 0), ("random", 5)):
+        canon, gr = G.build_grid(3, order=order, seed=seed, with_canonical=True)
+        c = CS.config_case(2, k=3, n_lev=20, grids=(canon, gr))
+        s = _run(c, 2).state()
+        ic, ie = np.argsort(gr.canon_cell), np.argsort(gr.canon_edge)
+        back = {f: (v[:, ie] if f == "vn" else v[:, ic]) for f, v in s.items()}
+        if ref is None:
+            ref = back
+        else:
+            for f in ref:
+                assert np.array_equal(ref[f], back[f]), (order, f)
+
+
+def test_save_and_resume_is_exact():
+    c = CS.config_case(2, k=3, n_lev=20)
+    a = _run(c, 4).state()
+    m = _run(c, 2)
+    s = m.state()
+    m2 = oracle.Model(c)
+    m2.set_state(s["vn"], s["w"], s["rho"], s["pi"], s["theta_v"], s["pi_prev"])
+    for _ in range(2):
+        m2.step(c.dt, c.nsub)
+    b = m2.state()
+    for f in a:
+        assert np.array_equal(a[f], b[f]), f
+
+
+def test_flux_accumulators_average_the_substeps():
+    c = CS.config_case(2, k=3, n_lev=20)
+    m = oracle.Model(c)
+    M0, _ = m.diag()
+    m.step(c.dt, c.nsub)
+    facc, wacc = m.flux()
+    s = m.state()
+    # mass budget of one step from the averaged fluxes reproduces the new density
+    g = c.grid
+    dz = c.zh[:-1] - c.zh[1:]
+    div = np.stack([oracle.div(g, facc[k]) for k in range(c.n_lev)]) / dz
+    rho_chk = c.rho - c.dt * (div + (wacc[:-1] - wacc[1:]) / dz)
+    assert np.abs(rho_chk - s["rho"]).max() <= 1e-12 * np.abs(c.rho).max()
+    assert np.all(wacc[0] == 0) and np.all(wacc[-1] == 0)
