@@ -1,0 +1,175 @@
+/*
+ * nhdc.h -- C-ABI of the MI355X (gfx950) nonhydrostatic dynamical-core
+ * substep library libnhdc.so.
+ *
+ * The library advances the atmosphere's dynamical core on the icosahedral
+ * triangular C grid (paper Sec. 2: nonhydrostatic formulation on the
+ * icosahedral-triangular C grid with a terrain-following hybrid height
+ * coordinate; Table 2: normal velocity on edges, 90 levels; Sec. 3.2: the
+ * dynamical core is memory-bandwidth bound and dominated by indirect
+ * neighbour lookups).  The boundary follows the problem statement: upload a
+ * grid with its connectivity and vertical coordinate, initialise a state, then
+ * step(dt, nsubsteps).  Every step of the path runs in HIP kernels on the GPU;
+ * the state stays resident in device memory between calls (Sec. 3.1: data
+ * stay on the GPU for the whole run).
+ *
+ * One substep (length dt/nsubsteps) is: velocity tendencies of the current
+ * state; extrapolated Exner perturbation and its terrain-corrected normal
+ * gradient; predicted normal velocity, edge mass and rho*theta_v fluxes and
+ * their divergences; a vertically implicit tridiagonal solve per column for
+ * w and Exner pressure (with rho and theta_v updates); velocity tendencies of
+ * the predicted state; corrected normal velocity with averaged tendencies and
+ * divergence damping; fluxes; the implicit column solve again about the old
+ * state with interface values averaged between old and predicted; FP64
+ * accumulation of the mass fluxes.
+ *
+ * Conventions
+ *  - Return values: NHDC_OK (0) or a negative NHDC_E* code; nothing throws or
+ *    aborts across the ABI.  nhdc_last_error(ctx) gives the message of the
+ *    last failure of that context.
+ *  - Arrays: FP64 unless stated, level-major [k][i] (entity index fastest).
+ *    Full levels k = 0..N-1 top to bottom; half levels i = 0..N, half level i
+ *    is the top interface of full level i, i = N the ground.  Connectivity is
+ *    int32 slot-major [slot][i], -1 padded (see nhgrid.h for the conventions).
+ *  - Ownership: the caller owns every array it passes; upload and init copy.
+ *    The context owns its device memory until nhdc_destroy.
+ *  - Streams: `stream` is a hipStream_t passed as void* (NULL = default
+ *    stream).  nhdc_step only enqueues work; the caller synchronises.
+ *  - Numbering: arrays are used in the order given (the library never
+ *    renumbers); a space-filling-curve order (nhgrid_reorder) makes the
+ *    indirect gathers coalesce.
+ *  - Threading: one context is used by one host thread at a time; distinct
+ *    contexts are independent.
+ */
+#ifndef NHDC_H
+#define NHDC_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    NHDC_OK = 0,
+    NHDC_EINVAL = -1,    /* bad argument: NULL pointer, dt <= 0 or not finite, nsub < 1, size mismatch */
+    NHDC_ENOMEM = -2,    /* device or host allocation failed */
+    NHDC_EHIP = -3,      /* a HIP runtime call failed (message has hipGetErrorString) */
+    NHDC_EGRID = -4,     /* grid or vertical coordinate failed validation */
+    NHDC_ESTATE = -5,    /* call out of order (e.g. step before init) */
+    NHDC_EUNSTABLE = -6  /* non-finite value found by nhdc_check_finite */
+};
+
+enum { NHDC_FP64 = 0, NHDC_MIXED = 1 };
+
+typedef struct nhdc_ctx nhdc_ctx;
+
+/* Grid: host arrays, same layout as nhgrid_view (nhgrid.h). */
+typedef struct nhdc_grid {
+    int64_t n_cells, n_edges, n_verts;
+    double radius;
+    const int32_t *cell_edges;   /* [3][n_cells] */
+    const int8_t *cell_sign;     /* [3][n_cells] s(c,e): +1 if the edge normal points out of c */
+    const int32_t *edge_cells;   /* [2][n_edges] c1, c2 (normal points from c1 to c2) */
+    const int32_t *edge_verts;   /* [2][n_edges] v1, v2 (tangent points from v1 to v2) */
+    const int32_t *vert_edges;   /* [6][n_verts] counter-clockwise ring, -1 pad */
+    const int32_t *vert_cells;   /* [6][n_verts] ring cell j between ring edges j and j+1 */
+    const int8_t *vert_sign;     /* [6][n_verts] +1 if the vertex is v2 of the edge */
+    const int32_t *vert_valence; /* [n_verts] 5 or 6 */
+    const double *cell_x;        /* [3][n_cells] unit circumcentres */
+    const double *cell_area;     /* [n_cells] m^2 */
+    const double *edge_x;        /* [3][n_edges] unit edge midpoints */
+    const double *edge_tangent;  /* [3][n_edges] */
+    const double *edge_length;   /* [n_edges] primal length [m] */
+    const double *dual_length;   /* [n_edges] distance between the two circumcentres [m] */
+    const double *vert_area;     /* [n_verts] dual area [m^2] */
+} nhdc_grid;
+
+/* Vertical coordinate and reference profile of one column set (host arrays). */
+typedef struct nhdc_vertical {
+    int32_t n_lev;             /* N, 2 <= N <= NHDC_MAX_LEV */
+    const double *zh;          /* [N+1][n_cells] half-level heights, strictly decreasing in i */
+    const double *pi_ref;      /* [N][n_cells] reference Exner pressure at full levels */
+    const double *theta_ref;   /* [N][n_cells] reference potential temperature at full levels */
+} nhdc_vertical;
+
+#define NHDC_MAX_LEV 256
+
+typedef struct nhdc_params {
+    double omega;     /* planetary rotation [1/s] (Coriolis 2*omega*z at edge midpoints) */
+    double grav, rd, cpd, p00;
+    double beta;      /* implicit weight of the vertical solve (0.5..1) */
+    double wgt_corr;  /* weight of the predicted-state tendency in the corrector */
+    double extrap;    /* extrapolation factor of the Exner perturbation */
+    double div_damp;  /* second-order divergence damping coefficient (times mean cell area) */
+} nhdc_params;
+
+/* Prognostic state; pointers are host or device memory per `on_device`.
+ * vn [N][n_edges], w [N+1][n_cells], rho, pi (Exner), theta_v, pi_prev [N][n_cells].
+ * pi_prev is the Exner perturbation (pi - pi_ref) of the previous substep; on
+ * init it may be NULL, meaning pi - pi_ref (the first extrapolation is then
+ * the identity). */
+typedef struct nhdc_state_view {
+    double *vn, *w, *rho, *pi, *theta_v, *pi_prev;
+    int32_t on_device;
+} nhdc_state_view;
+
+/* Create a context on HIP device `device` with precision NHDC_FP64 (every
+ * operation in FP64) or NHDC_MIXED (horizontal stencils and tendencies in
+ * FP32; vertical solve, reference-state perturbations and mass fluxes FP64). */
+int nhdc_create(nhdc_ctx **out, int precision, int device);
+
+/* Copy and validate the grid (index ranges, edge-cell consistency, signs,
+ * positive lengths and areas) and the vertical coordinate; derive device
+ * metrics and stencil coefficients.  May be called once per context. */
+int nhdc_upload_grid(nhdc_ctx *ctx, const nhdc_grid *grid, const nhdc_vertical *vert,
+                     const nhdc_params *params);
+
+/* Copy the initial state (host or device memory); zeroes the flux accumulators. */
+int nhdc_init_state(nhdc_ctx *ctx, const nhdc_state_view *state, void *stream);
+
+/* Enqueue nsubsteps substeps of dt/nsubsteps.  The mass-flux accumulators are
+ * restarted at entry and hold the average over these substeps afterwards. */
+int nhdc_step(nhdc_ctx *ctx, double dt, int nsubsteps, void *stream);
+
+/* Copy the state into caller buffers (host or device per dst->on_device;
+ * NULL members are skipped).  Host copies are complete when this returns. */
+int nhdc_get_state(nhdc_ctx *ctx, const nhdc_state_view *dst, void *stream);
+
+/* Substep-averaged FP64 mass fluxes of the last step: edge fluxes
+ * rho*vn*dz [N][n_edges] (kg/m/s per unit edge length and layer) and
+ * vertical fluxes at half levels [N+1][n_cells] (kg/m^2/s). */
+int nhdc_get_mass_flux(nhdc_ctx *ctx, double *facc, double *wacc, int on_device, void *stream);
+
+/* Global dry mass sum A_c dz rho and sum A_c dz rho theta_v, computed on the
+ * device with a fixed-order two-level reduction (bitwise reproducible);
+ * synchronous. */
+int nhdc_diag(nhdc_ctx *ctx, double *mass, double *rho_theta, void *stream);
+
+/* NHDC_EUNSTABLE if any prognostic value is NaN or Inf, else NHDC_OK; synchronous. */
+int nhdc_check_finite(nhdc_ctx *ctx, void *stream);
+
+/* Number of cells, edges, vertices and levels of the uploaded grid. */
+int nhdc_sizes(const nhdc_ctx *ctx, int64_t *n_cells, int64_t *n_edges, int64_t *n_verts,
+               int32_t *n_lev);
+
+/* Per-kernel timing (the paper times with a cycle counter and reports the
+ * dynamical core's sustained bandwidth, Sec. 3.2 and 4.3).  While enabled,
+ * every kernel launch of nhdc_step is bracketed by HIP events on the step's
+ * stream and nhdc_step synchronises that stream before returning, so the
+ * timed work is the same kernels with events in between.  Enabling resets
+ * the accumulators. */
+int nhdc_set_timing(nhdc_ctx *ctx, int enable);
+/* Number of distinct kernels reported by nhdc_kernel_stats. */
+int nhdc_kernel_count(void);
+/* Name, accumulated time [ms] and launch count of kernel `index` since timing
+ * was enabled; NHDC_EINVAL for an index out of range. *name is static storage. */
+int nhdc_kernel_stats(const nhdc_ctx *ctx, int index, const char **name, double *total_ms,
+                      int64_t *launches);
+
+const char *nhdc_last_error(const nhdc_ctx *ctx);
+void nhdc_destroy(nhdc_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,441 @@
+// nhdc_runtime.hip -- host side of libnhdc: context, validation, stencil
+// coefficients, device memory, state transfer and the step driver.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "nhdc_internal.h"
+
+// host-side coefficients are formed without contraction, as the operators form them
+#pragma clang fp contract(off)
+
+using namespace nhdc;
+
+namespace {
+
+int set_err(nhdc_ctx *ctx, int code, const std::string &msg) {
+    if (ctx) ctx->err = msg;
+    return code;
+}
+
+int hip_err(nhdc_ctx *ctx, hipError_t e, const char *where) {
+    return set_err(ctx, NHDC_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(ctx, call)                                      \
+    do {                                                        \
+        hipError_t e_ = (call);                                 \
+        if (e_ != hipSuccess) return hip_err((ctx), e_, #call); \
+    } while (0)
+
+template <class T>
+int dalloc(nhdc_ctx *ctx, T **p, int64_t n) {
+    void *q = nullptr;
+    size_t bytes = size_t(n > 0 ? n : 1) * sizeof(T);
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return set_err(ctx, NHDC_ENOMEM,
+                       "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+    }
+    ctx->allocs.push_back(q);
+    *p = static_cast<T *>(q);
+    return NHDC_OK;
+}
+
+template <class T>
+int upload(nhdc_ctx *ctx, T **p, const T *host, int64_t n) {
+    int rc = dalloc(ctx, p, n);
+    if (rc) return rc;
+    HIP_TRY(ctx, hipMemcpy(*p, host, size_t(n) * sizeof(T), hipMemcpyHostToDevice));
+    return NHDC_OK;
+}
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0; }
+
+int validate(nhdc_ctx *ctx, const nhdc_grid *g, const nhdc_vertical *v) {
+    const int64_t nc = g->n_cells, ne = g->n_edges, nv = g->n_verts;
+    if (nc <= 0 || ne <= 0 || nv <= 0) return set_err(ctx, NHDC_EGRID, "grid: empty");
+    if (nv - ne + nc != 2) return set_err(ctx, NHDC_EGRID, "grid: Euler characteristic is not 2");
+    if (nc > INT32_MAX || ne > INT32_MAX || nv > INT32_MAX)
+        return set_err(ctx, NHDC_EGRID, "grid: too many entities for int32 indices");
+    if (!(g->radius > 0)) return set_err(ctx, NHDC_EGRID, "grid: radius must be positive");
+    const int N = v->n_lev;
+    if (N < 2 || N > NHDC_MAX_LEV) return set_err(ctx, NHDC_EINVAL, "vertical: n_lev out of range");
+    for (int64_t c = 0; c < nc; ++c) {
+        if (!finite_pos(g->cell_area[c])) return set_err(ctx, NHDC_EGRID, "grid: cell area <= 0");
+        for (int j = 0; j < 3; ++j) {
+            int64_t e = g->cell_edges[j * nc + c];
+            if (e < 0 || e >= ne) return set_err(ctx, NHDC_EGRID, "grid: cell_edges out of range");
+            int8_t s = g->cell_sign[j * nc + c];
+            int64_t c1 = g->edge_cells[e], c2 = g->edge_cells[ne + e];
+            if (!((s == 1 && c1 == c) || (s == -1 && c2 == c)))
+                return set_err(ctx, NHDC_EGRID, "grid: cell_sign inconsistent with edge_cells");
+        }
+    }
+    std::vector<uint8_t> seen(ne, 0);
+    for (int64_t c = 0; c < nc; ++c)
+        for (int j = 0; j < 3; ++j) seen[g->cell_edges[j * nc + c]]++;
+    for (int64_t e = 0; e < ne; ++e) {
+        if (seen[e] != 2) return set_err(ctx, NHDC_EGRID, "grid: edge not shared by exactly two cells");
+        for (int s = 0; s < 2; ++s) {
+            int64_t c = g->edge_cells[s * ne + e], vv = g->edge_verts[s * ne + e];
+            if (c < 0 || c >= nc) return set_err(ctx, NHDC_EGRID, "grid: edge_cells out of range");
+            if (vv < 0 || vv >= nv) return set_err(ctx, NHDC_EGRID, "grid: edge_verts out of range");
+        }
+        if (g->edge_cells[e] == g->edge_cells[ne + e])
+            return set_err(ctx, NHDC_EGRID, "grid: edge with identical cells");
+        if (!finite_pos(g->edge_length[e]) || !finite_pos(g->dual_length[e]))
+            return set_err(ctx, NHDC_EGRID, "grid: edge length <= 0");
+    }
+    for (int64_t vtx = 0; vtx < nv; ++vtx) {
+        int val = g->vert_valence[vtx];
+        if (val != 5 && val != 6) return set_err(ctx, NHDC_EGRID, "grid: valence not 5 or 6");
+        if (!finite_pos(g->vert_area[vtx])) return set_err(ctx, NHDC_EGRID, "grid: dual area <= 0");
+        for (int j = 0; j < 6; ++j) {
+            int64_t e = g->vert_edges[j * nv + vtx], c = g->vert_cells[j * nv + vtx];
+            if (j < val) {
+                if (e < 0 || e >= ne || c < 0 || c >= nc)
+                    return set_err(ctx, NHDC_EGRID, "grid: vertex ring index out of range");
+                int8_t s = g->vert_sign[j * nv + vtx];
+                bool is2 = g->edge_verts[ne + e] == vtx, is1 = g->edge_verts[e] == vtx;
+                if (!((s == 1 && is2) || (s == -1 && is1)))
+                    return set_err(ctx, NHDC_EGRID, "grid: vert_sign inconsistent with edge_verts");
+            } else if (e != -1 || c != -1) {
+                return set_err(ctx, NHDC_EGRID, "grid: pentagon pad slot must be -1");
+            }
+        }
+    }
+    for (int64_t c = 0; c < nc; ++c) {
+        for (int i = 0; i < N; ++i) {
+            double a = v->zh[int64_t(i) * nc + c], b = v->zh[int64_t(i + 1) * nc + c];
+            if (!(std::isfinite(a) && std::isfinite(b) && a > b))
+                return set_err(ctx, NHDC_EGRID, "vertical: zh not strictly decreasing");
+            if (!finite_pos(v->pi_ref[int64_t(i) * nc + c]) || !finite_pos(v->theta_ref[int64_t(i) * nc + c]))
+                return set_err(ctx, NHDC_EGRID, "vertical: reference state must be positive");
+        }
+    }
+    return NHDC_OK;
+}
+
+}  // namespace
+
+namespace nhdc {
+
+hipError_t timing_begin(nhdc_ctx *ctx, int id, hipStream_t st) {
+    Timing &t = ctx->tm;
+    if (!t.on) return hipSuccess;
+    size_t slot = t.ids.size();
+    while (t.ev.size() < 2 * (slot + 1)) {
+        hipEvent_t e;
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return r;
+        t.ev.push_back(e);
+    }
+    t.ids.push_back(id);
+    return hipEventRecord(t.ev[2 * slot], st);
+}
+
+hipError_t timing_end(nhdc_ctx *ctx, hipStream_t st) {
+    Timing &t = ctx->tm;
+    if (!t.on) return hipSuccess;
+    return hipEventRecord(t.ev[2 * (t.ids.size() - 1) + 1], st);
+}
+
+}  // namespace nhdc
+
+namespace {
+
+int timing_collect(nhdc_ctx *ctx, hipStream_t s) {
+    Timing &t = ctx->tm;
+    if (!t.on) return NHDC_OK;
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    for (size_t i = 0; i < t.ids.size(); ++i) {
+        float ms = 0.f;
+        HIP_TRY(ctx, hipEventElapsedTime(&ms, t.ev[2 * i], t.ev[2 * i + 1]));
+        t.total_ms[t.ids[i]] += ms;
+        t.launches[t.ids[i]] += 1;
+    }
+    t.ids.clear();
+    return NHDC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nhdc_create(nhdc_ctx **out, int precision, int device) {
+    if (!out) return NHDC_EINVAL;
+    *out = nullptr;
+    if (precision != NHDC_FP64 && precision != NHDC_MIXED) return NHDC_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+        (void)hipGetLastError();
+        return NHDC_EHIP;
+    }
+    nhdc_ctx *ctx = new (std::nothrow) nhdc_ctx;
+    if (!ctx) return NHDC_ENOMEM;
+    ctx->device = device;
+    ctx->precision = precision;
+    *out = ctx;
+    return NHDC_OK;
+}
+
+int nhdc_upload_grid(nhdc_ctx *ctx, const nhdc_grid *g, const nhdc_vertical *v,
+                     const nhdc_params *prm) {
+    if (!ctx) return NHDC_EINVAL;
+    if (!g || !v || !prm) return set_err(ctx, NHDC_EINVAL, "upload_grid: NULL argument");
+    if (ctx->grid_ready) return set_err(ctx, NHDC_ESTATE, "upload_grid: grid already uploaded");
+    const void *need[] = {g->cell_edges, g->cell_sign, g->edge_cells, g->edge_verts, g->vert_edges,
+                          g->vert_cells, g->vert_sign, g->vert_valence, g->cell_x, g->cell_area,
+                          g->edge_x, g->edge_tangent, g->edge_length, g->dual_length,
+                          g->vert_area, v->zh, v->pi_ref, v->theta_ref};
+    for (const void *q : need)
+        if (!q) return set_err(ctx, NHDC_EINVAL, "upload_grid: NULL array");
+    if (!(prm->beta >= 0.5 && prm->beta <= 1.0) || !(prm->cpd > prm->rd && prm->rd > 0) ||
+        !(prm->grav > 0) || !std::isfinite(prm->omega) || !std::isfinite(prm->extrap) ||
+        !std::isfinite(prm->wgt_corr) || !std::isfinite(prm->div_damp))
+        return set_err(ctx, NHDC_EINVAL, "upload_grid: bad parameters");
+    int rc = validate(ctx, g, v);
+    if (rc) return rc;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+
+    const int64_t nc = g->n_cells, ne = g->n_edges, nv = g->n_verts;
+    const int N = v->n_lev;
+    const double a = g->radius;
+    Grid &G = ctx->g;
+    G.nc = nc;
+    G.ne = ne;
+    G.nv = nv;
+    G.N = N;
+    G.radius = a;
+    G.abar = 4.0 * 3.14159265358979323846 * a * a / double(nc);
+    ctx->p = Params{prm->omega, prm->grav, prm->rd, prm->cpd, prm->p00, prm->beta,
+                    prm->wgt_corr, prm->extrap, prm->div_damp};
+
+    // ---- stencil coefficients on the host (each formed exactly as the
+    // operators form it, so device sums see the same operands) ----
+    std::vector<double> c_sl(3 * nc), c_dv(9 * nc), v_sd(6 * nv), v_m(6 * nv), v_val(nv), fe(ne);
+    std::vector<int32_t> v_e(6 * nv), v_c(6 * nv);
+    for (int64_t c = 0; c < nc; ++c) {
+        const double xc[3] = {g->cell_x[c], g->cell_x[nc + c], g->cell_x[2 * nc + c]};
+        for (int j = 0; j < 3; ++j) {
+            int64_t e = g->cell_edges[j * nc + c];
+            c_sl[j * nc + c] = g->cell_sign[j * nc + c] * g->edge_length[e];
+            for (int q = 0; q < 3; ++q) c_dv[(3 * j + q) * nc + c] = a * (g->edge_x[q * ne + e] - xc[q]);
+        }
+    }
+    for (int64_t vtx = 0; vtx < nv; ++vtx) {
+        int val = g->vert_valence[vtx];
+        v_val[vtx] = double(val);
+        for (int j = 0; j < 6; ++j) {
+            bool real = j < val;
+            int64_t e = real ? g->vert_edges[j * nv + vtx] : g->vert_edges[vtx];
+            int64_t c = real ? g->vert_cells[j * nv + vtx] : g->vert_cells[vtx];
+            v_e[j * nv + vtx] = int32_t(e);
+            v_c[j * nv + vtx] = int32_t(c);
+            v_sd[j * nv + vtx] = real ? g->vert_sign[j * nv + vtx] * g->dual_length[e] : 0.0;
+            v_m[j * nv + vtx] = real ? 1.0 : 0.0;
+        }
+    }
+    for (int64_t e = 0; e < ne; ++e) fe[e] = 2.0 * prm->omega * g->edge_x[2 * ne + e];
+    if ((rc = upload(ctx, &G.c_e, g->cell_edges, 3 * nc))) return rc;
+    if ((rc = upload(ctx, &G.e_c, g->edge_cells, 2 * ne))) return rc;
+    if ((rc = upload(ctx, &G.e_v, g->edge_verts, 2 * ne))) return rc;
+    if ((rc = upload(ctx, &G.v_e, v_e.data(), 6 * nv))) return rc;
+    if ((rc = upload(ctx, &G.v_c, v_c.data(), 6 * nv))) return rc;
+    if ((rc = upload(ctx, &G.c_sl, c_sl.data(), 3 * nc))) return rc;
+    if ((rc = upload(ctx, &G.c_area, g->cell_area, nc))) return rc;
+    if ((rc = upload(ctx, &G.c_x, g->cell_x, 3 * nc))) return rc;
+    if ((rc = upload(ctx, &G.c_dv, c_dv.data(), 9 * nc))) return rc;
+    if ((rc = upload(ctx, &G.e_de, g->dual_length, ne))) return rc;
+    if ((rc = upload(ctx, &G.e_le, g->edge_length, ne))) return rc;
+    if ((rc = upload(ctx, &G.e_t, g->edge_tangent, 3 * ne))) return rc;
+    if ((rc = upload(ctx, &G.fe, fe.data(), ne))) return rc;
+    if ((rc = upload(ctx, &G.v_sd, v_sd.data(), 6 * nv))) return rc;
+    if ((rc = upload(ctx, &G.v_m, v_m.data(), 6 * nv))) return rc;
+    if ((rc = upload(ctx, &G.v_val, v_val.data(), nv))) return rc;
+    if ((rc = upload(ctx, &G.v_area, g->vert_area, nv))) return rc;
+    const int64_t NC = int64_t(N) * nc, NC1 = int64_t(N + 1) * nc, NE = int64_t(N) * ne;
+    const int64_t NV = int64_t(N) * nv, NV1 = int64_t(N + 1) * nv;
+    if ((rc = upload(ctx, &G.zh, v->zh, NC1))) return rc;
+    if ((rc = upload(ctx, &G.pi_ref, v->pi_ref, NC))) return rc;
+    if ((rc = upload(ctx, &G.theta_ref, v->theta_ref, NC))) return rc;
+    if ((rc = dalloc(ctx, &G.gw, NC1))) return rc;
+    if ((rc = dalloc(ctx, &G.dref, NC1))) return rc;
+    if ((rc = dalloc(ctx, &G.zhv, NV1))) return rc;
+
+    // ---- state, accumulators and work arrays ----
+    State &S = ctx->s;
+    Work &W = ctx->w;
+    double **cellsN[] = {&S.rho, &S.pi, &S.thv, &S.pi_prev, &W.kc, &W.dvn, &W.rhos, &W.thvs,
+                         &W.rh, &W.ph};
+    double **cellsN1[] = {&S.w, &S.wacc, &W.wcc0, &W.tw0, &W.wcc1, &W.tw1, &W.ws, &W.cp, &W.dp};
+    double **edgesN[] = {&S.vn, &S.facc, &W.vt, &W.tvn0, &W.gp, &W.vns, &W.flx, &W.hfl};
+    for (auto q : cellsN)
+        if ((rc = dalloc(ctx, q, NC))) return rc;
+    for (auto q : cellsN1)
+        if ((rc = dalloc(ctx, q, NC1))) return rc;
+    for (auto q : edgesN)
+        if ((rc = dalloc(ctx, q, NE))) return rc;
+    if ((rc = dalloc(ctx, &W.zeta, NV))) return rc;
+    if ((rc = dalloc(ctx, &W.wv, NV1))) return rc;
+    if ((rc = dalloc(ctx, &W.red, 2 * ((nc + 255) / 256) + 2))) return rc;
+    if ((rc = dalloc(ctx, &W.flag, 1))) return rc;
+    HIP_TRY(ctx, hipMemset(W.wv, 0, sizeof(double) * NV1));
+    HIP_TRY(ctx, launch_metrics(G, ctx->p, nullptr));
+    HIP_TRY(ctx, hipDeviceSynchronize());
+    ctx->grid_ready = true;
+    return NHDC_OK;
+}
+
+int nhdc_init_state(nhdc_ctx *ctx, const nhdc_state_view *st, void *stream) {
+    if (!ctx) return NHDC_EINVAL;
+    if (!st) return set_err(ctx, NHDC_EINVAL, "init_state: NULL state");
+    if (!ctx->grid_ready) return set_err(ctx, NHDC_ESTATE, "init_state: no grid uploaded");
+    if (!st->vn || !st->w || !st->rho || !st->pi || !st->theta_v)
+        return set_err(ctx, NHDC_EINVAL, "init_state: NULL field");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Grid &G = ctx->g;
+    const size_t NC = size_t(G.N) * G.nc * 8, NC1 = size_t(G.N + 1) * G.nc * 8,
+                 NE = size_t(G.N) * G.ne * 8;
+    hipMemcpyKind kind = st->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->s.vn, st->vn, NE, kind, s));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->s.w, st->w, NC1, kind, s));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->s.rho, st->rho, NC, kind, s));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->s.pi, st->pi, NC, kind, s));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->s.thv, st->theta_v, NC, kind, s));
+    if (st->pi_prev) HIP_TRY(ctx, hipMemcpyAsync(ctx->s.pi_prev, st->pi_prev, NC, kind, s));
+    else HIP_TRY(ctx, launch_init_prev(ctx, s));
+    HIP_TRY(ctx, hipMemsetAsync(ctx->s.facc, 0, NE, s));
+    HIP_TRY(ctx, hipMemsetAsync(ctx->s.wacc, 0, NC1, s));
+    if (!st->on_device) HIP_TRY(ctx, hipStreamSynchronize(s));
+    ctx->state_ready = true;
+    return NHDC_OK;
+}
+
+int nhdc_step(nhdc_ctx *ctx, double dt, int nsub, void *stream) {
+    if (!ctx) return NHDC_EINVAL;
+    if (!(dt > 0) || !std::isfinite(dt)) return set_err(ctx, NHDC_EINVAL, "step: dt must be positive and finite");
+    if (nsub < 1) return set_err(ctx, NHDC_EINVAL, "step: nsubsteps must be >= 1");
+    if (!ctx->state_ready) return set_err(ctx, NHDC_ESTATE, "step: state not initialised");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const double dts = dt / nsub;
+    ctx->tm.ids.clear();
+    for (int i = 0; i < nsub; ++i) HIP_TRY(ctx, launch_substep(ctx, dts, nsub, i == 0, s));
+    return timing_collect(ctx, s);
+}
+
+int nhdc_set_timing(nhdc_ctx *ctx, int enable) {
+    if (!ctx) return NHDC_EINVAL;
+    ctx->tm.on = enable != 0;
+    ctx->tm.ids.clear();
+    for (int k = 0; k < K_NUM; ++k) {
+        ctx->tm.total_ms[k] = 0.0;
+        ctx->tm.launches[k] = 0;
+    }
+    return NHDC_OK;
+}
+
+int nhdc_kernel_count(void) { return K_NUM; }
+
+int nhdc_kernel_stats(const nhdc_ctx *ctx, int index, const char **name, double *total_ms,
+                      int64_t *launches) {
+    if (!ctx || index < 0 || index >= K_NUM) return NHDC_EINVAL;
+    if (name) *name = kKernelNames[index];
+    if (total_ms) *total_ms = ctx->tm.total_ms[index];
+    if (launches) *launches = ctx->tm.launches[index];
+    return NHDC_OK;
+}
+
+int nhdc_get_state(nhdc_ctx *ctx, const nhdc_state_view *dst, void *stream) {
+    if (!ctx) return NHDC_EINVAL;
+    if (!dst) return set_err(ctx, NHDC_EINVAL, "get_state: NULL view");
+    if (!ctx->state_ready) return set_err(ctx, NHDC_ESTATE, "get_state: state not initialised");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Grid &G = ctx->g;
+    const size_t NC = size_t(G.N) * G.nc * 8, NC1 = size_t(G.N + 1) * G.nc * 8,
+                 NE = size_t(G.N) * G.ne * 8;
+    hipMemcpyKind kind = dst->on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (dst->vn) HIP_TRY(ctx, hipMemcpyAsync(dst->vn, ctx->s.vn, NE, kind, s));
+    if (dst->w) HIP_TRY(ctx, hipMemcpyAsync(dst->w, ctx->s.w, NC1, kind, s));
+    if (dst->rho) HIP_TRY(ctx, hipMemcpyAsync(dst->rho, ctx->s.rho, NC, kind, s));
+    if (dst->pi) HIP_TRY(ctx, hipMemcpyAsync(dst->pi, ctx->s.pi, NC, kind, s));
+    if (dst->theta_v) HIP_TRY(ctx, hipMemcpyAsync(dst->theta_v, ctx->s.thv, NC, kind, s));
+    if (dst->pi_prev) HIP_TRY(ctx, hipMemcpyAsync(dst->pi_prev, ctx->s.pi_prev, NC, kind, s));
+    if (!dst->on_device) HIP_TRY(ctx, hipStreamSynchronize(s));
+    return NHDC_OK;
+}
+
+int nhdc_get_mass_flux(nhdc_ctx *ctx, double *facc, double *wacc, int on_device, void *stream) {
+    if (!ctx) return NHDC_EINVAL;
+    if (!ctx->state_ready) return set_err(ctx, NHDC_ESTATE, "get_mass_flux: state not initialised");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Grid &G = ctx->g;
+    hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (facc) HIP_TRY(ctx, hipMemcpyAsync(facc, ctx->s.facc, size_t(G.N) * G.ne * 8, kind, s));
+    if (wacc) HIP_TRY(ctx, hipMemcpyAsync(wacc, ctx->s.wacc, size_t(G.N + 1) * G.nc * 8, kind, s));
+    if (!on_device) HIP_TRY(ctx, hipStreamSynchronize(s));
+    return NHDC_OK;
+}
+
+int nhdc_diag(nhdc_ctx *ctx, double *mass, double *rho_theta, void *stream) {
+    if (!ctx) return NHDC_EINVAL;
+    if (!ctx->state_ready) return set_err(ctx, NHDC_ESTATE, "diag: state not initialised");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double *out = ctx->w.red + 2 * ((ctx->g.nc + 255) / 256);
+    HIP_TRY(ctx, launch_diag(ctx, out, s));
+    double h[2];
+    HIP_TRY(ctx, hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    if (mass) *mass = h[0];
+    if (rho_theta) *rho_theta = h[1];
+    return NHDC_OK;
+}
+
+int nhdc_check_finite(nhdc_ctx *ctx, void *stream) {
+    if (!ctx) return NHDC_EINVAL;
+    if (!ctx->state_ready) return set_err(ctx, NHDC_ESTATE, "check_finite: state not initialised");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(ctx, hipMemsetAsync(ctx->w.flag, 0, sizeof(int), s));
+    HIP_TRY(ctx, launch_finite(ctx, ctx->w.flag, s));
+    int h = 0;
+    HIP_TRY(ctx, hipMemcpyAsync(&h, ctx->w.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    if (h) return set_err(ctx, NHDC_EUNSTABLE, "check_finite: non-finite value in the state");
+    return NHDC_OK;
+}
+
+int nhdc_sizes(const nhdc_ctx *ctx, int64_t *n_cells, int64_t *n_edges, int64_t *n_verts,
+               int32_t *n_lev) {
+    if (!ctx || !ctx->grid_ready) return NHDC_ESTATE;
+    if (n_cells) *n_cells = ctx->g.nc;
+    if (n_edges) *n_edges = ctx->g.ne;
+    if (n_verts) *n_verts = ctx->g.nv;
+    if (n_lev) *n_lev = ctx->g.N;
+    return NHDC_OK;
+}
+
+const char *nhdc_last_error(const nhdc_ctx *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+void nhdc_destroy(nhdc_ctx *ctx) {
+    if (!ctx) return;
+    if (hipSetDevice(ctx->device) == hipSuccess) {
+        for (hipEvent_t e : ctx->tm.ev) (void)hipEventDestroy(e);
+        for (void *q : ctx->allocs) (void)hipFree(q);
+    }
+    delete ctx;
+}
+
+}  // extern "C"

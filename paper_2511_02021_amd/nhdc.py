@@ -1,0 +1,257 @@
+"""Python binding of libnhdc (include/nhdc.h): argument marshalling only.
+
+Every step of the dynamical core runs in the library's HIP kernels; PyTorch
+is used for device memory (tensors handed over by pointer) and for the HIP
+stream on which work is enqueued.  There is no CPU fallback: if libnhdc.so is
+missing or fails to load, the import of the library raises.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import _build
+
+NHDC_FP64, NHDC_MIXED = 0, 1
+PRECISIONS = {"fp64": NHDC_FP64, "mixed": NHDC_MIXED}
+ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EGRID", -5: "ESTATE", -6: "EUNSTABLE"}
+
+EXPORTS = ("nhdc_create", "nhdc_upload_grid", "nhdc_init_state", "nhdc_step", "nhdc_get_state",
+           "nhdc_get_mass_flux", "nhdc_diag", "nhdc_check_finite", "nhdc_sizes",
+           "nhdc_set_timing", "nhdc_kernel_count", "nhdc_kernel_stats", "nhdc_last_error",
+           "nhdc_destroy")
+
+
+class NhdcError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Grid(C.Structure):
+    _fields_ = [("n_cells", C.c_int64), ("n_edges", C.c_int64), ("n_verts", C.c_int64),
+                ("radius", C.c_double)] + [(n, C.c_void_p) for n in (
+                    "cell_edges", "cell_sign", "edge_cells", "edge_verts", "vert_edges",
+                    "vert_cells", "vert_sign", "vert_valence", "cell_x", "cell_area", "edge_x",
+                    "edge_tangent", "edge_length", "dual_length", "vert_area")]
+
+
+class _Vertical(C.Structure):
+    _fields_ = [("n_lev", C.c_int32), ("zh", C.c_void_p), ("pi_ref", C.c_void_p),
+                ("theta_ref", C.c_void_p)]
+
+
+class _Params(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("omega", "grav", "rd", "cpd", "p00", "beta", "wgt_corr",
+                                          "extrap", "div_damp")]
+
+
+class _State(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("vn", "w", "rho", "pi", "theta_v", "pi_prev")] + [
+        ("on_device", C.c_int32)]
+
+
+_LIB = None
+
+
+def library_path():
+    return _build.NHDC_SO
+
+
+def lib():
+    """Load libnhdc.so (building it in-tree if nothing is built yet).
+
+    torch is imported first: its HIP runtime (soname libamdhip64.so.7) is then
+    already in the process and libnhdc binds to that same runtime, so streams
+    and device pointers from torch are valid in the library.  Loading libnhdc
+    first would bring in a second copy of the runtime."""
+    global _LIB
+    if _LIB is None:
+        import torch  # noqa: F401  (HIP runtime first, see above)
+        path = _build.ensure(_build.NHDC_SO, _build.build_nhdc)
+        L = C.CDLL(path)
+        vp, i, d = C.c_void_p, C.c_int, C.c_double
+        L.nhdc_create.argtypes = [C.POINTER(vp), i, i]
+        L.nhdc_upload_grid.argtypes = [vp, vp, vp, vp]
+        L.nhdc_init_state.argtypes = [vp, vp, vp]
+        L.nhdc_step.argtypes = [vp, d, i, vp]
+        L.nhdc_get_state.argtypes = [vp, vp, vp]
+        L.nhdc_get_mass_flux.argtypes = [vp, vp, vp, i, vp]
+        L.nhdc_diag.argtypes = [vp, vp, vp, vp]
+        L.nhdc_check_finite.argtypes = [vp, vp]
+        L.nhdc_sizes.argtypes = [vp] + [vp] * 4
+        L.nhdc_set_timing.argtypes = [vp, i]
+        L.nhdc_kernel_count.argtypes = []
+        L.nhdc_kernel_stats.argtypes = [vp, i, C.POINTER(C.c_char_p), C.POINTER(d),
+                                        C.POINTER(C.c_int64)]
+        L.nhdc_last_error.argtypes = [vp]
+        L.nhdc_last_error.restype = C.c_char_p
+        L.nhdc_destroy.argtypes = [vp]
+        L.nhdc_destroy.restype = None
+        _LIB = L
+    return _LIB
+
+
+def _np_ptr(a):
+    assert isinstance(a, np.ndarray) and a.flags.c_contiguous
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+
+
+def params_struct(p):
+    return _Params(p.omega, p.grav, p.rd, p.cpd, p.p00, p.beta, p.wgt_corr, p.extrap, p.div_damp)
+
+
+class Dycore:
+    """One dynamical-core instance resident on a GPU."""
+
+    def __init__(self, case, precision="fp64", device=0, init=True):
+        self.L = lib()
+        self.case = case
+        self.grid = case.grid
+        self.N = case.n_lev
+        self.device = device
+        self.precision = precision
+        h = C.c_void_p()
+        rc = self.L.nhdc_create(C.byref(h), PRECISIONS[precision], int(device))
+        if rc != 0:
+            raise NhdcError(rc, "nhdc_create failed (no usable HIP device?)")
+        self.h = h
+        g = case.grid
+        keep = {}
+
+        def arr(name, dtype):
+            keep[name] = np.ascontiguousarray(getattr(g, name), dtype=dtype)
+            return _np_ptr(keep[name])
+
+        gs = _Grid(g.n_cells, g.n_edges, g.n_verts, g.radius,
+                   arr("cell_edges", np.int32), arr("cell_sign", np.int8),
+                   arr("edge_cells", np.int32), arr("edge_verts", np.int32),
+                   arr("vert_edges", np.int32), arr("vert_cells", np.int32),
+                   arr("vert_sign", np.int8), arr("vert_valence", np.int32),
+                   arr("cell_x", np.float64), arr("cell_area", np.float64),
+                   arr("edge_x", np.float64), arr("edge_tangent", np.float64),
+                   arr("edge_length", np.float64), arr("dual_length", np.float64),
+                   arr("vert_area", np.float64))
+        zh = np.ascontiguousarray(case.zh, dtype=np.float64)
+        pr = np.ascontiguousarray(case.pi_ref, dtype=np.float64)
+        tr = np.ascontiguousarray(case.theta_ref, dtype=np.float64)
+        vs = _Vertical(self.N, _np_ptr(zh), _np_ptr(pr), _np_ptr(tr))
+        ps = params_struct(case.params)
+        self._check(self.L.nhdc_upload_grid(self.h, C.byref(gs), C.byref(vs), C.byref(ps)))
+        if init:
+            self.init_state(case.vn, case.w, case.rho, case.pi, case.theta_v)
+
+    # -- helpers ------------------------------------------------------------
+    def _check(self, rc):
+        if rc != 0:
+            raise NhdcError(rc, self.L.nhdc_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.nhdc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    @property
+    def shapes(self):
+        nc, ne, N = self.grid.n_cells, self.grid.n_edges, self.N
+        return dict(vn=(N, ne), w=(N + 1, nc), rho=(N, nc), pi=(N, nc), theta_v=(N, nc),
+                    pi_prev=(N, nc))
+
+    # -- state ----------------------------------------------------------------
+    def init_state(self, vn, w, rho, pi, theta_v, pi_prev=None, stream=None):
+        """Host numpy arrays or device torch tensors (float64, contiguous)."""
+        fields = [vn, w, rho, pi, theta_v, pi_prev]
+        names = ["vn", "w", "rho", "pi", "theta_v", "pi_prev"]
+        on_dev = not isinstance(vn, np.ndarray)
+        keep, ptrs = [], []
+        for n, f in zip(names, fields):
+            if f is None:
+                ptrs.append(None)
+                continue
+            if on_dev:
+                assert f.is_cuda and f.dtype.is_floating_point and f.element_size() == 8
+                f = f.contiguous()
+                assert tuple(f.shape) == self.shapes[n], (n, tuple(f.shape))
+                keep.append(f)
+                ptrs.append(C.c_void_p(f.data_ptr()))
+            else:
+                a = np.ascontiguousarray(f, dtype=np.float64)
+                assert a.shape == self.shapes[n], (n, a.shape)
+                keep.append(a)
+                ptrs.append(_np_ptr(a))
+        st = _State(*ptrs, int(on_dev))
+        self._check(self.L.nhdc_init_state(self.h, C.byref(st),
+                                           _stream_ptr(stream) if on_dev else None))
+        self._keep = keep
+
+    def step(self, dt, nsub, stream=None):
+        self._check(self.L.nhdc_step(self.h, float(dt), int(nsub), _stream_ptr(stream)))
+
+    def get_state(self):
+        """Host copy of the prognostic state (numpy, float64)."""
+        out = {n: np.empty(s) for n, s in self.shapes.items()}
+        st = _State(*[_np_ptr(out[n]) for n in ("vn", "w", "rho", "pi", "theta_v", "pi_prev")], 0)
+        self._check(self.L.nhdc_get_state(self.h, C.byref(st), _stream_ptr(None)))
+        return out
+
+    def get_state_device(self, stream=None):
+        import torch
+        dev = torch.device("cuda", self.device)
+        out = {n: torch.empty(s, dtype=torch.float64, device=dev) for n, s in self.shapes.items()}
+        st = _State(*[C.c_void_p(out[n].data_ptr()) for n in
+                      ("vn", "w", "rho", "pi", "theta_v", "pi_prev")], 1)
+        self._check(self.L.nhdc_get_state(self.h, C.byref(st), _stream_ptr(stream)))
+        return out
+
+    def mass_flux(self):
+        N, nc, ne = self.N, self.grid.n_cells, self.grid.n_edges
+        facc, wacc = np.empty((N, ne)), np.empty((N + 1, nc))
+        self._check(self.L.nhdc_get_mass_flux(self.h, _np_ptr(facc), _np_ptr(wacc), 0,
+                                              _stream_ptr(None)))
+        return facc, wacc
+
+    def diag(self):
+        m, r = C.c_double(), C.c_double()
+        self._check(self.L.nhdc_diag(self.h, C.byref(m), C.byref(r), _stream_ptr(None)))
+        return m.value, r.value
+
+    def check_finite(self):
+        self._check(self.L.nhdc_check_finite(self.h, _stream_ptr(None)))
+
+    def set_timing(self, on):
+        self._check(self.L.nhdc_set_timing(self.h, int(bool(on))))
+
+    def kernel_stats(self):
+        """{kernel name: (total ms, launches)} accumulated while timing is on."""
+        out = {}
+        for k in range(self.L.nhdc_kernel_count()):
+            name, ms, n = C.c_char_p(), C.c_double(), C.c_int64()
+            self._check(self.L.nhdc_kernel_stats(self.h, k, C.byref(name), C.byref(ms), C.byref(n)))
+            out[name.value.decode()] = (ms.value, n.value)
+        return out
+
+
+def exported_symbols(path=None):
+    """Names of the nhdc_* symbols the shared library exports (no GPU needed)."""
+    import subprocess
+    path = path or _build.NHDC_SO
+    out = subprocess.run(["nm", "-D", "--defined-only", path], capture_output=True, text=True,
+                         check=True).stdout
+    return sorted({ln.split()[-1] for ln in out.splitlines() if " T nhdc_" in ln})
+
+
+def header_symbols():
+    """Function names declared in include/nhdc.h."""
+    import re
+    src = open(os.path.join(_build.INCLUDE, "nhdc.h")).read()
+    return sorted(set(re.findall(r"\b(nhdc_[a-z_]+)\s*\(", src)))
