@@ -18,6 +18,8 @@ struct Grid {
     int N = 0;
     double radius = 0, abar = 0;     // mean cell area 4 pi a^2 / nc
     int32_t *c_e = nullptr;          // [3][nc] cell -> edges
+    int32_t *c_n = nullptr;          // [3][nc] neighbour across edge slot j
+    int32_t *c_v = nullptr;          // [3][nc] vertex slot j (edge slot j joins vertex slots j, j+1)
     int32_t *e_c = nullptr;          // [2][ne] edge -> c1, c2
     int32_t *e_v = nullptr;          // [2][ne] edge -> v1, v2
     int32_t *v_e = nullptr;          // [6][nv] vertex ring edges (pad -> slot 0)

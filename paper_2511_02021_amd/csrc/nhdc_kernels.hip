@@ -184,7 +184,9 @@ __global__ void __launch_bounds__(BLOCK) k_vertex(Grid g, const double *__restri
 }
 
 // Cell part of the tendencies: kinetic energy K_c, contravariant correction
-// w_cc, w tendency T_w and (optionally) the divergence of vn.
+// w_cc, w tendency T_w and (optionally) the divergence of vn.  The cell, its
+// three neighbours and its three vertices are each gathered once per level;
+// the own column's w and zh are carried in registers (levels i-1, i, i+1).
 template <bool WANT_DIV>
 __global__ void __launch_bounds__(BLOCK) k_cell_vt(Grid g, const double *__restrict__ vn,
                                                    const double *__restrict__ vt,
@@ -198,21 +200,23 @@ __global__ void __launch_bounds__(BLOCK) k_cell_vt(Grid g, const double *__restr
     const int64_t nc = g.nc, ne = g.ne, nv = g.nv;
     const int N = g.N;
     if (c >= nc) return;
-    int32_t e[3], c1[3], c2[3], v1[3], v2[3];
+    int32_t e[3], nb[3], vx[3];
+    bool out[3];
     double de[3], le[3], sl[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
         e[j] = g.c_e[j * nc + c];
-        c1[j] = g.e_c[e[j]];
-        c2[j] = g.e_c[ne + e[j]];
-        v1[j] = g.e_v[e[j]];
-        v2[j] = g.e_v[ne + e[j]];
+        nb[j] = g.c_n[j * nc + c];
+        vx[j] = g.c_v[j * nc + c];
+        sl[j] = g.c_sl[j * nc + c];
+        out[j] = sl[j] > 0.0;
         de[j] = g.e_de[e[j]];
         le[j] = g.e_le[e[j]];
-        sl[j] = g.c_sl[j * nc + c];
     }
     const double area = g.c_area[c];
     double vnp[3] = {0.0, 0.0, 0.0}, vtp[3] = {0.0, 0.0, 0.0};  // full level i-1
+    double w_m = 0.0, w_0 = w[c], w_p = w[nc + c];               // own w at i-1, i, i+1
+    double z_m = 0.0, z_0 = g.zh[c], z_p = g.zh[nc + c];         // own zh at i-1, i, i+1
     wcc[c] = 0.0;
     tw[c] = 0.0;
     for (int i = 0; i <= N; ++i) {
@@ -230,41 +234,58 @@ __global__ void __launch_bounds__(BLOCK) k_cell_vt(Grid g, const double *__restr
             if (WANT_DIV) dvn[int64_t(i) * nc + c] = ds / area;
         }
         if (i > 0) {
-            const double *zhi = g.zh + int64_t(i) * nc;
-            const double *zvi = g.zhv + int64_t(i) * nv;
+            const bool interior = i < N;
+            const int64_t oc = int64_t(i) * nc, ov = int64_t(i) * nv;
+            double zn[3], zv[3], gwn[3] = {0.0, 0.0, 0.0}, wnb[3] = {0.0, 0.0, 0.0},
+                   wvv[3] = {0.0, 0.0, 0.0};
+            double gwc = interior ? g.gw[oc + c] : 0.0;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                zn[j] = g.zh[oc + nb[j]];
+                zv[j] = g.zhv[ov + vx[j]];
+                if (interior) {
+                    gwn[j] = g.gw[oc + nb[j]];
+                    wnb[j] = w[oc + nb[j]];
+                    wvv[j] = wv[ov + vx[j]];
+                }
+            }
             double ccs = 0.0, adv = 0.0;
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
+                const int jn = j == 2 ? 0 : j + 1;
+                // edge j runs from vertex slot j to j+1: (v1, v2) in that order when
+                // its normal points out of this cell, reversed otherwise
+                double zc1 = out[j] ? z_0 : zn[j], zc2 = out[j] ? zn[j] : z_0;
+                double zv1 = out[j] ? zv[j] : zv[jn], zv2 = out[j] ? zv[jn] : zv[j];
                 double hn, ht;
-                if (i < N) {
-                    double gg = 0.5 * (g.gw[int64_t(i) * nc + c1[j]] + g.gw[int64_t(i) * nc + c2[j]]);
+                if (interior) {
+                    double gg = 0.5 * (out[j] ? gwc + gwn[j] : gwn[j] + gwc);
                     hn = gg * vni[j] + (1.0 - gg) * vnp[j];
                     ht = gg * vti[j] + (1.0 - gg) * vtp[j];
                 } else {
                     hn = vnp[j];
                     ht = vtp[j];
                 }
-                double snh = (zhi[c2[j]] - zhi[c1[j]]) / de[j];
-                double sth = (zvi[v2[j]] - zvi[v1[j]]) / le[j];
+                double snh = (zc2 - zc1) / de[j];
+                double sth = (zv2 - zv1) / le[j];
                 ccs += hn * snh + ht * sth;
-                if (i < N) {
-                    const double *wi = w + int64_t(i) * nc;
-                    const double *wvi = wv + int64_t(i) * nv;
-                    double gw_ = (wi[c2[j]] - wi[c1[j]]) / de[j];
-                    double tw_ = (wvi[v2[j]] - wvi[v1[j]]) / le[j];
+                if (interior) {
+                    double wc1 = out[j] ? w_0 : wnb[j], wc2 = out[j] ? wnb[j] : w_0;
+                    double wv1 = out[j] ? wvv[j] : wvv[jn], wv2 = out[j] ? wvv[jn] : wvv[j];
+                    double gw_ = (wc2 - wc1) / de[j];
+                    double tw_ = (wv2 - wv1) / le[j];
                     adv += hn * gw_ + ht * tw_;
                 }
             }
             double wcci = ccs / 3.0;
-            wcc[int64_t(i) * nc + c] = wcci;
-            if (i < N) {
+            wcc[oc + c] = wcci;
+            if (interior) {
                 double hadv = adv / 3.0;
-                double om = w[int64_t(i) * nc + c] - wcci;
-                double dwdz = (w[int64_t(i - 1) * nc + c] - w[int64_t(i + 1) * nc + c]) /
-                              (g.zh[int64_t(i - 1) * nc + c] - g.zh[int64_t(i + 1) * nc + c]);
-                tw[int64_t(i) * nc + c] = -hadv - om * dwdz;
+                double om = w_0 - wcci;
+                double dwdz = (w_m - w_p) / (z_m - z_p);
+                tw[oc + c] = -hadv - om * dwdz;
             } else {
-                tw[int64_t(i) * nc + c] = 0.0;
+                tw[oc + c] = 0.0;
             }
         }
         if (i < N) {
@@ -274,44 +295,22 @@ __global__ void __launch_bounds__(BLOCK) k_cell_vt(Grid g, const double *__restr
                 vtp[j] = vti[j];
             }
         }
+        w_m = w_0;
+        w_0 = w_p;
+        z_m = z_0;
+        z_0 = z_p;
+        if (i + 2 <= N) {
+            w_p = w[int64_t(i + 2) * nc + c];
+            z_p = g.zh[int64_t(i + 2) * nc + c];
+        }
     }
 }
 
-// Per-edge constants shared by the two edge kernels.
-struct EdgeCtx {
-    int32_t c1, c2, v1, v2;
-    double de, fe;
-};
-
-__device__ __forceinline__ double omega_at(const double *w, const double *wcc, int i, int N,
-                                           int64_t nc, int32_t c) {
-    if (i <= 0 || i >= N) return 0.0;
-    return w[int64_t(i) * nc + c] - wcc[int64_t(i) * nc + c];
-}
-
-// vn tendency at (edge, level k); vnh_k / vnh_k1 are vn at half levels k and k+1.
-__device__ __forceinline__ double vn_tendency(const Grid &g, const EdgeCtx &ec, int k,
-                                              const double *kc, const double *zeta,
-                                              double vtk, const double *w, const double *wcc,
-                                              double vnh_k, double vnh_k1, double dze) {
-    const int64_t nc = g.nc, nv = g.nv;
-    const int N = g.N;
-    double gradk = (kc[int64_t(k) * nc + ec.c2] - kc[int64_t(k) * nc + ec.c1]) / ec.de;
-    double ze = 0.5 * (zeta[int64_t(k) * nv + ec.v1] + zeta[int64_t(k) * nv + ec.v2]);
-    double of1 = 0.5 * (omega_at(w, wcc, k, N, nc, ec.c1) + omega_at(w, wcc, k + 1, N, nc, ec.c1));
-    double of2 = 0.5 * (omega_at(w, wcc, k, N, nc, ec.c2) + omega_at(w, wcc, k + 1, N, nc, ec.c2));
-    double obar = 0.5 * (of1 + of2);
-    double dvdz = (vnh_k - vnh_k1) / dze;
-    return -gradk + (ze + ec.fe) * vtk - obar * dvdz;
-}
-
-// value at half level i from full levels i (below) and i-1 (above), edge weight
-__device__ __forceinline__ double half_interp(const Grid &g, const EdgeCtx &ec, int i,
-                                              double below, double above) {
-    const int64_t nc = g.nc;
-    double gg = 0.5 * (g.gw[int64_t(i) * nc + ec.c1] + g.gw[int64_t(i) * nc + ec.c2]);
-    return gg * below + (1.0 - gg) * above;
-}
+// Edge kernels march one edge down its column.  Per level they gather each
+// cell field at c1 and c2 once; values needed at adjacent levels (the Exner
+// perturbation and heights for the vertical derivative, interpolation
+// weights, contravariant velocity at the two half levels) are carried in
+// registers from the previous level.
 
 __device__ __forceinline__ double exner_x(const Grid &g, const State &s, double eps, int k,
                                           int32_t c) {
@@ -320,50 +319,69 @@ __device__ __forceinline__ double exner_x(const Grid &g, const State &s, double 
     return (1.0 + eps) * pp - eps * s.pi_prev[o];
 }
 
-__device__ __forceinline__ double dpz_at(const Grid &g, const State &s, double eps, int k,
-                                         int32_t c) {
-    const int N = g.N;
-    const int64_t nc = g.nc;
-    int ka = k == 0 ? 0 : k - 1, kb = k == N - 1 ? N - 1 : k + 1;
-    double za = 0.5 * (g.zh[int64_t(ka) * nc + c] + g.zh[int64_t(ka + 1) * nc + c]);
-    double zb = 0.5 * (g.zh[int64_t(kb) * nc + c] + g.zh[int64_t(kb + 1) * nc + c]);
-    return (exner_x(g, s, eps, ka, c) - exner_x(g, s, eps, kb, c)) / (za - zb);
-}
-
-__device__ __forceinline__ double edge_dz(const Grid &g, const EdgeCtx &ec, int k) {
-    const int64_t nc = g.nc;
-    double dz1 = g.zh[int64_t(k) * nc + ec.c1] - g.zh[int64_t(k + 1) * nc + ec.c1];
-    double dz2 = g.zh[int64_t(k) * nc + ec.c2] - g.zh[int64_t(k + 1) * nc + ec.c2];
-    return 0.5 * (dz1 + dz2);
-}
-
 // Predictor on edges: vn tendency of state n, terrain-corrected gradient of
 // the extrapolated Exner perturbation, predicted vn, mass and theta fluxes.
 __global__ void __launch_bounds__(BLOCK) k_edge_pred(Grid g, State s, Work wk, Params p,
                                                      double dt) {
     int64_t e = gid();
-    const int64_t ne = g.ne, nc = g.nc;
+    const int64_t ne = g.ne, nc = g.nc, nv = g.nv;
     const int N = g.N;
     if (e >= ne) return;
-    EdgeCtx ec{g.e_c[e], g.e_c[ne + e], g.e_v[e], g.e_v[ne + e], g.e_de[e], g.fe[e]};
-    double vnm = 0.0, vn0 = s.vn[e];  // levels k-1, k
+    const int32_t c1 = g.e_c[e], c2 = g.e_c[ne + e], v1 = g.e_v[e], v2 = g.e_v[ne + e];
+    const double de = g.e_de[e], fe = g.fe[e], eps = p.extrap;
+    // heights zh at k, k+1, k+2; Exner perturbation and full-level heights at k-1, k, k+1
+    double h1_0 = g.zh[c1], h1_1 = g.zh[nc + c1], h1_2 = g.zh[2 * nc + c1];
+    double h2_0 = g.zh[c2], h2_1 = g.zh[nc + c2], h2_2 = g.zh[2 * nc + c2];
+    double p1_m = 0.0, p1_0 = exner_x(g, s, eps, 0, c1), p1_p = exner_x(g, s, eps, 1, c1);
+    double p2_m = 0.0, p2_0 = exner_x(g, s, eps, 0, c2), p2_p = exner_x(g, s, eps, 1, c2);
+    double z1_m = 0.0, z1_0 = 0.5 * (h1_0 + h1_1), z1_p = 0.5 * (h1_1 + h1_2);
+    double z2_m = 0.0, z2_0 = 0.5 * (h2_0 + h2_1), z2_p = 0.5 * (h2_1 + h2_2);
+    double gk1 = 0.0, gk2 = 0.0;   // interpolation weights at half level k
+    double om1 = 0.0, om2 = 0.0;   // contravariant vertical velocity at half level k
+    double vnm = 0.0, vn0 = s.vn[e];
     for (int k = 0; k < N; ++k) {
-        const int64_t o = int64_t(k) * ne + e;
-        double vn1 = k + 1 < N ? s.vn[o + ne] : vn0;
-        double vnh_k = k == 0 ? vn0 : half_interp(g, ec, k, vn0, vnm);
-        double vnh_k1 = k + 1 == N ? vn0 : half_interp(g, ec, k + 1, vn1, vn0);
-        double dze = edge_dz(g, ec, k);
-        double tvn = vn_tendency(g, ec, k, wk.kc, wk.zeta, wk.vt[o], s.w, wk.wcc0, vnh_k, vnh_k1, dze);
-        double px1 = exner_x(g, s, p.extrap, k, ec.c1), px2 = exner_x(g, s, p.extrap, k, ec.c2);
-        double dpz1 = dpz_at(g, s, p.extrap, k, ec.c1), dpz2 = dpz_at(g, s, p.extrap, k, ec.c2);
-        double z1 = 0.5 * (g.zh[int64_t(k) * nc + ec.c1] + g.zh[int64_t(k + 1) * nc + ec.c1]);
-        double z2 = 0.5 * (g.zh[int64_t(k) * nc + ec.c2] + g.zh[int64_t(k + 1) * nc + ec.c2]);
-        double sn = (z2 - z1) / ec.de;
-        double gl = (px2 - px1) / ec.de;
-        double dz2 = 0.5 * (dpz1 + dpz2);
-        double gp = gl - sn * dz2;
-        double the = 0.5 * (s.thv[int64_t(k) * nc + ec.c1] + s.thv[int64_t(k) * nc + ec.c2]);
-        double rhe = 0.5 * (s.rho[int64_t(k) * nc + ec.c1] + s.rho[int64_t(k) * nc + ec.c2]);
+        const int64_t o = int64_t(k) * ne + e, oc = int64_t(k) * nc, ov = int64_t(k) * nv;
+        const bool last = k + 1 == N;
+        double vn1 = vn0, gb1 = 0.0, gb2 = 0.0, omb1 = 0.0, omb2 = 0.0;
+        if (!last) {
+            const int64_t ob = oc + nc;
+            vn1 = s.vn[o + ne];
+            gb1 = g.gw[ob + c1];
+            gb2 = g.gw[ob + c2];
+            omb1 = s.w[ob + c1] - wk.wcc0[ob + c1];
+            omb2 = s.w[ob + c2] - wk.wcc0[ob + c2];
+        }
+        double vnh_k = vn0, vnh_k1 = vn0;
+        if (k > 0) {
+            double gg = 0.5 * (gk1 + gk2);
+            vnh_k = gg * vn0 + (1.0 - gg) * vnm;
+        }
+        if (!last) {
+            double gg = 0.5 * (gb1 + gb2);
+            vnh_k1 = gg * vn1 + (1.0 - gg) * vn0;
+        }
+        double dz1 = h1_0 - h1_1, dz2 = h2_0 - h2_1;
+        double dze = 0.5 * (dz1 + dz2);
+        double gradk = (wk.kc[oc + c2] - wk.kc[oc + c1]) / de;
+        double ze = 0.5 * (wk.zeta[ov + v1] + wk.zeta[ov + v2]);
+        double of1 = 0.5 * (om1 + omb1);
+        double of2 = 0.5 * (om2 + omb2);
+        double obar = 0.5 * (of1 + of2);
+        double dvdz = (vnh_k - vnh_k1) / dze;
+        double tvn = -gradk + (ze + fe) * wk.vt[o] - obar * dvdz;
+        // vertical derivative of the extrapolated perturbation, one-sided at the ends
+        double pa1 = k == 0 ? p1_0 : p1_m, pb1 = last ? p1_0 : p1_p;
+        double za1 = k == 0 ? z1_0 : z1_m, zb1 = last ? z1_0 : z1_p;
+        double pa2 = k == 0 ? p2_0 : p2_m, pb2 = last ? p2_0 : p2_p;
+        double za2 = k == 0 ? z2_0 : z2_m, zb2 = last ? z2_0 : z2_p;
+        double dpz1 = (pa1 - pb1) / (za1 - zb1);
+        double dpz2 = (pa2 - pb2) / (za2 - zb2);
+        double sn = (z2_0 - z1_0) / de;
+        double gl = (p2_0 - p1_0) / de;
+        double dzp = 0.5 * (dpz1 + dpz2);
+        double gp = gl - sn * dzp;
+        double the = 0.5 * (s.thv[oc + c1] + s.thv[oc + c2]);
+        double rhe = 0.5 * (s.rho[oc + c1] + s.rho[oc + c2]);
         double vns = vn0 + dt * (tvn - p.cpd * the * gp);
         double f = rhe * vns * dze;
         wk.tvn0[o] = tvn;
@@ -371,8 +389,33 @@ __global__ void __launch_bounds__(BLOCK) k_edge_pred(Grid g, State s, Work wk, P
         wk.vns[o] = vns;
         wk.flx[o] = f;
         wk.hfl[o] = the * f;
+        // shift the level windows
         vnm = vn0;
         vn0 = vn1;
+        gk1 = gb1;
+        gk2 = gb2;
+        om1 = omb1;
+        om2 = omb2;
+        p1_m = p1_0;
+        p1_0 = p1_p;
+        p2_m = p2_0;
+        p2_0 = p2_p;
+        z1_m = z1_0;
+        z1_0 = z1_p;
+        z2_m = z2_0;
+        z2_0 = z2_p;
+        h1_0 = h1_1;
+        h1_1 = h1_2;
+        h2_0 = h2_1;
+        h2_1 = h2_2;
+        if (k + 2 < N) {
+            p1_p = exner_x(g, s, eps, k + 2, c1);
+            p2_p = exner_x(g, s, eps, k + 2, c2);
+            h1_2 = g.zh[int64_t(k + 3) * nc + c1];
+            h2_2 = g.zh[int64_t(k + 3) * nc + c2];
+            z1_p = 0.5 * (h1_1 + h1_2);
+            z2_p = 0.5 * (h2_1 + h2_2);
+        }
     }
 }
 
@@ -382,26 +425,53 @@ __global__ void __launch_bounds__(BLOCK) k_edge_pred(Grid g, State s, Work wk, P
 __global__ void __launch_bounds__(BLOCK) k_edge_corr(Grid g, State s, Work wk, Params p, double dt,
                                                      int nsub, int first) {
     int64_t e = gid();
-    const int64_t ne = g.ne, nc = g.nc;
+    const int64_t ne = g.ne, nc = g.nc, nv = g.nv;
     const int N = g.N;
     if (e >= ne) return;
-    EdgeCtx ec{g.e_c[e], g.e_c[ne + e], g.e_v[e], g.e_v[ne + e], g.e_de[e], g.fe[e]};
+    const int32_t c1 = g.e_c[e], c2 = g.e_c[ne + e], v1 = g.e_v[e], v2 = g.e_v[ne + e];
+    const double de = g.e_de[e], fe = g.fe[e];
     const double cv = p.wgt_corr;
     const double dnsub = double(nsub);
+    double h1_0 = g.zh[c1], h2_0 = g.zh[c2];  // zh at level k
+    double gk1 = 0.0, gk2 = 0.0, om1 = 0.0, om2 = 0.0;
     double vnm = 0.0, vn0 = wk.vns[e];  // predicted vn at levels k-1, k
     for (int k = 0; k < N; ++k) {
-        const int64_t o = int64_t(k) * ne + e;
-        double vn1 = k + 1 < N ? wk.vns[o + ne] : vn0;
-        double vnh_k = k == 0 ? vn0 : half_interp(g, ec, k, vn0, vnm);
-        double vnh_k1 = k + 1 == N ? vn0 : half_interp(g, ec, k + 1, vn1, vn0);
-        double dze = edge_dz(g, ec, k);
-        double tvn1 = vn_tendency(g, ec, k, wk.kc, wk.zeta, wk.vt[o], wk.ws, wk.wcc1, vnh_k, vnh_k1, dze);
-        double ths = 0.5 * (wk.thvs[int64_t(k) * nc + ec.c1] + wk.thvs[int64_t(k) * nc + ec.c2]);
+        const int64_t o = int64_t(k) * ne + e, oc = int64_t(k) * nc, ov = int64_t(k) * nv;
+        const bool last = k + 1 == N;
+        double vn1 = vn0, gb1 = 0.0, gb2 = 0.0, omb1 = 0.0, omb2 = 0.0;
+        if (!last) {
+            const int64_t ob = oc + nc;
+            vn1 = wk.vns[o + ne];
+            gb1 = g.gw[ob + c1];
+            gb2 = g.gw[ob + c2];
+            omb1 = wk.ws[ob + c1] - wk.wcc1[ob + c1];
+            omb2 = wk.ws[ob + c2] - wk.wcc1[ob + c2];
+        }
+        double vnh_k = vn0, vnh_k1 = vn0;
+        if (k > 0) {
+            double gg = 0.5 * (gk1 + gk2);
+            vnh_k = gg * vn0 + (1.0 - gg) * vnm;
+        }
+        if (!last) {
+            double gg = 0.5 * (gb1 + gb2);
+            vnh_k1 = gg * vn1 + (1.0 - gg) * vn0;
+        }
+        double h1_b = g.zh[oc + nc + c1], h2_b = g.zh[oc + nc + c2];
+        double dz1 = h1_0 - h1_b, dz2 = h2_0 - h2_b;
+        double dze = 0.5 * (dz1 + dz2);
+        double gradk = (wk.kc[oc + c2] - wk.kc[oc + c1]) / de;
+        double ze = 0.5 * (wk.zeta[ov + v1] + wk.zeta[ov + v2]);
+        double of1 = 0.5 * (om1 + omb1);
+        double of2 = 0.5 * (om2 + omb2);
+        double obar = 0.5 * (of1 + of2);
+        double dvdz = (vnh_k - vnh_k1) / dze;
+        double tvn1 = -gradk + (ze + fe) * wk.vt[o] - obar * dvdz;
+        double ths = 0.5 * (wk.thvs[oc + c1] + wk.thvs[oc + c2]);
         double tend = (1.0 - cv) * wk.tvn0[o] + cv * tvn1 - p.cpd * ths * wk.gp[o];
-        double gdiv = (wk.dvn[int64_t(k) * nc + ec.c2] - wk.dvn[int64_t(k) * nc + ec.c1]) / ec.de;
+        double gdiv = (wk.dvn[oc + c2] - wk.dvn[oc + c1]) / de;
         double vnn = s.vn[o] + dt * tend + p.div_damp * g.abar * gdiv;
-        double the = 0.5 * (s.thv[int64_t(k) * nc + ec.c1] + s.thv[int64_t(k) * nc + ec.c2]);
-        double rhe = 0.5 * (s.rho[int64_t(k) * nc + ec.c1] + s.rho[int64_t(k) * nc + ec.c2]);
+        double the = 0.5 * (s.thv[oc + c1] + s.thv[oc + c2]);
+        double rhe = 0.5 * (s.rho[oc + c1] + s.rho[oc + c2]);
         double f = rhe * vnn * dze;
         s.vn[o] = vnn;
         wk.flx[o] = f;
@@ -410,15 +480,25 @@ __global__ void __launch_bounds__(BLOCK) k_edge_corr(Grid g, State s, Work wk, P
         s.facc[o] = acc + f / dnsub;
         vnm = vn0;
         vn0 = vn1;
+        gk1 = gb1;
+        gk2 = gb2;
+        om1 = omb1;
+        om2 = omb2;
+        h1_0 = h1_b;
+        h2_0 = h2_b;
     }
 }
 
 // ---------------------------------------------------------------------------
 // column: horizontal divergences, explicit parts, tridiagonal solve in w
 // (Thomas, no pivoting; factors and the explicit rho / Exner parts kept in
-// global scratch), then rho, Exner and theta_v.  CORR selects the corrector:
-// interface state averaged between n and the prediction, averaged w tendency,
-// in-place update of the state, Exner history and flux accumulation.
+// global scratch), then rho, Exner and theta_v.  One lane per column, 64
+// adjacent columns per wavefront, levels in sequence; values of the level
+// above and below are carried in registers, and the interpolation weight and
+// reference derivative are recomputed from zh and theta_ref rather than read.
+// CORR selects the corrector: interface state averaged between n and the
+// prediction, averaged w tendency, in-place update of the state, Exner
+// history and flux accumulation.
 template <bool CORR>
 __global__ void __launch_bounds__(BLOCK) k_column(Grid g, State s, Work wk, Params p, double dt,
                                                   int nsub, int first) {
@@ -426,7 +506,7 @@ __global__ void __launch_bounds__(BLOCK) k_column(Grid g, State s, Work wk, Para
     const int64_t nc = g.nc, ne = g.ne;
     const int N = g.N;
     if (c >= nc) return;
-    const double beta = p.beta, cpd = p.cpd, rd = p.rd, cvd = p.cpd - p.rd;
+    const double beta = p.beta, cpd = p.cpd, rd = p.rd, cvd = p.cpd - p.rd, grav = p.grav;
     const double cv = p.wgt_corr;
     const double dnsub = double(nsub);
     int32_t e[3];
@@ -442,43 +522,62 @@ __global__ void __launch_bounds__(BLOCK) k_column(Grid g, State s, Work wk, Para
     double *rho_out = CORR ? s.rho : wk.rhos;
     double *thv_out = CORR ? s.thv : wk.thvs;
     auto at = [&](int k) { return int64_t(k) * nc + c; };
-    auto rho_if = [&](int k) {
-        return CORR ? 0.5 * (s.rho[at(k)] + wk.rhos[at(k)]) : s.rho[at(k)];
+    // values of one full level
+    struct Lev {
+        double rn, tn, pn, prf, trf, ri, ti;
     };
-    auto thv_if = [&](int k) {
-        return CORR ? 0.5 * (s.thv[at(k)] + wk.thvs[at(k)]) : s.thv[at(k)];
+    auto load = [&](int k) {
+        Lev L;
+        L.rn = s.rho[at(k)];
+        L.tn = s.thv[at(k)];
+        L.pn = s.pi[at(k)];
+        L.prf = g.pi_ref[at(k)];
+        L.trf = g.theta_ref[at(k)];
+        if (CORR) {
+            L.ri = 0.5 * (L.rn + wk.rhos[at(k)]);
+            L.ti = 0.5 * (L.tn + wk.thvs[at(k)]);
+        } else {
+            L.ri = L.rn;
+            L.ti = L.tn;
+        }
+        return L;
     };
     auto twv = [&](int i) {
         return CORR ? (1.0 - cv) * wk.tw0[at(i)] + cv * wk.tw1[at(i)] : wk.tw0[at(i)];
     };
     // ---- forward sweep, top to bottom ----
     // carried: explicit fluxes, alpha, gamma and W-hat of half level k (top of
-    // level k); Pi-hat and B of level k-1; alpha of half level k-1; Thomas factors.
+    // level k); Pi-hat and B of level k-1; alpha of half level k-1; Thomas
+    // factors; level k and zh at k, k+1, k+2.
     double fx_k = 0.0, hx_k = 0.0, al_k = 0.0, ga_k = 0.0, wh_k = 0.0;
     double ph_prev = 0.0, b_prev = 0.0, al_prev = 0.0, cp_prev = 0.0, dp_prev = 0.0;
+    Lev cur = load(0), nxt = cur;
+    double h0 = g.zh[at(0)], h1 = g.zh[at(1)], h2 = g.zh[at(2)];
     for (int k = 0; k < N; ++k) {
         double fx_b = 0.0, hx_b = 0.0, al_b = 0.0, ga_b = 0.0, wh_b = 0.0;
         const int i = k + 1;  // bottom interface of level k
         if (i < N) {
-            double za = 0.5 * (g.zh[at(i - 1)] + g.zh[at(i)]);
-            double zb = 0.5 * (g.zh[at(i)] + g.zh[at(i + 1)]);
+            nxt = load(i);
+            double za = 0.5 * (h0 + h1);
+            double zb = 0.5 * (h1 + h2);
             double dzh = za - zb;
-            double gw = g.gw[at(i)];
-            double ti = thv_if(i), ta = thv_if(i - 1);
-            double rhoh = gw * rho_if(i) + (1.0 - gw) * rho_if(i - 1);
-            double thh = gw * ti + (1.0 - gw) * ta;
-            double thph = gw * (ti - g.theta_ref[at(i)]) + (1.0 - gw) * (ta - g.theta_ref[at(i - 1)]);
-            double ppa = s.pi[at(i - 1)] - g.pi_ref[at(i - 1)];
-            double ppb = s.pi[at(i)] - g.pi_ref[at(i)];
+            double gw = (za - h1) / (za - zb);
+            double rhoh = gw * nxt.ri + (1.0 - gw) * cur.ri;
+            double thh = gw * nxt.ti + (1.0 - gw) * cur.ti;
+            double thph = gw * (nxt.ti - nxt.trf) + (1.0 - gw) * (cur.ti - cur.trf);
+            double threfh = gw * nxt.trf + (1.0 - gw) * cur.trf;
+            double dref = -grav / (cpd * threfh);
+            double ppa = cur.pn - cur.prf;
+            double ppb = nxt.pn - nxt.prf;
             double wn = s.w[at(i)];
-            double pterm = (1.0 - beta) * thh * (ppa - ppb) / dzh + thph * g.dref[at(i)];
+            double pterm = (1.0 - beta) * thh * (ppa - ppb) / dzh + thph * dref;
             wh_b = wn + dt * (twv(i) - cpd * pterm);
             fx_b = rhoh * ((1.0 - beta) * wn - wcc[at(i)]);
             hx_b = thh * fx_b;
             al_b = beta * rhoh * thh;
             ga_b = dt * cpd * beta * thh / dzh;
         }
-        double dz = g.zh[at(k)] - g.zh[at(k + 1)];
+        double dz = h0 - h1;
         double sr = 0.0, st = 0.0;
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
@@ -487,10 +586,9 @@ __global__ void __launch_bounds__(BLOCK) k_column(Grid g, State s, Work wk, Para
         }
         double divr = sr / area / dz;
         double divt = st / area / dz;
-        double rn = s.rho[at(k)], tn = s.thv[at(k)], pn = s.pi[at(k)];
-        double ppn = pn - g.pi_ref[at(k)];
-        double rh = rn - dt * (divr + (fx_k - fx_b) / dz);
-        double bk = dt * (rd / cvd) * pn / (rn * tn * dz);
+        double ppn = cur.pn - cur.prf;
+        double rh = cur.rn - dt * (divr + (fx_k - fx_b) / dz);
+        double bk = dt * (rd / cvd) * cur.pn / (cur.rn * cur.tn * dz);
         double ph = ppn - bk * dz * (divt + (hx_k - hx_b) / dz);
         wk.rh[at(k)] = rh;
         wk.ph[at(k)] = ph;
@@ -521,19 +619,31 @@ __global__ void __launch_bounds__(BLOCK) k_column(Grid g, State s, Work wk, Para
         al_k = al_b;
         ga_k = ga_b;
         wh_k = wh_b;
+        cur = nxt;
+        h0 = h1;
+        h1 = h2;
+        if (k + 3 <= N) h2 = g.zh[at(k + 3)];
     }
     // ---- back substitution, bottom to top, with the level updates ----
     double w_b = wcc[at(N)];          // w at half level k+1; kinematic value at the ground
     double fl_b = 0.0, alw_b = 0.0;   // implicit fluxes at half level k+1 (zero at the ground)
     w_out[at(N)] = w_b;
+    double hb = g.zh[at(N)], hk = g.zh[at(N - 1)];  // zh at k+1, k
+    Lev lk = load(N - 1);
     for (int k = N - 1; k >= 0; --k) {
         double w_t = 0.0, fl_t = 0.0, alw_t = 0.0;  // half level k (zero at the lid)
+        double ha = 0.0;
+        Lev la = lk;
         if (k >= 1) {
+            ha = g.zh[at(k - 1)];
+            la = load(k - 1);
             // the bottom interior row has no super-diagonal
             w_t = (k == N - 1) ? wk.dp[at(k)] : wk.dp[at(k)] - wk.cp[at(k)] * w_b;
-            double gw = g.gw[at(k)];
-            double rhoh = gw * rho_if(k) + (1.0 - gw) * rho_if(k - 1);
-            double thh = gw * thv_if(k) + (1.0 - gw) * thv_if(k - 1);
+            double za = 0.5 * (ha + hk);
+            double zb = 0.5 * (hk + hb);
+            double gw = (za - hk) / (za - zb);
+            double rhoh = gw * lk.ri + (1.0 - gw) * la.ri;
+            double thh = gw * lk.ti + (1.0 - gw) * la.ti;
             double al = beta * rhoh * thh;
             fl_t = rhoh * w_t;
             alw_t = al * w_t;
@@ -543,17 +653,16 @@ __global__ void __launch_bounds__(BLOCK) k_column(Grid g, State s, Work wk, Para
                 s.wacc[at(k)] = acc + vf / dnsub;
             }
         }
-        double dz = g.zh[at(k)] - g.zh[at(k + 1)];
-        double rn = s.rho[at(k)], tn = s.thv[at(k)], pn = s.pi[at(k)];
-        double ppn = pn - g.pi_ref[at(k)];
-        double bk = dt * (rd / cvd) * pn / (rn * tn * dz);
+        double dz = hk - hb;
+        double ppn = lk.pn - lk.prf;
+        double bk = dt * (rd / cvd) * lk.pn / (lk.rn * lk.tn * dz);
         double rnew = wk.rh[at(k)] - dt * beta * (fl_t - fl_b) / dz;
         double ppnew = wk.ph[at(k)] - bk * (alw_t - alw_b);
-        double rt = rn * tn;
-        double thnew = (rt + (cvd / rd) * (rt / pn) * (ppnew - ppn)) / rnew;
+        double rt = lk.rn * lk.tn;
+        double thnew = (rt + (cvd / rd) * (rt / lk.pn) * (ppnew - ppn)) / rnew;
         if (CORR) {
             s.pi_prev[at(k)] = ppn;
-            s.pi[at(k)] = g.pi_ref[at(k)] + ppnew;
+            s.pi[at(k)] = lk.prf + ppnew;
         }
         rho_out[at(k)] = rnew;
         thv_out[at(k)] = thnew;
@@ -561,6 +670,9 @@ __global__ void __launch_bounds__(BLOCK) k_column(Grid g, State s, Work wk, Para
         w_b = w_t;
         fl_b = fl_t;
         alw_b = alw_t;
+        hb = hk;
+        hk = ha;
+        lk = la;
     }
     if (CORR && first) {
         s.wacc[at(0)] = 0.0;

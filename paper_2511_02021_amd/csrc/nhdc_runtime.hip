@@ -244,7 +244,28 @@ int nhdc_upload_grid(nhdc_ctx *ctx, const nhdc_grid *g, const nhdc_vertical *v,
         }
     }
     for (int64_t e = 0; e < ne; ++e) fe[e] = 2.0 * prm->omega * g->edge_x[2 * ne + e];
+    // neighbours and vertex slots of every cell, from its edges: edge slot j runs
+    // from vertex slot j to j+1 counter-clockwise, i.e. from v1 to v2 when the
+    // normal points out of the cell (s = +1) and from v2 to v1 otherwise.
+    std::vector<int32_t> c_n(3 * nc), c_v(3 * nc);
+    for (int64_t c = 0; c < nc; ++c) {
+        int32_t first[3], second[3];
+        for (int j = 0; j < 3; ++j) {
+            int64_t e = g->cell_edges[j * nc + c];
+            bool out = g->cell_sign[j * nc + c] > 0;
+            c_n[j * nc + c] = out ? g->edge_cells[ne + e] : g->edge_cells[e];
+            first[j] = out ? g->edge_verts[e] : g->edge_verts[ne + e];
+            second[j] = out ? g->edge_verts[ne + e] : g->edge_verts[e];
+            c_v[j * nc + c] = first[j];
+        }
+        for (int j = 0; j < 3; ++j)
+            if (second[j] != first[(j + 1) % 3])
+                return set_err(ctx, NHDC_EGRID,
+                               "grid: cell edges are not a counter-clockwise chain of its vertices");
+    }
     if ((rc = upload(ctx, &G.c_e, g->cell_edges, 3 * nc))) return rc;
+    if ((rc = upload(ctx, &G.c_n, c_n.data(), 3 * nc))) return rc;
+    if ((rc = upload(ctx, &G.c_v, c_v.data(), 3 * nc))) return rc;
     if ((rc = upload(ctx, &G.e_c, g->edge_cells, 2 * ne))) return rc;
     if ((rc = upload(ctx, &G.e_v, g->edge_verts, 2 * ne))) return rc;
     if ((rc = upload(ctx, &G.v_e, v_e.data(), 6 * nv))) return rc;
