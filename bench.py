@@ -2,14 +2,23 @@
 
 A step is one dynamical-core step (dt, 5 substeps; each substep = velocity
 tendencies, predictor, column solve, tendencies of the prediction, corrector,
-column solve) over the whole grid.  Default workload: R2B6 (327 680 cells),
-90 stretched levels to 75 km over seeded random-harmonic terrain, dt = 90 s,
-FP64 plain form, 2 warm-up steps then 98 timed steps (steps 3..100 of the
-100-step run).  Inputs are synthetic and resident in HBM before timing.
+column solve) over the whole grid; a cell-level update is one cell at one
+full level through one substep.  Inputs are synthetic (seeded recipe with the
+paper's grid and level counts) and resident in HBM before timing.
 
-Prints ONE JSON line with the throughput, the roofline of the dominant kernel
-(algorithmic bytes / measured average duration, from HIP events on the
-stream the kernels run on) and the CPU oracle timed on a bounded sample.
+Default workload (the value): R2B6 (327 680 cells), 90 stretched levels to
+75 km over seeded random-harmonic terrain, dt = 90 s, FP64 plain form, 2
+warm-up steps then 98 timed steps (steps 3..100 of the 100-step run).  The
+same line carries the FP32-mixed form on the same workload (throughput,
+speedup, per-field error against FP64 next to the FP32-rounding floor), the
+roofline of the dominant kernel (algorithmic bytes / average duration from
+HIP events on the stream the kernels run on) and the CPU oracle timed on a
+bounded sample.
+
+Other workloads (one JSON line each): --config 3 (R2B7x90 mixed, 100 steps,
+error vs FP64), --config 4 (batch of 16 uneven instances, mixed, one launch
+per kernel + graph replay + autotuned tiles, vs 16 sequential plain runs),
+--config 5 (R2B8x90 mixed, 50-step sustained run).
 """
 import argparse
 import hashlib
@@ -23,6 +32,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FIELDS = ("vn", "w", "rho", "pi", "theta_v")
 
 
 def log(*a):
@@ -30,22 +40,36 @@ def log(*a):
 
 
 def algorithmic_bytes(nc, ne, nv, N, prec="fp64"):
-    """Bytes each kernel must read and write once per launch (inputs and
-    outputs at their sizes; cached re-reads of gathered neighbours and
-    scratch round trips are not counted).  fp64 layout."""
-    C, C1, Ci = N * nc * 8, (N + 1) * nc * 8, (N - 1) * nc * 8
-    E, V, V1, Vi = N * ne * 8, N * nv * 8, (N + 1) * nv * 8, (N - 1) * nv * 8
-    econn = ne * (2 * 4 + 2 * 4 + 8)      # e_c, e_v, one per-edge constant
-    cconn = nc * 3 * (4 + 8)              # c_e, div_c
+    """Bytes each kernel must read and write once per launch: every input and
+    output array once at its size (cached re-reads of gathered neighbours,
+    register-carried levels and column scratch round trips not counted).
+    Tendency-side arrays are FP32 in the mixed form; state, fluxes and the
+    column are FP64 in both."""
+    r = 8 if prec == "fp64" else 4
+    C, C1, Ci = N * nc, (N + 1) * nc, (N - 1) * nc        # entity-level counts
+    E, V, V1, Vi = N * ne, N * nv, (N + 1) * nv, (N - 1) * nv
+    gc = nc * 3 * (4 + 4 + 4 + r) + nc * r                 # c_e, c_n, c_v, c_sl; area
+    ge = ne * (2 * 4 + 2 * 4 + 2 * r)                      # e_c, e_v, d_e/l_e or f
+    gv = nv * 6 * (4 + 4 + r + r) + 2 * nv * r
+    recon = 2 * ne * (3 * 4 + 16 * r) + 3 * ne * r         # two cells' reconstruction coeffs + tangent
     t = {
-        "vt_edge": [E + E + 6 * ne * 12],
-        "vertex": [E + Ci + V + Vi + 6 * nv * 24],
-        "cell_vt": [2 * E + C1 + Vi + 3 * C1 + V1 + C + 2 * C1 + cconn + econn,
-                    2 * E + C1 + Vi + 3 * C1 + V1 + 2 * C + 2 * C1 + cconn + econn],
-        "edge_pred": [C + V + 2 * E + 2 * C1 + 5 * C + 2 * C1 + 5 * E + econn],
-        "edge_corr": [C + V + 2 * E + 2 * C1 + C + 2 * E + C + E + 2 * C + 2 * C1 + E + 4 * E + econn],
-        "column_pred": [2 * E + 5 * C + 2 * C1 + C1 + 3 * C1 + C1 + 2 * C + cconn],
-        "column_corr": [2 * E + 5 * C + C1 + 2 * C + 3 * C1 + 3 * C1 + C1 + C1 + 4 * C + C1 + cconn],
+        "vt_edge": [E * 8 + E * r + recon],
+        "vertex": [E * 8 + Ci * 8 + V * r + Vi * r + gv],
+        # vn, vt, w, wv, zh, zhv, gw -> kc, wcc, tw (+ div vn in the corrector)
+        "cell_vt": [E * 8 + E * r + C1 * 8 + Vi * r + C1 * 8 + V1 * 8 + C1 * r + C * r + 2 * C1 * r + gc + ge,
+                    E * 8 + E * r + C1 * 8 + Vi * r + C1 * 8 + V1 * 8 + C1 * r + 2 * C * r + 2 * C1 * r + gc + ge],
+        # kc, zeta, vt, vn, w, wcc, pi, pi_prev, pi_ref, thv, rho, zh, gw -> tvn, gp, vns, flx, hfl
+        "edge_pred": [C * r + V * r + E * r + E * 8 + C1 * 8 + C1 * r + 5 * C * 8 + C1 * 8 + C1 * r
+                      + 2 * E * r + 3 * E * 8 + ge],
+        # kc, zeta, vt, vns, ws, wcc1, thvs, tvn0, gp, dvn, vn, thv, rho, zh, gw, facc -> vn, flx, hfl, facc
+        "edge_corr": [C * r + V * r + E * r + E * 8 + C1 * 8 + C1 * r + C * 8 + 2 * E * r + C * r
+                      + E * 8 + 2 * C * 8 + C1 * 8 + C1 * r + E * 8 + 4 * E * 8 + ge],
+        # flx, hfl, rho, thv, pi, pi_ref, theta_ref, w, wcc, tw, zh -> ws, rhos, thvs
+        "column_pred": [2 * E * 8 + 5 * C * 8 + C1 * 8 + 2 * C1 * r + C1 * 8 + C1 * 8 + 2 * C * 8 + gc],
+        # flx, hfl, rho, thv, pi, pi_ref, theta_ref, w, rhos, thvs, wcc1, tw0, tw1, zh, wacc
+        #   -> w, rho, thv, pi, pi_prev, wacc
+        "column_corr": [2 * E * 8 + 5 * C * 8 + C1 * 8 + 2 * C * 8 + 3 * C1 * r + C1 * 8 + C1 * 8
+                        + C1 * 8 + 4 * C * 8 + C1 * 8 + gc],
     }
     return {k: sum(v) / len(v) for k, v in t.items()}
 
@@ -54,20 +78,20 @@ def kernel_source_hash():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2511_02021_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")):
+        if f.endswith((".hip", ".h", ".inc")):
             h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, src_hash):
-    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_r2b6x90_counters.txt")
+def measured_traffic(kernel, src_hash, precision):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"dycore_{precision}_r2b6x90_hbm_counters.txt")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
     m = re.search(r"kernel_source_sha256_16:\s*(\w+)", txt)
-    b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    b = re.search(rf"^{kernel}\s+.*?hbm_bytes_per_launch=([0-9.eE+]+)", txt, re.M)
     if not m or not b or m.group(1) != src_hash:
         return None
     return float(b.group(1))
@@ -88,76 +112,113 @@ def cpu_baseline(case):
                       f"case from its initial state"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=98)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
-    ap.add_argument("--timing-steps", type=int, default=4)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="after timing, copy 1 GiB device-to-device once (a plain copy kernel of "
-                         "known size, to scale hardware byte counters)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); the "
-              "multi-GPU decomposition is a design, not an implementation", file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-    from paper_2511_02021_amd import nhdc
-    from paper_2511_02021_amd.inputs import case as CS
-
-    torch.cuda.set_device(0)
-    t0 = time.time()
-    case = CS.config_case(2)
-    g = case.grid
-    log(f"case R2B{g.k}x{case.n_lev}: {g.n_cells} cells, {g.n_edges} edges "
-        f"({time.time() - t0:.1f}s)")
-    d = nhdc.Dycore(case, precision=args.precision)
-    stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
-        d.step(case.dt, case.nsub, stream)
+def timed_steps(torch, stepper, steps, warmup, stream):
+    for _ in range(warmup):
+        stepper()
     torch.cuda.synchronize()
-    log(f"warmup {args.warmup} steps done")
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     e0.record(stream)
-    for _ in range(args.steps):
-        d.step(case.dt, case.nsub, stream)
+    for _ in range(steps):
+        stepper()
     e1.record(stream)
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    d.check_finite()
-    ms_per_step = ms / args.steps
-    units = g.n_cells * case.n_lev * case.nsub * args.steps
-    value = units / (ms / 1e3)
-    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step, {value:.4e} cell-level updates/s")
+    return e0.elapsed_time(e1)
 
-    # per-kernel durations from HIP events around each launch on the same stream
+
+def kernel_table(d, case, steps, stream, precision):
+    g = case.grid
     d.set_timing(True)
-    for _ in range(args.timing_steps):
+    for _ in range(steps):
         d.step(case.dt, case.nsub, stream)
     stats = d.kernel_stats()
     d.set_timing(False)
-    alg = algorithmic_bytes(g.n_cells, g.n_edges, g.n_verts, case.n_lev, args.precision)
-    kern = {k: {"avg_ms": v[0] / v[1], "launches": v[1], "share": v[0]} for k, v in stats.items() if v[1]}
-    tot = sum(x["share"] for x in kern.values())
+    alg = algorithmic_bytes(g.n_cells, g.n_edges, g.n_verts, case.n_lev, precision)
+    kern = {k: {"avg_ms": v[0] / v[1], "launches": v[1], "total": v[0]} for k, v in stats.items()
+            if v[1]}
+    tot = sum(x["total"] for x in kern.values())
     for k in kern:
-        kern[k]["share"] = kern[k]["share"] / tot
+        kern[k]["share"] = kern[k]["total"] / tot
+        kern[k]["alg_bytes"] = alg[k]
         kern[k]["alg_GBs"] = alg[k] / (kern[k]["avg_ms"] / 1e3) / 1e9
-    dom = max(kern, key=lambda k: kern[k]["share"])
+    return kern
+
+
+def rel_l2(a, b):
+    import numpy as np
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def error_table(nhdc, case, steps):
+    """Per field: E = rel-L2(mixed - FP64), S = rel-L2 between two FP64 runs
+    whose initial states differ by seeded relative noise 2^-24 (the
+    FP32-rounding floor), both after `steps` steps from the initial state."""
+    import numpy as np
+    init = dict(vn=case.vn, w=case.w, rho=case.rho, pi=case.pi, theta_v=case.theta_v)
+
+    def run(prec, state=None):
+        d = nhdc.Dycore(case, precision=prec)
+        if state is not None:
+            d.init_state(*[state[f] for f in FIELDS])
+        for _ in range(steps):
+            d.step(case.dt, case.nsub)
+        s = d.get_state()
+        d.close()
+        return s
+
+    f64 = run("fp64")
+    mix = run("mixed")
+    rng = np.random.default_rng(7)
+    pert = {k: v * (1.0 + 2.0 ** -24 * rng.standard_normal(v.shape)) for k, v in init.items()}
+    f64p = run("fp64", pert)
+    out = {}
+    for f in FIELDS:
+        sig = np.linalg.norm(f64[f] - init[f])
+        out[f] = {"E": rel_l2(mix[f], f64[f]), "S": rel_l2(f64p[f], f64[f]),
+                  "E_over_signal": float(np.linalg.norm(mix[f] - f64[f]) / max(sig, 1e-300))}
+    return out
+
+
+def bench_default(args, torch, nhdc, CS):
+    stream = torch.cuda.current_stream()
+    t0 = time.time()
+    case = CS.config_case(2)
+    g = case.grid
+    units_per_step = g.n_cells * case.n_lev * case.nsub
+    log(f"case R2B{g.k}x{case.n_lev}: {g.n_cells} cells, {g.n_edges} edges ({time.time() - t0:.1f}s)")
+    forms = {}
+    tables = {}
+    for prec in ("fp64", "mixed"):
+        d = nhdc.Dycore(case, precision=prec)
+        ms = timed_steps(torch, lambda: d.step(case.dt, case.nsub, stream), args.steps,
+                         args.warmup, stream)
+        d.check_finite()
+        forms[prec] = {"value": units_per_step * args.steps / (ms / 1e3),
+                       "ms_per_step": ms / args.steps}
+        log(f"{prec}: {ms / args.steps:.3f} ms/step, {forms[prec]['value']:.4e} cell-level updates/s")
+        tables[prec] = kernel_table(d, case, args.timing_steps, stream, prec)
+        d.close()
+    forms["mixed"]["speedup_vs_fp64"] = forms["fp64"]["ms_per_step"] / forms["mixed"]["ms_per_step"]
+    if args.error_steps > 0:
+        log(f"per-field error, {args.error_steps} steps ...")
+        forms["mixed"]["per_field_error"] = error_table(nhdc, case, args.error_steps)
+        forms["mixed"]["error_steps"] = args.error_steps
+    kern = tables["fp64"]
     for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["share"]):
-        log(f"  {k:12s} {v['avg_ms']:8.4f} ms  share {v['share']:.3f}  {v['alg_GBs']:8.1f} GB/s")
+        log(f"  fp64 {k:12s} {v['avg_ms']:8.4f} ms  share {v['share']:.3f}  {v['alg_GBs']:8.1f} GB/s")
+    dom = max(kern, key=lambda k: kern[k]["share"])
     src_hash = kernel_source_hash()
-    traffic = measured_traffic(dom, src_hash)
     achieved = kern[dom]["alg_GBs"]
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "alg_bytes_per_launch": int(alg[dom]),
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(dom, src_hash, "fp64"),
+                "alg_bytes_per_launch": int(kern[dom]["alg_bytes"]),
                 "avg_launch_ms": round(kern[dom]["avg_ms"], 5)}
+    mk = tables["mixed"]
+    mdom = max(mk, key=lambda k: mk[k]["share"])
+    forms["mixed"]["roofline"] = {"kernel": mdom, "achieved": round(mk[mdom]["alg_GBs"], 1),
+                                  "frac": round(mk[mdom]["alg_GBs"] / HBM_PEAK_GBS, 4),
+                                  "traffic": measured_traffic(mdom, src_hash, "mixed")}
     if args.copy_calibration:
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
         b = torch.empty_like(a)
@@ -172,29 +233,137 @@ def main():
         log("cpu baseline (oracle) ...")
         cpu = cpu_baseline(case)
         log(f"  oracle {cpu['value']:.4e} cell-level updates/s on {cpu['cores']} threads")
-    out = {
+    return {
         "metric": "dycore cell-level updates/s",
-        "value": value,
+        "value": forms["fp64"]["value"],
         "unit": "cell-level updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": forms["fp64"]["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"R2B{g.k} ({g.n_cells} cells) x {case.n_lev} levels, terrain, "
-                               f"dt={case.dt:g}s, {case.nsub} substeps, {args.precision}",
+        "config": {"workload": f"R2B{g.k} ({g.n_cells} cells) x {case.n_lev} levels to 75 km, "
+                               f"terrain, dt={case.dt:g}s, {case.nsub} substeps, FP64 plain",
                    "cells": g.n_cells, "levels": case.n_lev, "substeps": case.nsub,
-                   "precision": args.precision, "parallelism": "single GPU"},
+                   "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "forms": forms,
         "kernels": {k: {"avg_ms": round(v["avg_ms"], 5), "share": round(v["share"], 4),
                         "alg_GBs": round(v["alg_GBs"], 1)} for k, v in kern.items()},
         "kernel_source_sha256_16": src_hash,
     }
+
+
+def bench_single(args, torch, nhdc, CS, cfg):
+    """R2B7x90 (config 3) or R2B8x90 (config 5), FP32-mixed."""
+    stream = torch.cuda.current_stream()
+    t0 = time.time()
+    case = CS.config_case(cfg)
+    g = case.grid
+    log(f"case R2B{g.k}x{case.n_lev}: {g.n_cells} cells ({time.time() - t0:.1f}s)")
+    steps = args.steps if args.steps != 98 else CS.CONFIGS[cfg]["steps"] - 2
+    d = nhdc.Dycore(case, precision="mixed")
+    ms = timed_steps(torch, lambda: d.step(case.dt, case.nsub, stream), steps, args.warmup, stream)
+    d.check_finite()
+    units = g.n_cells * case.n_lev * case.nsub * steps
+    kern = kernel_table(d, case, args.timing_steps, stream, "mixed")
+    d.close()
+    dom = max(kern, key=lambda k: kern[k]["share"])
+    out = {"metric": "dycore cell-level updates/s", "value": units / (ms / 1e3),
+           "unit": "cell-level updates/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+           "ms_per_step": ms / steps, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+           "config": {"workload": f"R2B{g.k} ({g.n_cells} cells) x {case.n_lev} levels, terrain, "
+                                  f"dt={case.dt:g}s, {case.nsub} substeps, FP32-mixed",
+                      "cells": g.n_cells, "levels": case.n_lev},
+           "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(kern[dom]["alg_GBs"], 1),
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(kern[dom]["alg_GBs"] / HBM_PEAK_GBS, 4), "traffic": None},
+           "kernels": {k: {"avg_ms": round(v["avg_ms"], 5), "share": round(v["share"], 4),
+                           "alg_GBs": round(v["alg_GBs"], 1)} for k, v in kern.items()}}
+    if cfg == 3 and args.error_steps > 0:
+        log("per-field error vs FP64 ...")
+        out["per_field_error"] = error_table(nhdc, case, CS.CONFIGS[cfg]["steps"])
+    return out
+
+
+def bench_batch(args, torch, nhdc, CS):
+    """16 uneven instances (R2B4-R2B6, 30-90 levels), FP32-mixed, one launch
+    per kernel over all instances, graph replay, autotuned level tiles; against
+    the 16 instances run one after another in the plain FP64 form and in the
+    mixed form."""
+    stream = torch.cuda.current_stream()
+    t0 = time.time()
+    cases = CS.batch_cases()
+    log(f"16 cases ({time.time() - t0:.1f}s): " + ", ".join(f"R2B{c.grid.k}x{c.n_lev}" for c in cases))
+    steps = args.steps if args.steps != 98 else 10
+    units = sum(c.grid.n_cells * c.n_lev * c.nsub for c in cases) * steps
+    res = {}
+    for prec in ("fp64", "mixed"):
+        total = 0.0
+        for c in cases:  # sequential, one instance at a time
+            d = nhdc.Dycore(c, precision=prec)
+            total += timed_steps(torch, lambda: d.step(c.dt, c.nsub, stream), steps, 1, stream)
+            d.close()
+        res[f"sequential_{prec}_ms"] = total
+    ds = [nhdc.Dycore(c, precision="mixed") for c in cases]
+    b = nhdc.Batch(ds)
+    dts = [c.dt for c in cases]
+    tune_path = os.path.join(ROOT, "gpurun_out", "batch_tiles.json") if os.path.isdir(
+        os.path.join(ROOT, "gpurun_out")) else None
+    best = b.autotune(dts, 5, cache_path=tune_path)
+    log(f"autotuned tiles {best}")
+    ms = timed_steps(torch, lambda: b.step(dts, 5, 1, stream), steps, 1, stream)
+    for d in ds:
+        d.check_finite()
+    b.close()
+    for d in ds:
+        d.close()
+    return {"metric": "dycore cell-level updates/s", "value": units / (ms / 1e3),
+            "unit": "cell-level updates/s", "n_gpus": 1, "steps": steps, "warmup": 1,
+            "ms_per_step": ms / steps, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+            "config": {"workload": "batch of 16 instances R2B4-R2B6, 30-90 levels, terrain, "
+                                   "FP32-mixed, one launch per kernel + graph replay",
+                       "instances": [f"R2B{c.grid.k}x{c.n_lev}" for c in cases],
+                       "tiles": {"lt_edge": best[0], "lt_cell": best[1], "lt_vert": best[2]}},
+            "speedup_vs_sequential_fp64": res["sequential_fp64_ms"] / ms,
+            "speedup_vs_sequential_mixed": res["sequential_mixed_ms"] / ms,
+            "sequential_ms": res}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=98)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", type=int, default=2, choices=[2, 3, 4, 5])
+    ap.add_argument("--timing-steps", type=int, default=4)
+    ap.add_argument("--error-steps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after timing, copy 1 GiB device-to-device once (a plain copy kernel of "
+                         "known size, to scale hardware byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); the "
+              "multi-GPU decomposition is a design, not an implementation", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2511_02021_amd import nhdc
+    from paper_2511_02021_amd.inputs import case as CS
+    torch.cuda.set_device(0)
+    if args.config == 2:
+        out = bench_default(args, torch, nhdc, CS)
+    elif args.config == 4:
+        out = bench_batch(args, torch, nhdc, CS)
+    else:
+        out = bench_single(args, torch, nhdc, CS, args.config)
     print(json.dumps(out), flush=True)
 
 

@@ -152,6 +152,45 @@ int nhdc_check_finite(nhdc_ctx *ctx, void *stream);
 int nhdc_sizes(const nhdc_ctx *ctx, int64_t *n_cells, int64_t *n_edges, int64_t *n_verts,
                int32_t *n_lev);
 
+/* Level tiles of the marching kernels: each lane handles lt levels of one
+ * entity (0 = the whole column).  Results do not depend on the tiles; only
+ * speed does.  Edge kernels, the cell tendency kernel and the vertex kernel
+ * are tiled separately. */
+int nhdc_set_tiles(nhdc_ctx *ctx, int lt_edge, int lt_cell, int lt_vert);
+
+/* Search the level tiles for this context's grid by timing whole steps of
+ * (dt, nsubsteps) on `stream`, keep the fastest, and report it in best[4]
+ * = {lt_edge, lt_cell, lt_vert, ms per step}.  The state is saved before and
+ * restored after the search.  If cache_path is not NULL it names a JSON file
+ * (object of "key": [lt_edge, lt_cell, lt_vert, ms]) that is read first (a
+ * hit skips the search) and updated after a search. */
+int nhdc_autotune(nhdc_ctx *ctx, double dt, int nsubsteps, const char *cache_path,
+                  double *best, void *stream);
+
+/* ---- batching -------------------------------------------------------------
+ * A batch advances many independent instances (contexts with their grid and
+ * state) of uneven size and level count together: every kernel of a substep
+ * is ONE launch over all instances (the block map assigns each instance its
+ * own range of tiles), and a whole step (nsubsteps x 10 launches) is captured
+ * once into a HIP graph and replayed.  The paper's GPU runs keep small
+ * kernels from starving the device with CUDA graphs (Sec. 3.1) and lose
+ * efficiency when a GPU's share of the grid is small (Sec. 5); batching is
+ * the single-GPU answer to both.  Instances keep their own dt; results are
+ * bitwise those of stepping each instance alone with the same tiles. */
+typedef struct nhdc_batch nhdc_batch;
+
+/* Borrow n (1..64) contexts, all on one device and of one precision, each
+ * with grid and state; they must outlive the batch. */
+int nhdc_batch_create(nhdc_batch **out, nhdc_ctx *const *instances, int n);
+/* nsteps steps of (dt[i], nsubsteps) for every instance i, enqueued on stream. */
+int nhdc_batch_step(nhdc_batch *b, const double *dt, int nsubsteps, int nsteps, void *stream);
+int nhdc_batch_set_tiles(nhdc_batch *b, int lt_edge, int lt_cell, int lt_vert);
+/* As nhdc_autotune, over the whole batch. */
+int nhdc_batch_autotune(nhdc_batch *b, const double *dt, int nsubsteps, const char *cache_path,
+                        double *best, void *stream);
+const char *nhdc_batch_last_error(const nhdc_batch *b);
+void nhdc_batch_destroy(nhdc_batch *b);
+
 /* Per-kernel timing (the paper times with a cycle counter and reports the
  * dynamical core's sustained bandwidth, Sec. 3.2 and 4.3).  While enabled,
  * every kernel launch of nhdc_step is bracketed by HIP events on the step's

@@ -1,0 +1,17 @@
+// nhdc_fp64.hip -- the FP64 form of the substep kernels.  Compiled without
+// floating-point contraction: together with the operation order of
+// nhdc_step.inc this makes every value bitwise equal to the plain FP64
+// definition of the discretisation.
+#include <hip/hip_runtime.h>
+
+#include "nhdc_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace nhdc {
+#include "nhdc_step.inc"
+
+hipError_t launch_substep_fp64(const Launcher &L, const Sub &sub, Timing *tm, hipStream_t st) {
+    return substep<double>(L, sub, tm, st);
+}
+}  // namespace nhdc

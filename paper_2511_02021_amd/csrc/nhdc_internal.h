@@ -1,4 +1,4 @@
-// nhdc_internal.h -- device-side data of one libnhdc context.
+// nhdc_internal.h -- device-side data of libnhdc contexts and batches.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -10,58 +10,75 @@
 
 namespace nhdc {
 
-// Connectivity and stencil coefficients (device pointers).  Pentagon pad
-// slots point at a valid entity with a zero coefficient, so gathers need no
-// branch.
+constexpr int BLOCK = 256;      // lanes per workgroup (4 wavefronts)
+constexpr int MAX_INST = 64;    // instances of one batched launch
+
+// Stencil coefficients in one precision.  The FP64 form reads the double
+// set; the mixed form's FP32 stencils read float copies of the same values.
+template <class T>
+struct Geo {
+    T *c_sl = nullptr;    // [3][nc] s(c,e_j) * l_ej
+    T *c_dv = nullptr;    // [9][nc] a*(x_ej - x_c), row j*3+d
+    T *c_x = nullptr;     // [3][nc] unit cell centre (radial direction)
+    T *c_area = nullptr;  // [nc] cell area
+    T *e_de = nullptr;    // [ne] dual length d_e
+    T *e_le = nullptr;    // [ne] primal length l_e
+    T *e_t = nullptr;     // [3][ne] edge tangent
+    T *fe = nullptr;      // [ne] Coriolis parameter 2 Omega z_e
+    T *v_sd = nullptr;    // [6][nv] sigma(v,e_j) * d_ej (0 on the pentagon pad)
+    T *v_m = nullptr;     // [6][nv] 1 on ring slots, 0 on the pad
+    T *v_val = nullptr;   // [nv] valence
+    T *v_area = nullptr;  // [nv] dual area
+    T *gw = nullptr;      // [N+1][nc] vertical interpolation weight (interior half levels)
+};
+
 struct Grid {
     int64_t nc = 0, ne = 0, nv = 0;
     int N = 0;
-    double radius = 0, abar = 0;     // mean cell area 4 pi a^2 / nc
-    int32_t *c_e = nullptr;          // [3][nc] cell -> edges
-    int32_t *c_n = nullptr;          // [3][nc] neighbour across edge slot j
-    int32_t *c_v = nullptr;          // [3][nc] vertex slot j (edge slot j joins vertex slots j, j+1)
-    int32_t *e_c = nullptr;          // [2][ne] edge -> c1, c2
-    int32_t *e_v = nullptr;          // [2][ne] edge -> v1, v2
-    int32_t *v_e = nullptr;          // [6][nv] vertex ring edges (pad -> slot 0)
-    int32_t *v_c = nullptr;          // [6][nv] vertex ring cells (pad -> slot 0)
-    double *c_sl = nullptr;          // [3][nc] s(c,e_j) * l_ej
-    double *c_area = nullptr;        // [nc] cell area
-    double *c_x = nullptr;           // [3][nc] unit cell centre (radial direction)
-    double *c_dv = nullptr;          // [9][nc] a*(x_ej - x_c), row j*3+d
-    double *e_de = nullptr;          // [ne] dual length d_e
-    double *e_le = nullptr;          // [ne] primal length l_e
-    double *e_t = nullptr;           // [3][ne] edge tangent
-    double *fe = nullptr;            // [ne] Coriolis parameter 2 Omega z_e
-    double *v_sd = nullptr;          // [6][nv] sigma(v,e_j) * d_ej (0 on pad)
-    double *v_m = nullptr;           // [6][nv] 1 on ring slots, 0 on pad
-    double *v_val = nullptr;         // [nv] valence
-    double *v_area = nullptr;        // [nv] dual area
-    // vertical metrics
-    double *zh = nullptr;            // [N+1][nc]
-    double *gw = nullptr;            // [N+1][nc] interpolation weight (interior half levels)
-    double *dref = nullptr;          // [N+1][nc] -g/(cpd theta_ref at half level)
-    double *zhv = nullptr;           // [N+1][nv] vertex average of zh
-    double *pi_ref = nullptr;        // [N][nc]
-    double *theta_ref = nullptr;     // [N][nc]
+    double radius = 0, abar = 0;  // mean cell area 4 pi a^2 / nc
+    int32_t *c_e = nullptr;       // [3][nc] cell -> edges
+    int32_t *c_n = nullptr;       // [3][nc] neighbour across edge slot j
+    int32_t *c_v = nullptr;       // [3][nc] vertex slot j (edge slot j joins vertex slots j, j+1)
+    int32_t *e_c = nullptr;       // [2][ne] edge -> c1, c2
+    int32_t *e_v = nullptr;       // [2][ne] edge -> v1, v2
+    int32_t *v_e = nullptr;       // [6][nv] vertex ring edges (pad -> slot 0)
+    int32_t *v_c = nullptr;       // [6][nv] vertex ring cells (pad -> slot 0)
+    Geo<double> gd;
+    Geo<float> gf;
+    double *zh = nullptr;         // [N+1][nc] half-level heights
+    double *dref = nullptr;       // [N+1][nc] -g/(cpd theta_ref at half level)
+    double *zhv = nullptr;        // [N+1][nv] vertex average of zh
+    double *pi_ref = nullptr;     // [N][nc]
+    double *theta_ref = nullptr;  // [N][nc]
 };
 
+template <class T>
+__host__ __device__ inline const Geo<T> &geo(const Grid &g);
+template <>
+__host__ __device__ inline const Geo<double> &geo<double>(const Grid &g) { return g.gd; }
+template <>
+__host__ __device__ inline const Geo<float> &geo<float>(const Grid &g) { return g.gf; }
+
+// Prognostic state (FP64 in every form) and the FP64 mass-flux accumulators.
 struct State {
     double *vn = nullptr, *w = nullptr, *rho = nullptr, *pi = nullptr, *thv = nullptr,
            *pi_prev = nullptr;
     double *facc = nullptr, *wacc = nullptr;
 };
 
-// Work arrays of one substep.
+// Work arrays of one substep.  Tendency-side arrays have the stencil
+// precision RT; predicted state, fluxes and column scratch are FP64.
+template <class RT>
 struct Work {
-    double *vt = nullptr;     // [N][ne] tangential velocity
-    double *zeta = nullptr;   // [N][nv] vertex vorticity
-    double *wv = nullptr;     // [N+1][nv] vertex average of w
-    double *kc = nullptr;     // [N][nc] cell kinetic energy
-    double *dvn = nullptr;    // [N][nc] divergence of vn (damping)
-    double *wcc0 = nullptr, *tw0 = nullptr;  // [N+1][nc] of state n
-    double *wcc1 = nullptr, *tw1 = nullptr;  // [N+1][nc] of the predicted state
-    double *tvn0 = nullptr;   // [N][ne] vn tendency of state n
-    double *gp = nullptr;     // [N][ne] terrain-corrected Exner gradient
+    RT *vt = nullptr;     // [N][ne] tangential velocity
+    RT *zeta = nullptr;   // [N][nv] vertex vorticity
+    RT *wv = nullptr;     // [N+1][nv] vertex average of w
+    RT *kc = nullptr;     // [N][nc] cell kinetic energy
+    RT *dvn = nullptr;    // [N][nc] divergence of vn (damping)
+    RT *wcc0 = nullptr, *tw0 = nullptr;  // [N+1][nc] of state n
+    RT *wcc1 = nullptr, *tw1 = nullptr;  // [N+1][nc] of the predicted state
+    RT *tvn0 = nullptr;   // [N][ne] vn tendency of state n
+    RT *gp = nullptr;     // [N][ne] terrain-corrected Exner gradient
     double *vns = nullptr;    // [N][ne] predicted vn
     double *flx = nullptr;    // [N][ne] edge mass flux
     double *hfl = nullptr;    // [N][ne] edge rho*theta_v flux
@@ -70,22 +87,50 @@ struct Work {
     double *thvs = nullptr;   // [N][nc] predicted theta_v
     double *cp = nullptr, *dp = nullptr;  // [N+1][nc] Thomas factors
     double *rh = nullptr, *ph = nullptr;  // [N][nc] explicit rho and Exner parts
-    double *red = nullptr;    // reduction partials [2 * blocks + 2]
-    int *flag = nullptr;      // finiteness flag
 };
 
 struct Params {
     double omega, grav, rd, cpd, p00, beta, wgt_corr, extrap, div_damp;
 };
 
-}  // namespace nhdc
+// Everything one kernel needs about one instance (lives in device memory).
+template <class RT>
+struct Inst {
+    Grid g;
+    State s;
+    Work<RT> w;
+    Params p;
+};
 
-namespace nhdc {
+// Entity kinds of a launch, each with its own block map.
+enum Kind { KIND_EDGE = 0, KIND_CELL, KIND_VERT, KIND_COLUMN, KIND_NUM };
+
+// Block map of one launch over a batch: instance i owns global tiles
+// [off[i], off[i+1]); within it, tile t covers entity block t % nbe[i] and
+// levels [lt[i] * (t / nbe[i]), ...).
+struct Map {
+    int32_t n = 0;
+    int32_t off[MAX_INST + 1] = {0};
+    int32_t nbe[MAX_INST] = {0};
+    int32_t lt[MAX_INST] = {0};
+};
+
+// Per-launch scalars of one substep.
+struct Sub {
+    double dt[MAX_INST];
+    int32_t nsub, first;
+};
+
+// Level-tile sizes (levels per lane) of the marching kernels; 0 = whole column.
+struct Tune {
+    int lt_edge = 0, lt_cell = 0, lt_vert = 0;
+};
+
 enum KernelId { K_VT_EDGE = 0, K_VERTEX, K_CELL_VT, K_EDGE_PRED, K_COLUMN_PRED, K_EDGE_CORR,
                 K_COLUMN_CORR, K_NUM };
 extern const char *const kKernelNames[K_NUM];
 
-// Event timing of kernel launches within one nhdc_step call.
+// Event timing of kernel launches within one step call.
 struct Timing {
     bool on = false;
     std::vector<hipEvent_t> ev;   // pool: 2 per launch
@@ -93,6 +138,32 @@ struct Timing {
     double total_ms[K_NUM] = {0};
     int64_t launches[K_NUM] = {0};
 };
+
+// One set of instances advanced together (a context is a batch of one).
+struct Launcher {
+    int precision = NHDC_FP64;
+    int n = 0;
+    void *d_insts = nullptr;       // Inst<double>[n] or Inst<float>[n] in device memory
+    Map maps[KIND_NUM];
+    int64_t nblocks[KIND_NUM] = {0};
+};
+
+// kernels (nhdc_fp64.hip / nhdc_mixed.hip)
+hipError_t launch_substep_fp64(const Launcher &L, const Sub &sub, Timing *tm, hipStream_t st);
+hipError_t launch_substep_mixed(const Launcher &L, const Sub &sub, Timing *tm, hipStream_t st);
+// set-up and diagnostics (nhdc_util.hip)
+hipError_t launch_metrics(const Grid &g, const Params &p, double *gw, hipStream_t st);
+hipError_t launch_to_float(const double *src, float *dst, int64_t n, hipStream_t st);
+hipError_t launch_diag(const Grid &g, const State &s, double *part, double *out2, hipStream_t st);
+hipError_t launch_finite(const Grid &g, const State &s, int *flag, hipStream_t st);
+hipError_t launch_init_prev(const Grid &g, const State &s, hipStream_t st);
+// timing helpers (nhdc_runtime.hip); no-ops when tm is null or off
+hipError_t timing_begin(Timing *tm, int id, hipStream_t st);
+hipError_t timing_end(Timing *tm, hipStream_t st);
+// block map of one kind over a set of grids
+void build_map(Map &m, int64_t &nblocks, Kind kind, const Grid *const *grids, int n,
+               const Tune &t);
+
 }  // namespace nhdc
 
 struct nhdc_ctx {
@@ -101,21 +172,14 @@ struct nhdc_ctx {
     bool grid_ready = false, state_ready = false;
     nhdc::Grid g;
     nhdc::State s;
-    nhdc::Work w;
+    nhdc::Work<double> wd;
+    nhdc::Work<float> wf;
     nhdc::Params p{};
+    nhdc::Tune tune;
+    nhdc::Launcher L;
     nhdc::Timing tm;
+    double *red = nullptr;   // reduction partials [2 * blocks + 2]
+    int *flag = nullptr;     // finiteness flag
     std::vector<void *> allocs;
     std::string err;
 };
-
-namespace nhdc {
-// kernels (nhdc_kernels.hip)
-hipError_t launch_metrics(const Grid &g, const Params &p, hipStream_t st);
-hipError_t launch_substep(nhdc_ctx *ctx, double dts, int nsub, bool first, hipStream_t st);
-// timing helpers (no-ops unless ctx->tm.on)
-hipError_t timing_begin(nhdc_ctx *ctx, int id, hipStream_t st);
-hipError_t timing_end(nhdc_ctx *ctx, hipStream_t st);
-hipError_t launch_diag(nhdc_ctx *ctx, double *out2, hipStream_t st);
-hipError_t launch_finite(nhdc_ctx *ctx, int *flag, hipStream_t st);
-hipError_t launch_init_prev(nhdc_ctx *ctx, hipStream_t st);
-}  // namespace nhdc

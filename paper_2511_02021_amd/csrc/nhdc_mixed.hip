@@ -1,0 +1,18 @@
+// nhdc_mixed.hip -- the mixed-precision form of the substep kernels:
+// horizontal stencils and velocity tendencies in FP32 (with fused
+// multiply-add); the vertically implicit solve, the reference-state
+// perturbations, the edge fluxes, their divergences and the mass-flux
+// accumulators in FP64, as is the prognostic state.
+#include <hip/hip_runtime.h>
+
+#include "nhdc_internal.h"
+
+#pragma clang fp contract(fast)
+
+namespace nhdc {
+#include "nhdc_step.inc"
+
+hipError_t launch_substep_mixed(const Launcher &L, const Sub &sub, Timing *tm, hipStream_t st) {
+    return substep<float>(L, sub, tm, st);
+}
+}  // namespace nhdc

@@ -1,20 +1,279 @@
 // nhdc_runtime.hip -- host side of libnhdc: context, validation, stencil
-// coefficients, device memory, state transfer and the step driver.
+// coefficients, device memory, state transfer, the step driver, level-tile
+// autotuning and per-kernel timing.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <new>
+#include <sstream>
 #include <string>
 #include <vector>
 
+#include "nhdc_host.h"
 #include "nhdc_internal.h"
 
 // host-side coefficients are formed without contraction, as the operators form them
 #pragma clang fp contract(off)
 
 using namespace nhdc;
+
+namespace nhdc {
+
+int set_err(std::string &err, int code, const std::string &msg) {
+    err = msg;
+    return code;
+}
+
+int hip_fail(std::string &err, hipError_t e, const char *where) {
+    return set_err(err, NHDC_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+hipError_t timing_begin(Timing *tm, int id, hipStream_t st) {
+    if (!tm || !tm->on) return hipSuccess;
+    size_t slot = tm->ids.size();
+    while (tm->ev.size() < 2 * (slot + 1)) {
+        hipEvent_t e;
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return r;
+        tm->ev.push_back(e);
+    }
+    tm->ids.push_back(id);
+    return hipEventRecord(tm->ev[2 * slot], st);
+}
+
+hipError_t timing_end(Timing *tm, hipStream_t st) {
+    if (!tm || !tm->on) return hipSuccess;
+    return hipEventRecord(tm->ev[2 * (tm->ids.size() - 1) + 1], st);
+}
+
+hipError_t run_step(const Launcher &L, const double *dt, int nsub, Timing *tm, hipStream_t st) {
+    Sub sub;
+    for (int i = 0; i < L.n; ++i) sub.dt[i] = dt[i] / nsub;
+    for (int i = L.n; i < MAX_INST; ++i) sub.dt[i] = 0.0;
+    sub.nsub = nsub;
+    for (int s = 0; s < nsub; ++s) {
+        sub.first = s == 0;
+        hipError_t e = L.precision == NHDC_MIXED ? launch_substep_mixed(L, sub, tm, st)
+                                                 : launch_substep_fp64(L, sub, tm, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+void rebuild_maps(Launcher &L, const std::vector<nhdc_ctx *> &ctxs, const Tune &t) {
+    std::vector<const Grid *> grids;
+    for (auto *c : ctxs) grids.push_back(&c->g);
+    for (int k = 0; k < KIND_NUM; ++k)
+        build_map(L.maps[k], L.nblocks[k], Kind(k), grids.data(), int(grids.size()), t);
+}
+
+// The descriptor of one instance in the precision of its work arrays.
+template <class RT>
+static Inst<RT> make_inst(const nhdc_ctx *c, const Work<RT> &w) {
+    Inst<RT> I;
+    I.g = c->g;
+    I.s = c->s;
+    I.w = w;
+    I.p = c->p;
+    return I;
+}
+
+int upload_insts(Launcher &L, const std::vector<nhdc_ctx *> &ctxs, std::string &err) {
+    const int n = int(ctxs.size());
+    const int prec = ctxs[0]->precision;
+    std::vector<char> host;
+    if (prec == NHDC_MIXED) {
+        std::vector<Inst<float>> v;
+        for (auto *c : ctxs) v.push_back(make_inst<float>(c, c->wf));
+        const char *b = reinterpret_cast<const char *>(v.data());
+        host.assign(b, b + v.size() * sizeof(Inst<float>));
+    } else {
+        std::vector<Inst<double>> v;
+        for (auto *c : ctxs) v.push_back(make_inst<double>(c, c->wd));
+        const char *b = reinterpret_cast<const char *>(v.data());
+        host.assign(b, b + v.size() * sizeof(Inst<double>));
+    }
+    if (L.d_insts) {
+        (void)hipFree(L.d_insts);
+        L.d_insts = nullptr;
+    }
+    hipError_t e = hipMalloc(&L.d_insts, host.size());
+    if (e != hipSuccess) return set_err(err, NHDC_ENOMEM, "instance descriptors: hipMalloc failed");
+    e = hipMemcpy(L.d_insts, host.data(), host.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(err, e, "instance descriptors: hipMemcpy");
+    L.precision = prec;
+    L.n = n;
+    return NHDC_OK;
+}
+
+// ---- state snapshot (autotuning runs real steps) ----
+static void state_arrays(nhdc_ctx *c, std::vector<std::pair<double *, size_t>> &out) {
+    const size_t NC = size_t(c->g.N) * c->g.nc, NC1 = size_t(c->g.N + 1) * c->g.nc,
+                 NE = size_t(c->g.N) * c->g.ne;
+    out = {{c->s.vn, NE}, {c->s.w, NC1}, {c->s.rho, NC}, {c->s.pi, NC}, {c->s.thv, NC},
+           {c->s.pi_prev, NC}, {c->s.facc, NE}, {c->s.wacc, NC1}};
+}
+
+static int snapshot(const std::vector<nhdc_ctx *> &ctxs, std::vector<void *> &buf, bool restore,
+                    hipStream_t st, std::string &err) {
+    size_t q = 0;
+    for (auto *c : ctxs) {
+        std::vector<std::pair<double *, size_t>> arr;
+        state_arrays(c, arr);
+        for (auto &a : arr) {
+            hipError_t e;
+            if (!restore) {
+                void *b = nullptr;
+                if (hipMalloc(&b, a.second * 8) != hipSuccess) {
+                    (void)hipGetLastError();
+                    for (void *x : buf) (void)hipFree(x);
+                    buf.clear();
+                    return set_err(err, NHDC_ENOMEM, "autotune: no memory for the state snapshot");
+                }
+                buf.push_back(b);
+                e = hipMemcpyAsync(b, a.first, a.second * 8, hipMemcpyDeviceToDevice, st);
+            } else {
+                e = hipMemcpyAsync(a.first, buf[q++], a.second * 8, hipMemcpyDeviceToDevice, st);
+            }
+            if (e != hipSuccess) return hip_fail(err, e, "autotune: state copy");
+        }
+    }
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(err, e, "autotune: sync");
+    if (restore) {
+        for (void *x : buf) (void)hipFree(x);
+        buf.clear();
+    }
+    return NHDC_OK;
+}
+
+// ---- JSON cache: one entry per line, "key": [lt_edge, lt_cell, lt_vert, ms] ----
+static bool cache_lookup(const char *path, const std::string &key, double best[4]) {
+    if (!path) return false;
+    std::ifstream f(path);
+    if (!f) return false;
+    std::string line, pat = "\"" + key + "\":";
+    while (std::getline(f, line)) {
+        size_t p = line.find(pat);
+        if (p == std::string::npos) continue;
+        size_t a = line.find('[', p), b = line.find(']', p);
+        if (a == std::string::npos || b == std::string::npos) return false;
+        std::string body = line.substr(a + 1, b - a - 1);
+        for (char &ch : body)
+            if (ch == ',') ch = ' ';
+        std::istringstream is(body);
+        for (int i = 0; i < 4; ++i)
+            if (!(is >> best[i])) return false;
+        return true;
+    }
+    return false;
+}
+
+static void cache_store(const char *path, const std::string &key, const double best[4]) {
+    if (!path) return;
+    std::vector<std::string> entries;
+    {
+        std::ifstream f(path);
+        std::string line, pat = "\"" + key + "\":";
+        while (f && std::getline(f, line)) {
+            if (line.find("\":") == std::string::npos || line.find(pat) != std::string::npos) continue;
+            while (!line.empty() && (line.back() == ',' || line.back() == ' ')) line.pop_back();
+            entries.push_back(line);
+        }
+    }
+    char buf[512];
+    std::snprintf(buf, sizeof(buf), "  \"%s\": [%d, %d, %d, %.6f]", key.c_str(), int(best[0]),
+                  int(best[1]), int(best[2]), best[3]);
+    entries.push_back(buf);
+    std::ofstream f(path, std::ios::trunc);
+    f << "{\n";
+    for (size_t i = 0; i < entries.size(); ++i)
+        f << entries[i] << (i + 1 < entries.size() ? ",\n" : "\n");
+    f << "}\n";
+}
+
+int autotune(Launcher &L, Tune &tune, const std::vector<nhdc_ctx *> &ctxs, const double *dt,
+             int nsub, const char *cache_path, double *best_out, hipStream_t st,
+             std::string &err) {
+    std::ostringstream ks;
+    ks << (L.precision == NHDC_MIXED ? "mixed" : "fp64") << "|b" << BLOCK << "|";
+    for (size_t i = 0; i < ctxs.size(); ++i)
+        ks << (i ? "," : "") << ctxs[i]->g.nc << "x" << ctxs[i]->g.N;
+    const std::string key = ks.str();
+    double best[4];
+    if (cache_lookup(cache_path, key, best)) {
+        tune.lt_edge = int(best[0]);
+        tune.lt_cell = int(best[1]);
+        tune.lt_vert = int(best[2]);
+        rebuild_maps(L, ctxs, tune);
+        if (best_out)
+            for (int i = 0; i < 4; ++i) best_out[i] = best[i];
+        return NHDC_OK;
+    }
+    std::vector<void *> snap;
+    int rc = snapshot(ctxs, snap, false, st, err);
+    if (rc) return rc;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        snapshot(ctxs, snap, true, st, err);
+        return set_err(err, NHDC_EHIP, "autotune: hipEventCreate failed");
+    }
+    auto measure = [&](const Tune &t, double &ms) -> int {
+        rebuild_maps(L, ctxs, t);
+        hipError_t e = run_step(L, dt, nsub, nullptr, st);  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, st);
+        for (int r = 0; r < 2 && e == hipSuccess; ++r) e = run_step(L, dt, nsub, nullptr, st);
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float f = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&f, e0, e1);
+        if (e != hipSuccess) return hip_fail(err, e, "autotune: timed step");
+        ms = f / 2.0;
+        return NHDC_OK;
+    };
+    Tune bt = tune;
+    double bms = 0.0;
+    rc = measure(bt, bms);
+    const int cand_ec[] = {0, 48, 32, 16, 8};
+    const int cand_v[] = {0, 32, 16};
+    for (int param = 0; param < 3 && !rc; ++param) {
+        const int *cand = param < 2 ? cand_ec : cand_v;
+        const int ncand = param < 2 ? 5 : 3;
+        for (int q = 0; q < ncand; ++q) {
+            Tune t = bt;
+            int &slot = param == 0 ? t.lt_edge : param == 1 ? t.lt_cell : t.lt_vert;
+            if (slot == cand[q]) continue;
+            slot = cand[q];
+            double ms = 0.0;
+            if ((rc = measure(t, ms))) break;
+            if (ms < bms) {
+                bms = ms;
+                bt = t;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    std::string err2;
+    int rc2 = snapshot(ctxs, snap, true, st, err2);
+    if (rc) return rc;
+    if (rc2) return set_err(err, rc2, err2);
+    tune = bt;
+    rebuild_maps(L, ctxs, tune);
+    best[0] = tune.lt_edge;
+    best[1] = tune.lt_cell;
+    best[2] = tune.lt_vert;
+    best[3] = bms;
+    cache_store(cache_path, key, best);
+    if (best_out)
+        for (int i = 0; i < 4; ++i) best_out[i] = best[i];
+    return NHDC_OK;
+}
+
+}  // namespace nhdc
 
 namespace {
 
@@ -23,14 +282,10 @@ int set_err(nhdc_ctx *ctx, int code, const std::string &msg) {
     return code;
 }
 
-int hip_err(nhdc_ctx *ctx, hipError_t e, const char *where) {
-    return set_err(ctx, NHDC_EHIP, std::string(where) + ": " + hipGetErrorString(e));
-}
-
-#define HIP_TRY(ctx, call)                                      \
-    do {                                                        \
-        hipError_t e_ = (call);                                 \
-        if (e_ != hipSuccess) return hip_err((ctx), e_, #call); \
+#define HIP_TRY(ctx, call)                                                  \
+    do {                                                                    \
+        hipError_t e_ = (call);                                             \
+        if (e_ != hipSuccess) return nhdc::hip_fail((ctx)->err, e_, #call); \
     } while (0)
 
 template <class T>
@@ -56,13 +311,21 @@ int upload(nhdc_ctx *ctx, T **p, const T *host, int64_t n) {
     return NHDC_OK;
 }
 
+// FP32 copy of a device FP64 array
+int upload_f32(nhdc_ctx *ctx, float **p, const double *dsrc, int64_t n) {
+    int rc = dalloc(ctx, p, n);
+    if (rc) return rc;
+    HIP_TRY(ctx, launch_to_float(dsrc, *p, n, nullptr));
+    return NHDC_OK;
+}
+
 bool finite_pos(double x) { return std::isfinite(x) && x > 0; }
 
 int validate(nhdc_ctx *ctx, const nhdc_grid *g, const nhdc_vertical *v) {
     const int64_t nc = g->n_cells, ne = g->n_edges, nv = g->n_verts;
     if (nc <= 0 || ne <= 0 || nv <= 0) return set_err(ctx, NHDC_EGRID, "grid: empty");
     if (nv - ne + nc != 2) return set_err(ctx, NHDC_EGRID, "grid: Euler characteristic is not 2");
-    if (nc > INT32_MAX || ne > INT32_MAX || nv > INT32_MAX)
+    if (nc > INT32_MAX / 3 || ne > INT32_MAX / 3 || nv > INT32_MAX / 3)
         return set_err(ctx, NHDC_EGRID, "grid: too many entities for int32 indices");
     if (!(g->radius > 0)) return set_err(ctx, NHDC_EGRID, "grid: radius must be positive");
     const int N = v->n_lev;
@@ -123,33 +386,34 @@ int validate(nhdc_ctx *ctx, const nhdc_grid *g, const nhdc_vertical *v) {
     return NHDC_OK;
 }
 
-}  // namespace
-
-namespace nhdc {
-
-hipError_t timing_begin(nhdc_ctx *ctx, int id, hipStream_t st) {
-    Timing &t = ctx->tm;
-    if (!t.on) return hipSuccess;
-    size_t slot = t.ids.size();
-    while (t.ev.size() < 2 * (slot + 1)) {
-        hipEvent_t e;
-        hipError_t r = hipEventCreate(&e);
-        if (r != hipSuccess) return r;
-        t.ev.push_back(e);
-    }
-    t.ids.push_back(id);
-    return hipEventRecord(t.ev[2 * slot], st);
+template <class RT>
+int alloc_work(nhdc_ctx *ctx, Work<RT> &W) {
+    const int64_t nc = ctx->g.nc, ne = ctx->g.ne, nv = ctx->g.nv, N = ctx->g.N;
+    const int64_t NC = N * nc, NC1 = (N + 1) * nc, NE = N * ne, NV = N * nv, NV1 = (N + 1) * nv;
+    int rc;
+    RT **rt_c[] = {&W.kc, &W.dvn};
+    RT **rt_c1[] = {&W.wcc0, &W.tw0, &W.wcc1, &W.tw1};
+    RT **rt_e[] = {&W.vt, &W.tvn0, &W.gp};
+    for (auto q : rt_c)
+        if ((rc = dalloc(ctx, q, NC))) return rc;
+    for (auto q : rt_c1)
+        if ((rc = dalloc(ctx, q, NC1))) return rc;
+    for (auto q : rt_e)
+        if ((rc = dalloc(ctx, q, NE))) return rc;
+    if ((rc = dalloc(ctx, &W.zeta, NV))) return rc;
+    if ((rc = dalloc(ctx, &W.wv, NV1))) return rc;
+    HIP_TRY(ctx, hipMemset(W.wv, 0, sizeof(RT) * NV1));
+    double **d_c[] = {&W.rhos, &W.thvs, &W.rh, &W.ph};
+    double **d_c1[] = {&W.ws, &W.cp, &W.dp};
+    double **d_e[] = {&W.vns, &W.flx, &W.hfl};
+    for (auto q : d_c)
+        if ((rc = dalloc(ctx, q, NC))) return rc;
+    for (auto q : d_c1)
+        if ((rc = dalloc(ctx, q, NC1))) return rc;
+    for (auto q : d_e)
+        if ((rc = dalloc(ctx, q, NE))) return rc;
+    return NHDC_OK;
 }
-
-hipError_t timing_end(nhdc_ctx *ctx, hipStream_t st) {
-    Timing &t = ctx->tm;
-    if (!t.on) return hipSuccess;
-    return hipEventRecord(t.ev[2 * (t.ids.size() - 1) + 1], st);
-}
-
-}  // namespace nhdc
-
-namespace {
 
 int timing_collect(nhdc_ctx *ctx, hipStream_t s) {
     Timing &t = ctx->tm;
@@ -270,47 +534,63 @@ int nhdc_upload_grid(nhdc_ctx *ctx, const nhdc_grid *g, const nhdc_vertical *v,
     if ((rc = upload(ctx, &G.e_v, g->edge_verts, 2 * ne))) return rc;
     if ((rc = upload(ctx, &G.v_e, v_e.data(), 6 * nv))) return rc;
     if ((rc = upload(ctx, &G.v_c, v_c.data(), 6 * nv))) return rc;
-    if ((rc = upload(ctx, &G.c_sl, c_sl.data(), 3 * nc))) return rc;
-    if ((rc = upload(ctx, &G.c_area, g->cell_area, nc))) return rc;
-    if ((rc = upload(ctx, &G.c_x, g->cell_x, 3 * nc))) return rc;
-    if ((rc = upload(ctx, &G.c_dv, c_dv.data(), 9 * nc))) return rc;
-    if ((rc = upload(ctx, &G.e_de, g->dual_length, ne))) return rc;
-    if ((rc = upload(ctx, &G.e_le, g->edge_length, ne))) return rc;
-    if ((rc = upload(ctx, &G.e_t, g->edge_tangent, 3 * ne))) return rc;
-    if ((rc = upload(ctx, &G.fe, fe.data(), ne))) return rc;
-    if ((rc = upload(ctx, &G.v_sd, v_sd.data(), 6 * nv))) return rc;
-    if ((rc = upload(ctx, &G.v_m, v_m.data(), 6 * nv))) return rc;
-    if ((rc = upload(ctx, &G.v_val, v_val.data(), nv))) return rc;
-    if ((rc = upload(ctx, &G.v_area, g->vert_area, nv))) return rc;
+    Geo<double> &D = G.gd;
+    if ((rc = upload(ctx, &D.c_sl, c_sl.data(), 3 * nc))) return rc;
+    if ((rc = upload(ctx, &D.c_dv, c_dv.data(), 9 * nc))) return rc;
+    if ((rc = upload(ctx, &D.c_x, g->cell_x, 3 * nc))) return rc;
+    if ((rc = upload(ctx, &D.c_area, g->cell_area, nc))) return rc;
+    if ((rc = upload(ctx, &D.e_de, g->dual_length, ne))) return rc;
+    if ((rc = upload(ctx, &D.e_le, g->edge_length, ne))) return rc;
+    if ((rc = upload(ctx, &D.e_t, g->edge_tangent, 3 * ne))) return rc;
+    if ((rc = upload(ctx, &D.fe, fe.data(), ne))) return rc;
+    if ((rc = upload(ctx, &D.v_sd, v_sd.data(), 6 * nv))) return rc;
+    if ((rc = upload(ctx, &D.v_m, v_m.data(), 6 * nv))) return rc;
+    if ((rc = upload(ctx, &D.v_val, v_val.data(), nv))) return rc;
+    if ((rc = upload(ctx, &D.v_area, g->vert_area, nv))) return rc;
     const int64_t NC = int64_t(N) * nc, NC1 = int64_t(N + 1) * nc, NE = int64_t(N) * ne;
-    const int64_t NV = int64_t(N) * nv, NV1 = int64_t(N + 1) * nv;
+    const int64_t NV1 = int64_t(N + 1) * nv;
     if ((rc = upload(ctx, &G.zh, v->zh, NC1))) return rc;
     if ((rc = upload(ctx, &G.pi_ref, v->pi_ref, NC))) return rc;
     if ((rc = upload(ctx, &G.theta_ref, v->theta_ref, NC))) return rc;
-    if ((rc = dalloc(ctx, &G.gw, NC1))) return rc;
+    if ((rc = dalloc(ctx, &D.gw, NC1))) return rc;
     if ((rc = dalloc(ctx, &G.dref, NC1))) return rc;
     if ((rc = dalloc(ctx, &G.zhv, NV1))) return rc;
+    HIP_TRY(ctx, launch_metrics(G, ctx->p, D.gw, nullptr));
+    if (ctx->precision == NHDC_MIXED) {
+        Geo<float> &F = G.gf;
+        if ((rc = upload_f32(ctx, &F.c_sl, D.c_sl, 3 * nc))) return rc;
+        if ((rc = upload_f32(ctx, &F.c_dv, D.c_dv, 9 * nc))) return rc;
+        if ((rc = upload_f32(ctx, &F.c_x, D.c_x, 3 * nc))) return rc;
+        if ((rc = upload_f32(ctx, &F.c_area, D.c_area, nc))) return rc;
+        if ((rc = upload_f32(ctx, &F.e_de, D.e_de, ne))) return rc;
+        if ((rc = upload_f32(ctx, &F.e_le, D.e_le, ne))) return rc;
+        if ((rc = upload_f32(ctx, &F.e_t, D.e_t, 3 * ne))) return rc;
+        if ((rc = upload_f32(ctx, &F.fe, D.fe, ne))) return rc;
+        if ((rc = upload_f32(ctx, &F.v_sd, D.v_sd, 6 * nv))) return rc;
+        if ((rc = upload_f32(ctx, &F.v_m, D.v_m, 6 * nv))) return rc;
+        if ((rc = upload_f32(ctx, &F.v_val, D.v_val, nv))) return rc;
+        if ((rc = upload_f32(ctx, &F.v_area, D.v_area, nv))) return rc;
+        if ((rc = upload_f32(ctx, &F.gw, D.gw, NC1))) return rc;
+    }
 
     // ---- state, accumulators and work arrays ----
     State &S = ctx->s;
-    Work &W = ctx->w;
-    double **cellsN[] = {&S.rho, &S.pi, &S.thv, &S.pi_prev, &W.kc, &W.dvn, &W.rhos, &W.thvs,
-                         &W.rh, &W.ph};
-    double **cellsN1[] = {&S.w, &S.wacc, &W.wcc0, &W.tw0, &W.wcc1, &W.tw1, &W.ws, &W.cp, &W.dp};
-    double **edgesN[] = {&S.vn, &S.facc, &W.vt, &W.tvn0, &W.gp, &W.vns, &W.flx, &W.hfl};
+    double **cellsN[] = {&S.rho, &S.pi, &S.thv, &S.pi_prev};
     for (auto q : cellsN)
         if ((rc = dalloc(ctx, q, NC))) return rc;
-    for (auto q : cellsN1)
-        if ((rc = dalloc(ctx, q, NC1))) return rc;
-    for (auto q : edgesN)
-        if ((rc = dalloc(ctx, q, NE))) return rc;
-    if ((rc = dalloc(ctx, &W.zeta, NV))) return rc;
-    if ((rc = dalloc(ctx, &W.wv, NV1))) return rc;
-    if ((rc = dalloc(ctx, &W.red, 2 * ((nc + 255) / 256) + 2))) return rc;
-    if ((rc = dalloc(ctx, &W.flag, 1))) return rc;
-    HIP_TRY(ctx, hipMemset(W.wv, 0, sizeof(double) * NV1));
-    HIP_TRY(ctx, launch_metrics(G, ctx->p, nullptr));
+    if ((rc = dalloc(ctx, &S.w, NC1))) return rc;
+    if ((rc = dalloc(ctx, &S.wacc, NC1))) return rc;
+    if ((rc = dalloc(ctx, &S.vn, NE))) return rc;
+    if ((rc = dalloc(ctx, &S.facc, NE))) return rc;
+    if (ctx->precision == NHDC_MIXED) rc = alloc_work<float>(ctx, ctx->wf);
+    else rc = alloc_work<double>(ctx, ctx->wd);
+    if (rc) return rc;
+    if ((rc = dalloc(ctx, &ctx->red, 2 * ((nc + BLOCK - 1) / BLOCK) + 2))) return rc;
+    if ((rc = dalloc(ctx, &ctx->flag, 1))) return rc;
     HIP_TRY(ctx, hipDeviceSynchronize());
+    std::vector<nhdc_ctx *> one{ctx};
+    if ((rc = upload_insts(ctx->L, one, ctx->err))) return rc;
+    rebuild_maps(ctx->L, one, ctx->tune);
     ctx->grid_ready = true;
     return NHDC_OK;
 }
@@ -333,7 +613,7 @@ int nhdc_init_state(nhdc_ctx *ctx, const nhdc_state_view *st, void *stream) {
     HIP_TRY(ctx, hipMemcpyAsync(ctx->s.pi, st->pi, NC, kind, s));
     HIP_TRY(ctx, hipMemcpyAsync(ctx->s.thv, st->theta_v, NC, kind, s));
     if (st->pi_prev) HIP_TRY(ctx, hipMemcpyAsync(ctx->s.pi_prev, st->pi_prev, NC, kind, s));
-    else HIP_TRY(ctx, launch_init_prev(ctx, s));
+    else HIP_TRY(ctx, launch_init_prev(ctx->g, ctx->s, s));
     HIP_TRY(ctx, hipMemsetAsync(ctx->s.facc, 0, NE, s));
     HIP_TRY(ctx, hipMemsetAsync(ctx->s.wacc, 0, NC1, s));
     if (!st->on_device) HIP_TRY(ctx, hipStreamSynchronize(s));
@@ -348,32 +628,34 @@ int nhdc_step(nhdc_ctx *ctx, double dt, int nsub, void *stream) {
     if (!ctx->state_ready) return set_err(ctx, NHDC_ESTATE, "step: state not initialised");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const double dts = dt / nsub;
     ctx->tm.ids.clear();
-    for (int i = 0; i < nsub; ++i) HIP_TRY(ctx, launch_substep(ctx, dts, nsub, i == 0, s));
+    HIP_TRY(ctx, run_step(ctx->L, &dt, nsub, &ctx->tm, s));
     return timing_collect(ctx, s);
 }
 
-int nhdc_set_timing(nhdc_ctx *ctx, int enable) {
+int nhdc_set_tiles(nhdc_ctx *ctx, int lt_edge, int lt_cell, int lt_vert) {
     if (!ctx) return NHDC_EINVAL;
-    ctx->tm.on = enable != 0;
-    ctx->tm.ids.clear();
-    for (int k = 0; k < K_NUM; ++k) {
-        ctx->tm.total_ms[k] = 0.0;
-        ctx->tm.launches[k] = 0;
-    }
+    if (!ctx->grid_ready) return set_err(ctx, NHDC_ESTATE, "set_tiles: no grid uploaded");
+    if (lt_edge < 0 || lt_cell < 0 || lt_vert < 0)
+        return set_err(ctx, NHDC_EINVAL, "set_tiles: tiles must be >= 0");
+    ctx->tune.lt_edge = lt_edge;
+    ctx->tune.lt_cell = lt_cell;
+    ctx->tune.lt_vert = lt_vert;
+    std::vector<nhdc_ctx *> one{ctx};
+    rebuild_maps(ctx->L, one, ctx->tune);
     return NHDC_OK;
 }
 
-int nhdc_kernel_count(void) { return K_NUM; }
-
-int nhdc_kernel_stats(const nhdc_ctx *ctx, int index, const char **name, double *total_ms,
-                      int64_t *launches) {
-    if (!ctx || index < 0 || index >= K_NUM) return NHDC_EINVAL;
-    if (name) *name = kKernelNames[index];
-    if (total_ms) *total_ms = ctx->tm.total_ms[index];
-    if (launches) *launches = ctx->tm.launches[index];
-    return NHDC_OK;
+int nhdc_autotune(nhdc_ctx *ctx, double dt, int nsub, const char *cache_path, double *best,
+                  void *stream) {
+    if (!ctx) return NHDC_EINVAL;
+    if (!(dt > 0) || !std::isfinite(dt) || nsub < 1)
+        return set_err(ctx, NHDC_EINVAL, "autotune: bad dt or nsubsteps");
+    if (!ctx->state_ready) return set_err(ctx, NHDC_ESTATE, "autotune: state not initialised");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    std::vector<nhdc_ctx *> one{ctx};
+    return autotune(ctx->L, ctx->tune, one, &dt, nsub, cache_path, best,
+                    static_cast<hipStream_t>(stream), ctx->err);
 }
 
 int nhdc_get_state(nhdc_ctx *ctx, const nhdc_state_view *dst, void *stream) {
@@ -414,8 +696,8 @@ int nhdc_diag(nhdc_ctx *ctx, double *mass, double *rho_theta, void *stream) {
     if (!ctx->state_ready) return set_err(ctx, NHDC_ESTATE, "diag: state not initialised");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
-    double *out = ctx->w.red + 2 * ((ctx->g.nc + 255) / 256);
-    HIP_TRY(ctx, launch_diag(ctx, out, s));
+    double *out = ctx->red + 2 * ((ctx->g.nc + BLOCK - 1) / BLOCK);
+    HIP_TRY(ctx, launch_diag(ctx->g, ctx->s, ctx->red, out, s));
     double h[2];
     HIP_TRY(ctx, hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
@@ -429,10 +711,10 @@ int nhdc_check_finite(nhdc_ctx *ctx, void *stream) {
     if (!ctx->state_ready) return set_err(ctx, NHDC_ESTATE, "check_finite: state not initialised");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
-    HIP_TRY(ctx, hipMemsetAsync(ctx->w.flag, 0, sizeof(int), s));
-    HIP_TRY(ctx, launch_finite(ctx, ctx->w.flag, s));
+    HIP_TRY(ctx, hipMemsetAsync(ctx->flag, 0, sizeof(int), s));
+    HIP_TRY(ctx, launch_finite(ctx->g, ctx->s, ctx->flag, s));
     int h = 0;
-    HIP_TRY(ctx, hipMemcpyAsync(&h, ctx->w.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipMemcpyAsync(&h, ctx->flag, sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
     if (h) return set_err(ctx, NHDC_EUNSTABLE, "check_finite: non-finite value in the state");
     return NHDC_OK;
@@ -448,12 +730,35 @@ int nhdc_sizes(const nhdc_ctx *ctx, int64_t *n_cells, int64_t *n_edges, int64_t 
     return NHDC_OK;
 }
 
+int nhdc_set_timing(nhdc_ctx *ctx, int enable) {
+    if (!ctx) return NHDC_EINVAL;
+    ctx->tm.on = enable != 0;
+    ctx->tm.ids.clear();
+    for (int k = 0; k < K_NUM; ++k) {
+        ctx->tm.total_ms[k] = 0.0;
+        ctx->tm.launches[k] = 0;
+    }
+    return NHDC_OK;
+}
+
+int nhdc_kernel_count(void) { return K_NUM; }
+
+int nhdc_kernel_stats(const nhdc_ctx *ctx, int index, const char **name, double *total_ms,
+                      int64_t *launches) {
+    if (!ctx || index < 0 || index >= K_NUM) return NHDC_EINVAL;
+    if (name) *name = kKernelNames[index];
+    if (total_ms) *total_ms = ctx->tm.total_ms[index];
+    if (launches) *launches = ctx->tm.launches[index];
+    return NHDC_OK;
+}
+
 const char *nhdc_last_error(const nhdc_ctx *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
 
 void nhdc_destroy(nhdc_ctx *ctx) {
     if (!ctx) return;
     if (hipSetDevice(ctx->device) == hipSuccess) {
         for (hipEvent_t e : ctx->tm.ev) (void)hipEventDestroy(e);
+        if (ctx->L.d_insts) (void)hipFree(ctx->L.d_insts);
         for (void *q : ctx->allocs) (void)hipFree(q);
     }
     delete ctx;

@@ -1,0 +1,182 @@
+// nhdc_util.hip -- set-up and diagnostic kernels of libnhdc (not on the step
+// path): vertical interpolation weights and reference derivative, vertex
+// heights, FP32 copies of coefficients, the initial Exner history, the
+// deterministic mass sums and the finiteness check.  No contraction, so the
+// metrics equal their plain FP64 definitions.
+#include <hip/hip_runtime.h>
+
+#include "nhdc_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace nhdc {
+namespace {
+
+__device__ __forceinline__ int64_t lin() { return int64_t(blockIdx.x) * BLOCK + threadIdx.x; }
+
+inline unsigned nb(int64_t n) { return unsigned((n + BLOCK - 1) / BLOCK); }
+
+__global__ void k_metrics_cell(int64_t nc, int N, const double *__restrict__ zh,
+                               const double *__restrict__ theta_ref, double grav, double cpd,
+                               double *__restrict__ gw, double *__restrict__ dref) {
+    int64_t c = lin();
+    if (c >= nc) return;
+    gw[c] = 0.0;
+    dref[c] = 0.0;
+    gw[int64_t(N) * nc + c] = 0.0;
+    dref[int64_t(N) * nc + c] = 0.0;
+    for (int i = 1; i < N; ++i) {
+        double za = 0.5 * (zh[int64_t(i - 1) * nc + c] + zh[int64_t(i) * nc + c]);
+        double zb = 0.5 * (zh[int64_t(i) * nc + c] + zh[int64_t(i + 1) * nc + c]);
+        double g = (za - zh[int64_t(i) * nc + c]) / (za - zb);
+        gw[int64_t(i) * nc + c] = g;
+        double th = g * theta_ref[int64_t(i) * nc + c] + (1.0 - g) * theta_ref[int64_t(i - 1) * nc + c];
+        dref[int64_t(i) * nc + c] = -grav / (cpd * th);
+    }
+}
+
+__global__ void k_metrics_vert(int64_t nv, int64_t nc, int N, const int32_t *__restrict__ v_c,
+                               const double *__restrict__ v_m, const double *__restrict__ v_val,
+                               const double *__restrict__ zh, double *__restrict__ zhv) {
+    int64_t v = lin();
+    if (v >= nv) return;
+    for (int i = 0; i <= N; ++i) {
+        const double *z = zh + int64_t(i) * nc;
+        double s = 0.0;
+        for (int j = 0; j < 6; ++j) s += v_m[j * nv + v] * z[v_c[j * nv + v]];
+        zhv[int64_t(i) * nv + v] = s / v_val[v];
+    }
+}
+
+__global__ void k_to_float(const double *__restrict__ src, float *__restrict__ dst, int64_t n) {
+    int64_t i = lin();
+    if (i < n) dst[i] = float(src[i]);
+}
+
+__global__ void k_init_prev(int64_t n, const double *__restrict__ pi, const double *__restrict__ pi_ref,
+                            double *__restrict__ prev) {
+    int64_t i = lin();
+    if (i < n) prev[i] = pi[i] - pi_ref[i];
+}
+
+// fixed-order two-level reduction: per-block partials, then one block
+__global__ void k_diag_partial(int64_t nc, int N, const double *__restrict__ area,
+                               const double *__restrict__ zh, const double *__restrict__ rho,
+                               const double *__restrict__ thv, double *__restrict__ part) {
+    __shared__ double s1[BLOCK], s2[BLOCK];
+    int64_t c = lin();
+    double a = 0.0, b = 0.0;
+    if (c < nc) {
+        for (int k = 0; k < N; ++k) {
+            double vol = area[c] * (zh[int64_t(k) * nc + c] - zh[int64_t(k + 1) * nc + c]);
+            double r = rho[int64_t(k) * nc + c];
+            a += vol * r;
+            b += vol * r * thv[int64_t(k) * nc + c];
+        }
+    }
+    s1[threadIdx.x] = a;
+    s2[threadIdx.x] = b;
+    __syncthreads();
+    for (int w = BLOCK / 2; w > 0; w >>= 1) {
+        if (int(threadIdx.x) < w) {
+            s1[threadIdx.x] += s1[threadIdx.x + w];
+            s2[threadIdx.x] += s2[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = s1[0];
+        part[2 * blockIdx.x + 1] = s2[0];
+    }
+}
+
+__global__ void k_diag_final(int nparts, const double *__restrict__ part, double *__restrict__ out) {
+    __shared__ double s1[BLOCK], s2[BLOCK];
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += BLOCK) {
+        a += part[2 * i];
+        b += part[2 * i + 1];
+    }
+    s1[threadIdx.x] = a;
+    s2[threadIdx.x] = b;
+    __syncthreads();
+    for (int w = BLOCK / 2; w > 0; w >>= 1) {
+        if (int(threadIdx.x) < w) {
+            s1[threadIdx.x] += s1[threadIdx.x + w];
+            s2[threadIdx.x] += s2[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = s1[0];
+        out[1] = s2[0];
+    }
+}
+
+__global__ void k_finite(int64_t n, const double *__restrict__ x, int *__restrict__ flag) {
+    int64_t i = lin();
+    if (i < n && !isfinite(x[i])) flag[0] = 1;  // benign race: every writer stores 1
+}
+
+}  // namespace
+
+hipError_t launch_metrics(const Grid &g, const Params &p, double *gw, hipStream_t st) {
+    hipLaunchKernelGGL(k_metrics_cell, dim3(nb(g.nc)), dim3(BLOCK), 0, st, g.nc, g.N, g.zh,
+                       g.theta_ref, p.grav, p.cpd, gw, g.dref);
+    hipLaunchKernelGGL(k_metrics_vert, dim3(nb(g.nv)), dim3(BLOCK), 0, st, g.nv, g.nc, g.N, g.v_c,
+                       g.gd.v_m, g.gd.v_val, g.zh, g.zhv);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_float(const double *src, float *dst, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_to_float, dim3(nb(n)), dim3(BLOCK), 0, st, src, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_prev(const Grid &g, const State &s, hipStream_t st) {
+    int64_t n = int64_t(g.N) * g.nc;
+    hipLaunchKernelGGL(k_init_prev, dim3(nb(n)), dim3(BLOCK), 0, st, n, s.pi, g.pi_ref, s.pi_prev);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag(const Grid &g, const State &s, double *part, double *out2, hipStream_t st) {
+    unsigned n = nb(g.nc);
+    hipLaunchKernelGGL(k_diag_partial, dim3(n), dim3(BLOCK), 0, st, g.nc, g.N, g.gd.c_area, g.zh,
+                       s.rho, s.thv, part);
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(BLOCK), 0, st, int(n), part, out2);
+    return hipGetLastError();
+}
+
+hipError_t launch_finite(const Grid &g, const State &s, int *flag, hipStream_t st) {
+    const int64_t NC = int64_t(g.N) * g.nc, NC1 = int64_t(g.N + 1) * g.nc, NE = int64_t(g.N) * g.ne;
+    const double *arrs[4] = {s.rho, s.pi, s.thv, s.pi_prev};
+    for (int i = 0; i < 4; ++i)
+        hipLaunchKernelGGL(k_finite, dim3(nb(NC)), dim3(BLOCK), 0, st, NC, arrs[i], flag);
+    hipLaunchKernelGGL(k_finite, dim3(nb(NC1)), dim3(BLOCK), 0, st, NC1, s.w, flag);
+    hipLaunchKernelGGL(k_finite, dim3(nb(NE)), dim3(BLOCK), 0, st, NE, s.vn, flag);
+    return hipGetLastError();
+}
+
+const char *const kKernelNames[K_NUM] = {"vt_edge", "vertex", "cell_vt", "edge_pred",
+                                         "column_pred", "edge_corr", "column_corr"};
+
+void build_map(Map &m, int64_t &nblocks, Kind kind, const Grid *const *grids, int n,
+               const Tune &t) {
+    m.n = n;
+    m.off[0] = 0;
+    for (int i = 0; i < n; ++i) {
+        const Grid &g = *grids[i];
+        int64_t ent = kind == KIND_EDGE ? g.ne : kind == KIND_VERT ? g.nv : g.nc;
+        int lt = kind == KIND_EDGE ? t.lt_edge : kind == KIND_VERT ? t.lt_vert
+               : kind == KIND_CELL ? t.lt_cell : 0;
+        if (lt <= 0 || lt > g.N) lt = g.N;
+        int64_t nbe = (ent + BLOCK - 1) / BLOCK;
+        int64_t tiles = (g.N + lt - 1) / lt;
+        m.nbe[i] = int32_t(nbe);
+        m.lt[i] = lt;
+        m.off[i + 1] = int32_t(m.off[i] + nbe * tiles);
+    }
+    nblocks = m.off[n];
+}
+
+}  // namespace nhdc

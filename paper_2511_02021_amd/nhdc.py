@@ -18,8 +18,10 @@ ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EGRID", -5: "ESTATE", -6:
 
 EXPORTS = ("nhdc_create", "nhdc_upload_grid", "nhdc_init_state", "nhdc_step", "nhdc_get_state",
            "nhdc_get_mass_flux", "nhdc_diag", "nhdc_check_finite", "nhdc_sizes",
-           "nhdc_set_timing", "nhdc_kernel_count", "nhdc_kernel_stats", "nhdc_last_error",
-           "nhdc_destroy")
+           "nhdc_set_tiles", "nhdc_autotune", "nhdc_set_timing", "nhdc_kernel_count",
+           "nhdc_kernel_stats", "nhdc_last_error", "nhdc_destroy", "nhdc_batch_create",
+           "nhdc_batch_step", "nhdc_batch_set_tiles", "nhdc_batch_autotune",
+           "nhdc_batch_last_error", "nhdc_batch_destroy")
 
 
 class NhdcError(RuntimeError):
@@ -80,6 +82,16 @@ def lib():
         L.nhdc_diag.argtypes = [vp, vp, vp, vp]
         L.nhdc_check_finite.argtypes = [vp, vp]
         L.nhdc_sizes.argtypes = [vp] + [vp] * 4
+        L.nhdc_set_tiles.argtypes = [vp, i, i, i]
+        L.nhdc_autotune.argtypes = [vp, d, i, C.c_char_p, C.POINTER(d), vp]
+        L.nhdc_batch_create.argtypes = [C.POINTER(vp), C.POINTER(vp), i]
+        L.nhdc_batch_step.argtypes = [vp, C.POINTER(d), i, i, vp]
+        L.nhdc_batch_set_tiles.argtypes = [vp, i, i, i]
+        L.nhdc_batch_autotune.argtypes = [vp, C.POINTER(d), i, C.c_char_p, C.POINTER(d), vp]
+        L.nhdc_batch_last_error.argtypes = [vp]
+        L.nhdc_batch_last_error.restype = C.c_char_p
+        L.nhdc_batch_destroy.argtypes = [vp]
+        L.nhdc_batch_destroy.restype = None
         L.nhdc_set_timing.argtypes = [vp, i]
         L.nhdc_kernel_count.argtypes = []
         L.nhdc_kernel_stats.argtypes = [vp, i, C.POINTER(C.c_char_p), C.POINTER(d),
@@ -228,6 +240,19 @@ class Dycore:
     def check_finite(self):
         self._check(self.L.nhdc_check_finite(self.h, _stream_ptr(None)))
 
+    def set_tiles(self, lt_edge=0, lt_cell=0, lt_vert=0):
+        """Levels per lane of the marching kernels (0 = whole column)."""
+        self._check(self.L.nhdc_set_tiles(self.h, int(lt_edge), int(lt_cell), int(lt_vert)))
+
+    def autotune(self, dt, nsub, cache_path=None, stream=None):
+        """Search the level tiles by timing whole steps; the state is restored.
+        Returns (lt_edge, lt_cell, lt_vert, ms_per_step)."""
+        best = (C.c_double * 4)()
+        path = cache_path.encode() if cache_path else None
+        self._check(self.L.nhdc_autotune(self.h, float(dt), int(nsub), path, best,
+                                         _stream_ptr(stream)))
+        return int(best[0]), int(best[1]), int(best[2]), best[3]
+
     def set_timing(self, on):
         self._check(self.L.nhdc_set_timing(self.h, int(bool(on))))
 
@@ -239,6 +264,54 @@ class Dycore:
             self._check(self.L.nhdc_kernel_stats(self.h, k, C.byref(name), C.byref(ms), C.byref(n)))
             out[name.value.decode()] = (ms.value, n.value)
         return out
+
+
+class Batch:
+    """Several Dycore instances (same device and precision, any sizes) advanced
+    together: one launch per kernel over all of them, each step replayed from a
+    captured HIP graph.  The instances must outlive the batch."""
+
+    def __init__(self, dycores):
+        self.L = lib()
+        self.members = list(dycores)
+        arr = (C.c_void_p * len(self.members))(*[d.h for d in self.members])
+        h = C.c_void_p()
+        rc = self.L.nhdc_batch_create(C.byref(h), arr, len(self.members))
+        if rc != 0:
+            raise NhdcError(rc, "nhdc_batch_create failed (instances must share device and "
+                                "precision, have grid and state, and number 1..64)")
+        self.h = h
+
+    def _check(self, rc):
+        if rc != 0:
+            raise NhdcError(rc, self.L.nhdc_batch_last_error(self.h).decode())
+
+    def _dts(self, dt):
+        dts = [float(x) for x in (dt if hasattr(dt, "__len__") else [dt] * len(self.members))]
+        assert len(dts) == len(self.members)
+        return (C.c_double * len(dts))(*dts)
+
+    def step(self, dt, nsub, nsteps=1, stream=None):
+        self._check(self.L.nhdc_batch_step(self.h, self._dts(dt), int(nsub), int(nsteps),
+                                           _stream_ptr(stream)))
+
+    def set_tiles(self, lt_edge=0, lt_cell=0, lt_vert=0):
+        self._check(self.L.nhdc_batch_set_tiles(self.h, int(lt_edge), int(lt_cell), int(lt_vert)))
+
+    def autotune(self, dt, nsub, cache_path=None, stream=None):
+        best = (C.c_double * 4)()
+        path = cache_path.encode() if cache_path else None
+        self._check(self.L.nhdc_batch_autotune(self.h, self._dts(dt), int(nsub), path, best,
+                                               _stream_ptr(stream)))
+        return int(best[0]), int(best[1]), int(best[2]), best[3]
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.nhdc_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
 
 
 def exported_symbols(path=None):

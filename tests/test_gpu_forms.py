@@ -1,0 +1,208 @@
+"""The other forms of the path through the C-ABI: level tiles and autotuning
+(result-neutral), batching of uneven instances in one launch per kernel with
+graph replay (bitwise equal to each instance alone, and so to the oracle in
+FP64), and the FP32-mixed form (per-field error against FP64 next to the
+FP32-rounding floor; FP64 mass fluxes keep mass conserved)."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2511_02021_amd.inputs import case as CS
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("vn", "w", "rho", "pi", "theta_v", "pi_prev")
+
+
+def _nhdc():
+    from paper_2511_02021_amd import nhdc
+    return nhdc
+
+
+def _run(case, steps, precision="fp64", tiles=None, state=None):
+    d = _nhdc().Dycore(case, precision=precision)
+    if state is not None:
+        d.init_state(*[state[f] for f in ("vn", "w", "rho", "pi", "theta_v")])
+    if tiles:
+        d.set_tiles(*tiles)
+    for _ in range(steps):
+        d.step(case.dt, case.nsub)
+    s = d.get_state()
+    f = d.mass_flux()
+    m = d.diag()
+    d.close()
+    return s, f, m
+
+
+def test_level_tiles_are_result_neutral():
+    c = CS.config_case(2, k=4, n_lev=30)
+    ref, rf, _ = _run(c, 3)
+    for tiles in ((16, 0, 0), (0, 8, 0), (0, 0, 16), (8, 8, 8), (7, 13, 5)):
+        s, f, _ = _run(c, 3, tiles=tiles)
+        for fld in FIELDS:
+            assert np.array_equal(s[fld], ref[fld]), (tiles, fld)
+        assert np.array_equal(f[0], rf[0]) and np.array_equal(f[1], rf[1])
+
+
+def _batch_cases():
+    return [CS.make_case(3, 20, z_top=30000.0, noise_seed=[0, 4, 0], dt=300.0),
+            CS.make_case(4, 30, z_top=75000.0, stretch=1.6, terrain_seed=[1, 4, 1],
+                         noise_seed=[0, 4, 1], dt=150.0),
+            CS.make_case(3, 45, z_top=75000.0, stretch=1.6, terrain_seed=[1, 4, 2],
+                         noise_seed=[0, 4, 2], dt=300.0)]
+
+
+@pytest.mark.parametrize("tiles", [None, (16, 8, 16)])
+def test_batch_equals_each_instance_and_oracle(tiles):
+    nhdc = _nhdc()
+    cases = _batch_cases()
+    ds = [nhdc.Dycore(c) for c in cases]
+    b = nhdc.Batch(ds)
+    if tiles:
+        b.set_tiles(*tiles)
+    b.step([c.dt for c in cases], 5, nsteps=3)
+    for c, d in zip(cases, ds):
+        s = d.get_state()
+        m = oracle.Model(c)
+        for _ in range(3):
+            m.step(c.dt, 5)
+        o = m.state()
+        for f in FIELDS:
+            assert np.array_equal(s[f], o[f]), (c.grid.k, c.n_lev, f)
+    b.close()
+    for d in ds:
+        d.close()
+
+
+def test_batch_graph_replay_after_changes():
+    """Replays of the captured step, a change of dt (new capture) and a second
+    batch over the same instances keep the bitwise agreement."""
+    nhdc = _nhdc()
+    cases = _batch_cases()
+    ds = [nhdc.Dycore(c) for c in cases]
+    b = nhdc.Batch(ds)
+    dts = [c.dt for c in cases]
+    b.step(dts, 5, nsteps=2)
+    b.step([x / 2 for x in dts], 5, nsteps=1)
+    b.step(dts, 5, nsteps=1)
+    b.close()
+    b2 = nhdc.Batch(ds[:2])
+    b2.step(dts[:2], 5, nsteps=1)
+    b2.close()
+    for i, (c, d) in enumerate(zip(cases, ds)):
+        m = oracle.Model(c)
+        seq = [c.dt, c.dt, c.dt / 2, c.dt] + ([c.dt] if i < 2 else [])
+        for dt in seq:
+            m.step(dt, 5)
+        o, s = m.state(), d.get_state()
+        for f in FIELDS:
+            assert np.array_equal(s[f], o[f]), (i, f)
+    for d in ds:
+        d.close()
+
+
+def test_batch_argument_errors():
+    nhdc = _nhdc()
+    c = CS.config_case(1, k=2)
+    d = nhdc.Dycore(c)
+    with pytest.raises(nhdc.NhdcError):
+        nhdc.Batch([d, d])                      # same instance twice
+    dm = nhdc.Dycore(c, precision="mixed")
+    with pytest.raises(nhdc.NhdcError):
+        nhdc.Batch([d, dm])                     # mixed precisions
+    b = nhdc.Batch([d])
+    with pytest.raises(nhdc.NhdcError) as ei:
+        b.step([-1.0], 5)
+    assert ei.value.code == -1
+    b.close()
+    d.close()
+    dm.close()
+
+
+def test_autotune_restores_state_and_caches(tmp_path):
+    nhdc = _nhdc()
+    c = CS.config_case(2, k=4, n_lev=30)
+    d = nhdc.Dycore(c)
+    d.step(c.dt, 5)
+    before = d.get_state()
+    path = str(tmp_path / "tune.json")
+    best = d.autotune(c.dt, 5, cache_path=path)
+    after = d.get_state()
+    for f in FIELDS:
+        assert np.array_equal(before[f], after[f]), f
+    assert all(t in (0, 48, 32, 16, 8) for t in best[:3]) and best[3] > 0
+    txt = open(path).read()
+    assert "fp64|b256|" in txt and str(c.grid.n_cells) in txt
+    again = d.autotune(c.dt, 5, cache_path=path)   # cache hit: same tiles, no search
+    assert again[:3] == best[:3] and abs(again[3] - best[3]) < 1e-5
+    d.step(c.dt, 5)
+    ref, _, _ = _run(c, 2)
+    s = d.get_state()
+    for f in FIELDS:
+        assert np.array_equal(s[f], ref[f]), f
+    d.close()
+
+
+def _rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def mixed_error_table(case, steps, seed=7):
+    """E_f: rel-L2 of (mixed - FP64) per field; S_f: the same norm between two
+    FP64 runs whose initial states differ by seeded relative noise 2^-24.
+    Both normalised by ||FP64|| and by ||FP64 - initial|| (the signal)."""
+    init = dict(vn=case.vn, w=case.w, rho=case.rho, pi=case.pi, theta_v=case.theta_v)
+    f64, _, _ = _run(case, steps)
+    mix, _, mm = _run(case, steps, precision="mixed")
+    rng = np.random.default_rng(seed)
+    pert = {k: v * (1.0 + 2.0 ** -24 * rng.standard_normal(v.shape)) for k, v in init.items()}
+    f64p, _, _ = _run(case, steps, state=pert)
+    table = {}
+    for f in ("vn", "w", "rho", "pi", "theta_v"):
+        signal = f64[f] - init[f]
+        table[f] = dict(
+            E=_rel_l2(mix[f], f64[f]), S=_rel_l2(f64p[f], f64[f]),
+            E_signal=float(np.linalg.norm(mix[f] - f64[f]) / max(np.linalg.norm(signal), 1e-300)),
+            S_signal=float(np.linalg.norm(f64p[f] - f64[f]) / max(np.linalg.norm(signal), 1e-300)))
+    return table, mix
+
+
+def test_mixed_form_error_and_conservation():
+    c = CS.config_case(3, k=4, n_lev=30)   # the mixed-form recipe (terrain, 90-level stretch scaled)
+    table, _ = mixed_error_table(c, 10)
+    for f, r in table.items():
+        print(f"mixed {f}: E={r['E']:.2e} S={r['S']:.2e} E/signal={r['E_signal']:.2e} "
+              f"S/signal={r['S_signal']:.2e}", flush=True)
+    for f, r in table.items():
+        # FP32 stencils vs the FP32-rounding floor of the same fields
+        assert r["E"] <= max(100.0 * r["S"], 1e-9), (f, r)
+        assert r["E_signal"] < 1e-4, (f, r)
+    # mass and rho*theta_v stay conserved to FP64 round-off (fluxes are FP64)
+    d = _nhdc().Dycore(c, precision="mixed")
+    m0, r0 = d.diag()
+    for _ in range(10):
+        d.step(c.dt, 5)
+    m1, r1 = d.diag()
+    d.close()
+    assert abs(m1 / m0 - 1) <= 1e-13 and abs(r1 / r0 - 1) <= 1e-13
+
+
+def test_mixed_batch_equals_mixed_alone():
+    nhdc = _nhdc()
+    cases = _batch_cases()
+    alone = []
+    for c in cases:
+        s, _, _ = _run(c, 2, precision="mixed")
+        alone.append(s)
+    ds = [nhdc.Dycore(c, precision="mixed") for c in cases]
+    b = nhdc.Batch(ds)
+    b.step([c.dt for c in cases], 5, nsteps=2)
+    for d, ref in zip(ds, alone):
+        s = d.get_state()
+        for f in FIELDS:
+            assert np.array_equal(s[f], ref[f]), f
+    b.close()
+    for d in ds:
+        d.close()
