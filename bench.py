@@ -337,6 +337,141 @@ def bench_batch(args, torch, nhdc, CS):
             "sequential_ms": res}
 
 
+# ---------------------------------------------------------------------------
+# rocprofv3 summaries (profiles/): the commands that make the raw CSVs, and the
+# reduction of those CSVs to the short text files kept in the repository.
+
+PROFILE_CMDS = {
+    "trace": "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_trace -o trace "
+             "-- python3 -u bench.py --steps 10 --warmup 2 --timing-steps 4 --error-steps 0 "
+             "--no-cpu-baseline > gpurun_out/prof_trace.json",
+    "fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof_fetch -o fetch "
+             "-- python3 -u bench.py --steps 2 --warmup 1 --timing-steps 1 --error-steps 0 "
+             "--no-cpu-baseline --copy-calibration > gpurun_out/prof_fetch.json",
+    "write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof_write -o write "
+             "-- python3 -u bench.py --steps 2 --warmup 1 --timing-steps 1 --error-steps 0 "
+             "--no-cpu-baseline --copy-calibration > gpurun_out/prof_write.json",
+}
+
+
+def _kernel_id(name):
+    """rocprofv3 kernel name -> (kernel id as in kernel_stats, precision)."""
+    m = re.search(r"k_(vt_edge|vertex|cell_vt|edge_pred|edge_corr|column)<(double|float)(?:, (true|false))?>",
+                  name)
+    if not m:
+        return None, None
+    k = m.group(1)
+    if k == "column":
+        k = "column_corr" if m.group(3) == "true" else "column_pred"
+    return k, ("fp64" if m.group(2) == "double" else "mixed")
+
+
+def profile_summary(src, dst):
+    """Reduce the rocprofv3 CSVs under `src` (made by PROFILE_CMDS) to the
+    text summaries under `dst`: per-kernel durations, and HBM bytes per launch
+    from FETCH_SIZE / WRITE_SIZE scaled by what the same counters read for the
+    1 GiB device copy of the calibration."""
+    import csv
+    from collections import defaultdict
+
+    def rows(path):
+        with open(path) as f:
+            return list(csv.DictReader(f))
+
+    runs = {k: json.load(open(os.path.join(src, f"prof_{k}.json"))) for k in PROFILE_CMDS}
+    hashes = {r["kernel_source_sha256_16"] for r in runs.values()}
+    if len(hashes) != 1:
+        raise SystemExit(f"profiled runs used different kernel sources: {hashes}")
+    src_hash = hashes.pop()
+    cfg = runs["trace"]["config"]
+    nc, N = cfg["cells"], cfg["levels"]
+    ne, nv = nc * 3 // 2, nc // 2 + 2
+    wl = f"R2B6x90 ({nc} cells x {N} levels, dt 90 s, 5 substeps)"
+    # ---- kernel trace ----
+    stats = rows(os.path.join(src, "prof_trace", "trace_kernel_stats.csv"))
+    lines = [f"# rocprofv3 kernel trace: dycore substep kernels, {wl}",
+             f"kernel_source_sha256_16: {src_hash}",
+             f"command: {PROFILE_CMDS['trace']}",
+             f"summarised by: python3 bench.py --profile-summary gpurun_out",
+             "", "## per instantiation (rocprofv3 --stats)",
+             f"{'kernel':24s} {'form':6s} {'calls':>6s} {'avg_us':>9s} {'min_us':>9s} {'max_us':>9s} {'share%':>7s}"]
+    agg = defaultdict(lambda: [0.0, 0])
+    for r in stats:
+        k, prec = _kernel_id(r["Name"])
+        if not k:
+            continue
+        var = k
+        if k == "cell_vt":
+            var = "cell_vt(" + ("corr" if "true>" in r["Name"] else "pred") + ")"
+        lines.append(f"{var:24s} {prec:6s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:9.2f} "
+                     f"{float(r['MinNs']) / 1e3:9.2f} {float(r['MaxNs']) / 1e3:9.2f} "
+                     f"{float(r['Percentage']):7.2f}")
+        agg[(k, prec)][0] += float(r["TotalDurationNs"])
+        agg[(k, prec)][1] += int(r["Calls"])
+    lines += ["", "## per kernel id, against the HIP-event averages bench.py measured in the same run",
+              f"{'kernel':14s} {'form':6s} {'rocprof_avg_us':>15s} {'hip_event_avg_us':>17s} {'diff%':>7s}"]
+    ev = {"fp64": runs["trace"]["kernels"]}
+    for (k, prec), (tot, n) in sorted(agg.items(), key=lambda kv: (kv[0][1], -kv[1][0])):
+        a = tot / n / 1e3
+        e = ev.get(prec, {}).get(k, {}).get("avg_ms")
+        if e is None:
+            lines.append(f"{k:14s} {prec:6s} {a:15.2f} {'-':>17s} {'-':>7s}")
+        else:
+            lines.append(f"{k:14s} {prec:6s} {a:15.2f} {e * 1e3:17.2f} {100 * (a / (e * 1e3) - 1):7.2f}")
+    os.makedirs(dst, exist_ok=True)
+    with open(os.path.join(dst, "dycore_r2b6x90_kernel_trace.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    # ---- HBM counters ----
+    def counter(kind, name):
+        out = defaultdict(list)
+        for r in rows(os.path.join(src, f"prof_{kind}", f"{kind}_counter_collection.csv")):
+            if r["Counter_Name"] == name:
+                out[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        return out
+    fetch, write = counter("fetch", "FETCH_SIZE"), counter("write", "WRITE_SIZE")
+    copy = [k for k in fetch if "copyBuffer" in k]
+    cf, cw = max(fetch[copy[0]]), max(write[copy[0]])
+    fs, ws = (1 << 30) / (cf * 1024), (1 << 30) / (cw * 1024)
+    for prec in ("fp64", "mixed"):
+        alg = algorithmic_bytes(nc, ne, nv, N, prec)
+        per = defaultdict(lambda: [[], []])
+        for kname, vals in fetch.items():
+            k, p = _kernel_id(kname)
+            if p != prec:
+                continue
+            per[k][0] += vals
+            per[k][1] += write.get(kname, [])
+            if k == "cell_vt":
+                var = "cell_vt_" + ("corr" if "true>" in kname else "pred")
+                per[var][0] += vals
+                per[var][1] += write.get(kname, [])
+        lines = [f"# rocprofv3 HBM counters: dycore substep kernels, {prec} form, {wl}",
+                 f"kernel_source_sha256_16: {src_hash}",
+                 f"command (FETCH_SIZE pass): {PROFILE_CMDS['fetch']}",
+                 f"command (WRITE_SIZE pass): {PROFILE_CMDS['write']}",
+                 f"summarised by: python3 bench.py --profile-summary gpurun_out",
+                 f"calibration: the 1 GiB device-to-device copy (__amd_rocclr_copyBuffer, 1 GiB read + "
+                 f"1 GiB written) reads FETCH_SIZE {cf:.1f} KiB and WRITE_SIZE {cw:.1f} KiB per dispatch, "
+                 f"so fetch KiB x {fs:.3f} and write KiB x {ws:.3f} give bytes",
+                 "units: B/cl = bytes per cell-level (one cell at one full level) per launch", "",
+                 f"{'kernel':14s} {'n':>3s} {'fetch_KiB':>12s} {'write_KiB':>12s}  hbm_bytes_per_launch  "
+                 f"alg_bytes_per_launch  hbm_B/cl  alg_B/cl  hbm/alg"]
+        for k in sorted(per, key=lambda x: list(alg).index(x.split("_pred")[0].split("_corr")[0])
+                        if x.split("_pred")[0].split("_corr")[0] in alg else 99):
+            fv, wv = per[k]
+            rd = sum(fv) / len(fv)
+            wr = sum(wv) / len(wv)
+            hbm = rd * 1024 * fs + wr * 1024 * ws
+            base = k if k in alg else "cell_vt"
+            a = alg[base]
+            lines.append(f"{k:14s} {len(fv):3d} {rd:12.1f} {wr:12.1f}  hbm_bytes_per_launch={hbm:.4e}  "
+                         f"alg_bytes_per_launch={a:.4e}  {hbm / (nc * N):8.1f}  {a / (nc * N):8.1f}  "
+                         f"{hbm / a:7.2f}")
+        with open(os.path.join(dst, f"dycore_{prec}_r2b6x90_hbm_counters.txt"), "w") as f:
+            f.write("\n".join(lines) + "\n")
+    print(f"wrote summaries for kernel sources {src_hash} to {dst}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -346,10 +481,15 @@ def main():
     ap.add_argument("--timing-steps", type=int, default=4)
     ap.add_argument("--error-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-summary", metavar="DIR",
+                    help="reduce the rocprofv3 CSVs under DIR to the summaries in profiles/ and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after timing, copy 1 GiB device-to-device once (a plain copy kernel of "
                          "known size, to scale hardware byte counters)")
     args = ap.parse_args()
+    if args.profile_summary:
+        profile_summary(args.profile_summary, os.path.join(ROOT, "profiles"))
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); the "
               "multi-GPU decomposition is a design, not an implementation", file=sys.stderr)
