@@ -126,6 +126,26 @@ def timed_steps(torch, stepper, steps, warmup, stream):
     return e0.elapsed_time(e1)
 
 
+def copy_bandwidth(torch, gib=4, reps=10):
+    """Device-to-device copy of `gib` GiB (read + write counted), the best of
+    `reps`: the HBM rate a plain streaming kernel reaches on this GPU."""
+    n = (gib << 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    best = float("inf")
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * (gib << 30) / (best / 1e3) / 1e9
+
+
 def kernel_table(d, case, steps, stream, precision):
     g = case.grid
     d.set_timing(True)
@@ -214,8 +234,14 @@ def bench_default(args, torch, nhdc, CS):
                 "traffic": measured_traffic(dom, src_hash, "fp64"),
                 "alg_bytes_per_launch": int(kern[dom]["alg_bytes"]),
                 "avg_launch_ms": round(kern[dom]["avg_ms"], 5)}
+    copy_gbs = copy_bandwidth(torch)
+    roofline["copy_GBs"] = round(copy_gbs, 1)
+    roofline["frac_of_copy"] = round(achieved / copy_gbs, 4)
+    log(f"4 GiB device copy: {copy_gbs:.1f} GB/s")
     mk = tables["mixed"]
     mdom = max(mk, key=lambda k: mk[k]["share"])
+    forms["mixed"]["kernels"] = {k: {"avg_ms": round(v["avg_ms"], 5), "share": round(v["share"], 4),
+                                     "alg_GBs": round(v["alg_GBs"], 1)} for k, v in mk.items()}
     forms["mixed"]["roofline"] = {"kernel": mdom, "achieved": round(mk[mdom]["alg_GBs"], 1),
                                   "frac": round(mk[mdom]["alg_GBs"] / HBM_PEAK_GBS, 4),
                                   "traffic": measured_traffic(mdom, src_hash, "mixed")}
@@ -410,7 +436,7 @@ def profile_summary(src, dst):
         agg[(k, prec)][1] += int(r["Calls"])
     lines += ["", "## per kernel id, against the HIP-event averages bench.py measured in the same run",
               f"{'kernel':14s} {'form':6s} {'rocprof_avg_us':>15s} {'hip_event_avg_us':>17s} {'diff%':>7s}"]
-    ev = {"fp64": runs["trace"]["kernels"]}
+    ev = {"fp64": runs["trace"]["kernels"], "mixed": runs["trace"]["forms"]["mixed"].get("kernels", {})}
     for (k, prec), (tot, n) in sorted(agg.items(), key=lambda kv: (kv[0][1], -kv[1][0])):
         a = tot / n / 1e3
         e = ev.get(prec, {}).get(k, {}).get("avg_ms")
