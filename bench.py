@@ -39,12 +39,13 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(nc, ne, nv, N, prec="fp64"):
+def algorithmic_bytes(nc, ne, nv, N, prec="fp64", nsub=5):
     """Bytes each kernel must read and write once per launch: every input and
     output array once at its size (cached re-reads of gathered neighbours,
     register-carried levels and column scratch round trips not counted).
     Tendency-side arrays are FP32 in the mixed form; state, fluxes and the
-    column are FP64 in both."""
+    column are FP64 in both.  The Exner history is written on the last of
+    `nsub` substeps only, so it counts 1/nsub per corrector column launch."""
     r = 8 if prec == "fp64" else 4
     C, C1, Ci = N * nc, (N + 1) * nc, (N - 1) * nc        # entity-level counts
     E, V, V1, Vi = N * ne, N * nv, (N + 1) * nv, (N - 1) * nv
@@ -58,18 +59,18 @@ def algorithmic_bytes(nc, ne, nv, N, prec="fp64"):
         # vn, vt, w, wv, zh, zhv, gw -> kc, wcc, tw (+ div vn in the corrector)
         "cell_vt": [E * 8 + E * r + C1 * 8 + Vi * r + C1 * 8 + V1 * 8 + C1 * r + C * r + 2 * C1 * r + gc + ge,
                     E * 8 + E * r + C1 * 8 + Vi * r + C1 * 8 + V1 * 8 + C1 * r + 2 * C * r + 2 * C1 * r + gc + ge],
-        # kc, zeta, vt, vn, w, wcc, pi, pi_prev, pi_ref, thv, rho, zh, gw -> tvn, gp, vns, flx, hfl
-        "edge_pred": [C * r + V * r + E * r + E * 8 + C1 * 8 + C1 * r + 5 * C * 8 + C1 * 8 + C1 * r
-                      + 2 * E * r + 3 * E * 8 + ge],
-        # kc, zeta, vt, vns, ws, wcc1, thvs, tvn0, gp, dvn, vn, thv, rho, zh, gw, facc -> vn, flx, hfl, facc
+        # kc, zeta, vt, vn, w, wcc, px, thv, zh -> tvn, gp, vns
+        "edge_pred": [C * r + V * r + E * r + E * 8 + C1 * 8 + C1 * r + 2 * C * 8 + C1 * 8
+                      + 2 * E * r + E * 8 + ge],
+        # kc, zeta, vt, vns, ws, wcc1, thvs, tvn0, gp, dvn, vn, thv, rho, zh, facc -> vn, flx, hfl, facc
         "edge_corr": [C * r + V * r + E * r + E * 8 + C1 * 8 + C1 * r + C * 8 + 2 * E * r + C * r
-                      + E * 8 + 2 * C * 8 + C1 * 8 + C1 * r + E * 8 + 4 * E * 8 + ge],
-        # flx, hfl, rho, thv, pi, pi_ref, theta_ref, w, wcc, tw, zh -> ws, rhos, thvs
-        "column_pred": [2 * E * 8 + 5 * C * 8 + C1 * 8 + 2 * C1 * r + C1 * 8 + C1 * 8 + 2 * C * 8 + gc],
+                      + E * 8 + 2 * C * 8 + C1 * 8 + E * 8 + 4 * E * 8 + ge],
+        # vns, rho, thv, pi, pi_ref, theta_ref, w, wcc, tw, zh -> ws, rhos, thvs
+        "column_pred": [E * 8 + 5 * C * 8 + C1 * 8 + 2 * C1 * r + C1 * 8 + 2 * C * 8 + gc],
         # flx, hfl, rho, thv, pi, pi_ref, theta_ref, w, rhos, thvs, wcc1, tw0, tw1, zh, wacc
-        #   -> w, rho, thv, pi, pi_prev, wacc
+        #   -> w, rho, thv, pi, px, wacc (+ pi_prev on the last substep)
         "column_corr": [2 * E * 8 + 5 * C * 8 + C1 * 8 + 2 * C * 8 + 3 * C1 * r + C1 * 8 + C1 * 8
-                        + C1 * 8 + 4 * C * 8 + C1 * 8 + gc],
+                        + C1 * 8 + 4 * C * 8 + C * 8 / nsub + C1 * 8 + gc],
     }
     return {k: sum(v) / len(v) for k, v in t.items()}
 

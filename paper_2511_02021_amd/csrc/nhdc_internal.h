@@ -46,7 +46,6 @@ struct Grid {
     Geo<double> gd;
     Geo<float> gf;
     double *zh = nullptr;         // [N+1][nc] half-level heights
-    double *dref = nullptr;       // [N+1][nc] -g/(cpd theta_ref at half level)
     double *zhv = nullptr;        // [N+1][nv] vertex average of zh
     double *pi_ref = nullptr;     // [N][nc]
     double *theta_ref = nullptr;  // [N][nc]
@@ -60,10 +59,16 @@ template <>
 __host__ __device__ inline const Geo<float> &geo<float>(const Grid &g) { return g.gf; }
 
 // Prognostic state (FP64 in every form) and the FP64 mass-flux accumulators.
+// px is derived: the extrapolated Exner perturbation (1+eps)(pi - pi_ref) -
+// eps pi_prev that the next predictor uses, kept current by every call that
+// changes the state (the corrector's column writes it for the next substep).
+// pi_prev itself is only read back by callers, so the corrector stores it on
+// the last substep of a step.
 struct State {
     double *vn = nullptr, *w = nullptr, *rho = nullptr, *pi = nullptr, *thv = nullptr,
            *pi_prev = nullptr;
     double *facc = nullptr, *wacc = nullptr;
+    double *px = nullptr;  // [N][nc]
 };
 
 // Work arrays of one substep.  Tendency-side arrays have the stencil
@@ -80,8 +85,8 @@ struct Work {
     RT *tvn0 = nullptr;   // [N][ne] vn tendency of state n
     RT *gp = nullptr;     // [N][ne] terrain-corrected Exner gradient
     double *vns = nullptr;    // [N][ne] predicted vn
-    double *flx = nullptr;    // [N][ne] edge mass flux
-    double *hfl = nullptr;    // [N][ne] edge rho*theta_v flux
+    double *flx = nullptr;    // [N][ne] corrector edge mass flux
+    double *hfl = nullptr;    // [N][ne] corrector edge rho*theta_v flux
     double *ws = nullptr;     // [N+1][nc] predicted w
     double *rhos = nullptr;   // [N][nc] predicted rho
     double *thvs = nullptr;   // [N][nc] predicted theta_v
@@ -118,7 +123,7 @@ struct Map {
 // Per-launch scalars of one substep.
 struct Sub {
     double dt[MAX_INST];
-    int32_t nsub, first;
+    int32_t nsub, first, last;  // substeps per step; first / last substep of the step
 };
 
 // Level-tile sizes (levels per lane) of the marching kernels; 0 = whole column.
@@ -152,11 +157,12 @@ struct Launcher {
 hipError_t launch_substep_fp64(const Launcher &L, const Sub &sub, Timing *tm, hipStream_t st);
 hipError_t launch_substep_mixed(const Launcher &L, const Sub &sub, Timing *tm, hipStream_t st);
 // set-up and diagnostics (nhdc_util.hip)
-hipError_t launch_metrics(const Grid &g, const Params &p, double *gw, hipStream_t st);
+hipError_t launch_metrics(const Grid &g, double *gw, hipStream_t st);
 hipError_t launch_to_float(const double *src, float *dst, int64_t n, hipStream_t st);
 hipError_t launch_diag(const Grid &g, const State &s, double *part, double *out2, hipStream_t st);
 hipError_t launch_finite(const Grid &g, const State &s, int *flag, hipStream_t st);
 hipError_t launch_init_prev(const Grid &g, const State &s, hipStream_t st);
+hipError_t launch_exner_x(const Grid &g, const State &s, double eps, hipStream_t st);
 // timing helpers (nhdc_runtime.hip); no-ops when tm is null or off
 hipError_t timing_begin(Timing *tm, int id, hipStream_t st);
 hipError_t timing_end(Timing *tm, hipStream_t st);

@@ -56,6 +56,7 @@ hipError_t run_step(const Launcher &L, const double *dt, int nsub, Timing *tm, h
     sub.nsub = nsub;
     for (int s = 0; s < nsub; ++s) {
         sub.first = s == 0;
+        sub.last = s == nsub - 1;
         hipError_t e = L.precision == NHDC_MIXED ? launch_substep_mixed(L, sub, tm, st)
                                                  : launch_substep_fp64(L, sub, tm, st);
         if (e != hipSuccess) return e;
@@ -114,7 +115,7 @@ static void state_arrays(nhdc_ctx *c, std::vector<std::pair<double *, size_t>> &
     const size_t NC = size_t(c->g.N) * c->g.nc, NC1 = size_t(c->g.N + 1) * c->g.nc,
                  NE = size_t(c->g.N) * c->g.ne;
     out = {{c->s.vn, NE}, {c->s.w, NC1}, {c->s.rho, NC}, {c->s.pi, NC}, {c->s.thv, NC},
-           {c->s.pi_prev, NC}, {c->s.facc, NE}, {c->s.wacc, NC1}};
+           {c->s.pi_prev, NC}, {c->s.facc, NE}, {c->s.wacc, NC1}, {c->s.px, NC}};
 }
 
 static int snapshot(const std::vector<nhdc_ctx *> &ctxs, std::vector<void *> &buf, bool restore,
@@ -553,9 +554,8 @@ int nhdc_upload_grid(nhdc_ctx *ctx, const nhdc_grid *g, const nhdc_vertical *v,
     if ((rc = upload(ctx, &G.pi_ref, v->pi_ref, NC))) return rc;
     if ((rc = upload(ctx, &G.theta_ref, v->theta_ref, NC))) return rc;
     if ((rc = dalloc(ctx, &D.gw, NC1))) return rc;
-    if ((rc = dalloc(ctx, &G.dref, NC1))) return rc;
     if ((rc = dalloc(ctx, &G.zhv, NV1))) return rc;
-    HIP_TRY(ctx, launch_metrics(G, ctx->p, D.gw, nullptr));
+    HIP_TRY(ctx, launch_metrics(G, D.gw, nullptr));
     if (ctx->precision == NHDC_MIXED) {
         Geo<float> &F = G.gf;
         if ((rc = upload_f32(ctx, &F.c_sl, D.c_sl, 3 * nc))) return rc;
@@ -575,7 +575,7 @@ int nhdc_upload_grid(nhdc_ctx *ctx, const nhdc_grid *g, const nhdc_vertical *v,
 
     // ---- state, accumulators and work arrays ----
     State &S = ctx->s;
-    double **cellsN[] = {&S.rho, &S.pi, &S.thv, &S.pi_prev};
+    double **cellsN[] = {&S.rho, &S.pi, &S.thv, &S.pi_prev, &S.px};
     for (auto q : cellsN)
         if ((rc = dalloc(ctx, q, NC))) return rc;
     if ((rc = dalloc(ctx, &S.w, NC1))) return rc;
@@ -614,6 +614,7 @@ int nhdc_init_state(nhdc_ctx *ctx, const nhdc_state_view *st, void *stream) {
     HIP_TRY(ctx, hipMemcpyAsync(ctx->s.thv, st->theta_v, NC, kind, s));
     if (st->pi_prev) HIP_TRY(ctx, hipMemcpyAsync(ctx->s.pi_prev, st->pi_prev, NC, kind, s));
     else HIP_TRY(ctx, launch_init_prev(ctx->g, ctx->s, s));
+    HIP_TRY(ctx, launch_exner_x(ctx->g, ctx->s, ctx->p.extrap, s));
     HIP_TRY(ctx, hipMemsetAsync(ctx->s.facc, 0, NE, s));
     HIP_TRY(ctx, hipMemsetAsync(ctx->s.wacc, 0, NC1, s));
     if (!st->on_device) HIP_TRY(ctx, hipStreamSynchronize(s));

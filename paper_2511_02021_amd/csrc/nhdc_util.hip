@@ -1,6 +1,6 @@
 // nhdc_util.hip -- set-up and diagnostic kernels of libnhdc (not on the step
-// path): vertical interpolation weights and reference derivative, vertex
-// heights, FP32 copies of coefficients, the initial Exner history, the
+// path): vertical interpolation weights, vertex heights, FP32 copies of
+// coefficients, the initial Exner history and extrapolated perturbation, the
 // deterministic mass sums and the finiteness check.  No contraction, so the
 // metrics equal their plain FP64 definitions.
 #include <hip/hip_runtime.h>
@@ -17,21 +17,15 @@ __device__ __forceinline__ int64_t lin() { return int64_t(blockIdx.x) * BLOCK + 
 inline unsigned nb(int64_t n) { return unsigned((n + BLOCK - 1) / BLOCK); }
 
 __global__ void k_metrics_cell(int64_t nc, int N, const double *__restrict__ zh,
-                               const double *__restrict__ theta_ref, double grav, double cpd,
-                               double *__restrict__ gw, double *__restrict__ dref) {
+                               double *__restrict__ gw) {
     int64_t c = lin();
     if (c >= nc) return;
     gw[c] = 0.0;
-    dref[c] = 0.0;
     gw[int64_t(N) * nc + c] = 0.0;
-    dref[int64_t(N) * nc + c] = 0.0;
     for (int i = 1; i < N; ++i) {
         double za = 0.5 * (zh[int64_t(i - 1) * nc + c] + zh[int64_t(i) * nc + c]);
         double zb = 0.5 * (zh[int64_t(i) * nc + c] + zh[int64_t(i + 1) * nc + c]);
-        double g = (za - zh[int64_t(i) * nc + c]) / (za - zb);
-        gw[int64_t(i) * nc + c] = g;
-        double th = g * theta_ref[int64_t(i) * nc + c] + (1.0 - g) * theta_ref[int64_t(i - 1) * nc + c];
-        dref[int64_t(i) * nc + c] = -grav / (cpd * th);
+        gw[int64_t(i) * nc + c] = (za - zh[int64_t(i) * nc + c]) / (za - zb);
     }
 }
 
@@ -57,6 +51,16 @@ __global__ void k_init_prev(int64_t n, const double *__restrict__ pi, const doub
                             double *__restrict__ prev) {
     int64_t i = lin();
     if (i < n) prev[i] = pi[i] - pi_ref[i];
+}
+
+// extrapolated Exner perturbation of the next predictor
+__global__ void k_exner_x(int64_t n, const double *__restrict__ pi, const double *__restrict__ pi_ref,
+                          const double *__restrict__ prev, double eps, double *__restrict__ px) {
+    int64_t i = lin();
+    if (i < n) {
+        double pp = pi[i] - pi_ref[i];
+        px[i] = (1.0 + eps) * pp - eps * prev[i];
+    }
 }
 
 // fixed-order two-level reduction: per-block partials, then one block
@@ -120,9 +124,8 @@ __global__ void k_finite(int64_t n, const double *__restrict__ x, int *__restric
 
 }  // namespace
 
-hipError_t launch_metrics(const Grid &g, const Params &p, double *gw, hipStream_t st) {
-    hipLaunchKernelGGL(k_metrics_cell, dim3(nb(g.nc)), dim3(BLOCK), 0, st, g.nc, g.N, g.zh,
-                       g.theta_ref, p.grav, p.cpd, gw, g.dref);
+hipError_t launch_metrics(const Grid &g, double *gw, hipStream_t st) {
+    hipLaunchKernelGGL(k_metrics_cell, dim3(nb(g.nc)), dim3(BLOCK), 0, st, g.nc, g.N, g.zh, gw);
     hipLaunchKernelGGL(k_metrics_vert, dim3(nb(g.nv)), dim3(BLOCK), 0, st, g.nv, g.nc, g.N, g.v_c,
                        g.gd.v_m, g.gd.v_val, g.zh, g.zhv);
     return hipGetLastError();
@@ -136,6 +139,13 @@ hipError_t launch_to_float(const double *src, float *dst, int64_t n, hipStream_t
 hipError_t launch_init_prev(const Grid &g, const State &s, hipStream_t st) {
     int64_t n = int64_t(g.N) * g.nc;
     hipLaunchKernelGGL(k_init_prev, dim3(nb(n)), dim3(BLOCK), 0, st, n, s.pi, g.pi_ref, s.pi_prev);
+    return hipGetLastError();
+}
+
+hipError_t launch_exner_x(const Grid &g, const State &s, double eps, hipStream_t st) {
+    int64_t n = int64_t(g.N) * g.nc;
+    hipLaunchKernelGGL(k_exner_x, dim3(nb(n)), dim3(BLOCK), 0, st, n, s.pi, g.pi_ref, s.pi_prev, eps,
+                       s.px);
     return hipGetLastError();
 }
 
