@@ -56,14 +56,14 @@ def algorithmic_bytes(nc, ne, nv, N, prec="fp64", nsub=5):
     t = {
         "vt_edge": [E * 8 + E * r + recon],
         "vertex": [E * 8 + Ci * 8 + V * r + Vi * r + gv],
-        # vn, vt, w, wv, zh, zhv, gw -> kc, wcc, tw (+ div vn in the corrector)
-        "cell_vt": [E * 8 + E * r + C1 * 8 + Vi * r + C1 * 8 + V1 * 8 + C1 * r + C * r + 2 * C1 * r + gc + ge,
-                    E * 8 + E * r + C1 * 8 + Vi * r + C1 * 8 + V1 * 8 + C1 * r + 2 * C * r + 2 * C1 * r + gc + ge],
-        # kc, zeta, vt, vn, w, wcc, px, thv, zh -> tvn, gp, vns
+        # vn, vt, w, wv, zh, zhv -> kc, wcc, tw (+ div vn in the corrector)
+        "cell_vt": [E * 8 + E * r + C1 * 8 + Vi * r + C1 * 8 + V1 * 8 + C * r + 2 * C1 * r + gc + ge,
+                    E * 8 + E * r + C1 * 8 + Vi * r + C1 * 8 + V1 * 8 + 2 * C * r + 2 * C1 * r + gc + ge],
+        # kc, zeta, vt, vn, w, wcc, px, thv, zh -> tvn, vns
         "edge_pred": [C * r + V * r + E * r + E * 8 + C1 * 8 + C1 * r + 2 * C * 8 + C1 * 8
-                      + 2 * E * r + E * 8 + ge],
-        # kc, zeta, vt, vns, ws, wcc1, thvs, tvn0, gp, dvn, vn, thv, rho, zh, facc -> vn, flx, hfl, facc
-        "edge_corr": [C * r + V * r + E * r + E * 8 + C1 * 8 + C1 * r + C * 8 + 2 * E * r + C * r
+                      + E * r + E * 8 + ge],
+        # kc, zeta, vt, vns, ws, wcc1, thvs, tvn0, px, dvn, vn, thv, rho, zh, facc -> vn, flx, hfl, facc
+        "edge_corr": [C * r + V * r + E * r + E * 8 + C1 * 8 + C1 * r + C * 8 + E * r + C * 8 + C * r
                       + E * 8 + 2 * C * 8 + C1 * 8 + E * 8 + 4 * E * 8 + ge],
         # vns, rho, thv, pi, pi_ref, theta_ref, w, wcc, tw, zh -> ws, rhos, thvs
         "column_pred": [E * 8 + 5 * C * 8 + C1 * 8 + 2 * C1 * r + C1 * 8 + 2 * C * 8 + gc],
@@ -235,10 +235,11 @@ def bench_default(args, torch, nhdc, CS):
                 "traffic": measured_traffic(dom, src_hash, "fp64"),
                 "alg_bytes_per_launch": int(kern[dom]["alg_bytes"]),
                 "avg_launch_ms": round(kern[dom]["avg_ms"], 5)}
-    copy_gbs = copy_bandwidth(torch)
-    roofline["copy_GBs"] = round(copy_gbs, 1)
-    roofline["frac_of_copy"] = round(achieved / copy_gbs, 4)
-    log(f"4 GiB device copy: {copy_gbs:.1f} GB/s")
+    if not args.copy_calibration:  # counter runs keep a single copy: the calibration one
+        copy_gbs = copy_bandwidth(torch)
+        roofline["copy_GBs"] = round(copy_gbs, 1)
+        roofline["frac_of_copy"] = round(achieved / copy_gbs, 4)
+        log(f"4 GiB device copy: {copy_gbs:.1f} GB/s")
     mk = tables["mixed"]
     mdom = max(mk, key=lambda k: mk[k]["share"])
     forms["mixed"]["kernels"] = {k: {"avg_ms": round(v["avg_ms"], 5), "share": round(v["share"], 4),
@@ -451,13 +452,15 @@ def profile_summary(src, dst):
     # ---- HBM counters ----
     def counter(kind, name):
         out = defaultdict(list)
-        for r in rows(os.path.join(src, f"prof_{kind}", f"{kind}_counter_collection.csv")):
+        for r in sorted(rows(os.path.join(src, f"prof_{kind}", f"{kind}_counter_collection.csv")),
+                        key=lambda r: int(r["Dispatch_Id"])):
             if r["Counter_Name"] == name:
                 out[r["Kernel_Name"]].append(float(r["Counter_Value"]))
         return out
     fetch, write = counter("fetch", "FETCH_SIZE"), counter("write", "WRITE_SIZE")
     copy = [k for k in fetch if "copyBuffer" in k]
-    cf, cw = max(fetch[copy[0]]), max(write[copy[0]])
+    # the calibration copy is the last device copy of the profiled run
+    cf, cw = fetch[copy[0]][-1], write[copy[0]][-1]
     fs, ws = (1 << 30) / (cf * 1024), (1 << 30) / (cw * 1024)
     for prec in ("fp64", "mixed"):
         alg = algorithmic_bytes(nc, ne, nv, N, prec)

@@ -83,7 +83,6 @@ struct Work {
     RT *wcc0 = nullptr, *tw0 = nullptr;  // [N+1][nc] of state n
     RT *wcc1 = nullptr, *tw1 = nullptr;  // [N+1][nc] of the predicted state
     RT *tvn0 = nullptr;   // [N][ne] vn tendency of state n
-    RT *gp = nullptr;     // [N][ne] terrain-corrected Exner gradient
     double *vns = nullptr;    // [N][ne] predicted vn
     double *flx = nullptr;    // [N][ne] corrector edge mass flux
     double *hfl = nullptr;    // [N][ne] corrector edge rho*theta_v flux

@@ -394,7 +394,7 @@ int alloc_work(nhdc_ctx *ctx, Work<RT> &W) {
     int rc;
     RT **rt_c[] = {&W.kc, &W.dvn};
     RT **rt_c1[] = {&W.wcc0, &W.tw0, &W.wcc1, &W.tw1};
-    RT **rt_e[] = {&W.vt, &W.tvn0, &W.gp};
+    RT **rt_e[] = {&W.vt, &W.tvn0};
     for (auto q : rt_c)
         if ((rc = dalloc(ctx, q, NC))) return rc;
     for (auto q : rt_c1)
