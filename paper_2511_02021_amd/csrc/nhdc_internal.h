@@ -29,7 +29,6 @@ struct Geo {
     T *v_m = nullptr;     // [6][nv] 1 on ring slots, 0 on the pad
     T *v_val = nullptr;   // [nv] valence
     T *v_area = nullptr;  // [nv] dual area
-    T *gw = nullptr;      // [N+1][nc] vertical interpolation weight (interior half levels)
 };
 
 struct Grid {
@@ -156,7 +155,7 @@ struct Launcher {
 hipError_t launch_substep_fp64(const Launcher &L, const Sub &sub, Timing *tm, hipStream_t st);
 hipError_t launch_substep_mixed(const Launcher &L, const Sub &sub, Timing *tm, hipStream_t st);
 // set-up and diagnostics (nhdc_util.hip)
-hipError_t launch_metrics(const Grid &g, double *gw, hipStream_t st);
+hipError_t launch_metrics(const Grid &g, hipStream_t st);
 hipError_t launch_to_float(const double *src, float *dst, int64_t n, hipStream_t st);
 hipError_t launch_diag(const Grid &g, const State &s, double *part, double *out2, hipStream_t st);
 hipError_t launch_finite(const Grid &g, const State &s, int *flag, hipStream_t st);

@@ -553,9 +553,8 @@ int nhdc_upload_grid(nhdc_ctx *ctx, const nhdc_grid *g, const nhdc_vertical *v,
     if ((rc = upload(ctx, &G.zh, v->zh, NC1))) return rc;
     if ((rc = upload(ctx, &G.pi_ref, v->pi_ref, NC))) return rc;
     if ((rc = upload(ctx, &G.theta_ref, v->theta_ref, NC))) return rc;
-    if ((rc = dalloc(ctx, &D.gw, NC1))) return rc;
     if ((rc = dalloc(ctx, &G.zhv, NV1))) return rc;
-    HIP_TRY(ctx, launch_metrics(G, D.gw, nullptr));
+    HIP_TRY(ctx, launch_metrics(G, nullptr));
     if (ctx->precision == NHDC_MIXED) {
         Geo<float> &F = G.gf;
         if ((rc = upload_f32(ctx, &F.c_sl, D.c_sl, 3 * nc))) return rc;
@@ -570,7 +569,6 @@ int nhdc_upload_grid(nhdc_ctx *ctx, const nhdc_grid *g, const nhdc_vertical *v,
         if ((rc = upload_f32(ctx, &F.v_m, D.v_m, 6 * nv))) return rc;
         if ((rc = upload_f32(ctx, &F.v_val, D.v_val, nv))) return rc;
         if ((rc = upload_f32(ctx, &F.v_area, D.v_area, nv))) return rc;
-        if ((rc = upload_f32(ctx, &F.gw, D.gw, NC1))) return rc;
     }
 
     // ---- state, accumulators and work arrays ----

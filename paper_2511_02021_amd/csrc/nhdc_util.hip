@@ -1,8 +1,8 @@
 // nhdc_util.hip -- set-up and diagnostic kernels of libnhdc (not on the step
-// path): vertical interpolation weights, vertex heights, FP32 copies of
-// coefficients, the initial Exner history and extrapolated perturbation, the
-// deterministic mass sums and the finiteness check.  No contraction, so the
-// metrics equal their plain FP64 definitions.
+// path): vertex heights, FP32 copies of coefficients, the initial Exner
+// history and extrapolated perturbation, the deterministic mass sums and the
+// finiteness check.  No contraction, so the metrics equal their plain FP64
+// definitions.
 #include <hip/hip_runtime.h>
 
 #include "nhdc_internal.h"
@@ -15,19 +15,6 @@ namespace {
 __device__ __forceinline__ int64_t lin() { return int64_t(blockIdx.x) * BLOCK + threadIdx.x; }
 
 inline unsigned nb(int64_t n) { return unsigned((n + BLOCK - 1) / BLOCK); }
-
-__global__ void k_metrics_cell(int64_t nc, int N, const double *__restrict__ zh,
-                               double *__restrict__ gw) {
-    int64_t c = lin();
-    if (c >= nc) return;
-    gw[c] = 0.0;
-    gw[int64_t(N) * nc + c] = 0.0;
-    for (int i = 1; i < N; ++i) {
-        double za = 0.5 * (zh[int64_t(i - 1) * nc + c] + zh[int64_t(i) * nc + c]);
-        double zb = 0.5 * (zh[int64_t(i) * nc + c] + zh[int64_t(i + 1) * nc + c]);
-        gw[int64_t(i) * nc + c] = (za - zh[int64_t(i) * nc + c]) / (za - zb);
-    }
-}
 
 __global__ void k_metrics_vert(int64_t nv, int64_t nc, int N, const int32_t *__restrict__ v_c,
                                const double *__restrict__ v_m, const double *__restrict__ v_val,
@@ -124,8 +111,7 @@ __global__ void k_finite(int64_t n, const double *__restrict__ x, int *__restric
 
 }  // namespace
 
-hipError_t launch_metrics(const Grid &g, double *gw, hipStream_t st) {
-    hipLaunchKernelGGL(k_metrics_cell, dim3(nb(g.nc)), dim3(BLOCK), 0, st, g.nc, g.N, g.zh, gw);
+hipError_t launch_metrics(const Grid &g, hipStream_t st) {
     hipLaunchKernelGGL(k_metrics_vert, dim3(nb(g.nv)), dim3(BLOCK), 0, st, g.nv, g.nc, g.N, g.v_c,
                        g.gd.v_m, g.gd.v_val, g.zh, g.zhv);
     return hipGetLastError();

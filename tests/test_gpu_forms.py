@@ -176,9 +176,10 @@ def test_mixed_form_error_and_conservation():
         print(f"mixed {f}: E={r['E']:.2e} S={r['S']:.2e} E/signal={r['E_signal']:.2e} "
               f"S/signal={r['S_signal']:.2e}", flush=True)
     for f, r in table.items():
-        # FP32 stencils vs the FP32-rounding floor of the same fields
-        assert r["E"] <= max(100.0 * r["S"], 1e-9), (f, r)
-        assert r["E_signal"] < 1e-4, (f, r)
+        # the mixed form's deviation from FP64 stays below the FP32-rounding
+        # floor of the same fields
+        assert r["E"] <= r["S"], (f, r)
+        assert r["E_signal"] < 1e-5, (f, r)
     # mass and rho*theta_v stay conserved to FP64 round-off (fluxes are FP64)
     d = _nhdc().Dycore(c, precision="mixed")
     m0, r0 = d.diag()
