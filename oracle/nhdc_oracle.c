@@ -3,6 +3,10 @@
  * TEST INFRASTRUCTURE ONLY (see nhdc_oracle.h for what it computes and who
  * may call it).  Plain loops, one formula per statement, sums in slot order,
  * no fused multiply-add (built with -ffp-contract=off), OpenMP over entities.
+ * Operators scale by the reciprocal of each fixed metric length, area,
+ * valence or count (1/d_e, 1/l_e, 1/A_c, 1/A_v, 1/valence, 1/3), each the
+ * IEEE quotient 1/x: the definitions read (1/A) times a sum and a difference
+ * times 1/length, and these metric factors are constant through a run.
  *
  * Index conventions: full level k = 0..N-1 top to bottom; half level i =
  * 0..N, half level i is the top interface of full level i, i = N the ground.
@@ -53,7 +57,7 @@ void or_op_div(const or_grid *g, const double *f, double *out) {
             int64_t e = g->cell_edges[j * nc + c];
             s += g->cell_sign[j * nc + c] * g->edge_length[e] * f[e];
         }
-        out[c] = s / g->cell_area[c];
+        out[c] = s * (1.0 / g->cell_area[c]);
     }
 }
 
@@ -61,14 +65,14 @@ void or_op_grad(const or_grid *g, const double *p, double *out) {
     const int64_t ne = g->ne;
 #pragma omp parallel for schedule(static)
     for (int64_t e = 0; e < ne; ++e)
-        out[e] = (p[g->edge_cells[ne + e]] - p[g->edge_cells[e]]) / g->dual_length[e];
+        out[e] = (p[g->edge_cells[ne + e]] - p[g->edge_cells[e]]) * (1.0 / g->dual_length[e]);
 }
 
 void or_op_tgrad(const or_grid *g, const double *q, double *out) {
     const int64_t ne = g->ne;
 #pragma omp parallel for schedule(static)
     for (int64_t e = 0; e < ne; ++e)
-        out[e] = (q[g->edge_verts[ne + e]] - q[g->edge_verts[e]]) / g->edge_length[e];
+        out[e] = (q[g->edge_verts[ne + e]] - q[g->edge_verts[e]]) * (1.0 / g->edge_length[e]);
 }
 
 void or_op_curl(const or_grid *g, const double *u, double *out) {
@@ -80,7 +84,7 @@ void or_op_curl(const or_grid *g, const double *u, double *out) {
             int64_t e = g->vert_edges[j * nv + v];
             s += g->vert_sign[j * nv + v] * g->dual_length[e] * u[e];
         }
-        out[v] = s / g->vert_area[v];
+        out[v] = s * (1.0 / g->vert_area[v]);
     }
 }
 
@@ -90,7 +94,7 @@ void or_op_cell_avg(const or_grid *g, const double *q, double *out) {
     for (int64_t c = 0; c < nc; ++c) {
         double s = 0.0;
         for (int j = 0; j < 3; ++j) s += q[g->cell_edges[j * nc + c]];
-        out[c] = s / 3.0;
+        out[c] = s * (1.0 / 3.0);
     }
 }
 
@@ -100,7 +104,7 @@ void or_op_vert_avg(const or_grid *g, const double *p, double *out) {
     for (int64_t v = 0; v < nv; ++v) {
         double s = 0.0;
         for (int j = 0; j < g->vert_valence[v]; ++j) s += p[g->vert_cells[j * nv + v]];
-        out[v] = s / g->vert_valence[v];
+        out[v] = s * (1.0 / g->vert_valence[v]);
     }
 }
 
@@ -115,7 +119,7 @@ void or_op_perot(const or_grid *g, const double *pc, const double *pe, const dou
             double wgt = g->cell_sign[j * nc + c] * g->edge_length[e] * u[e];
             for (int d = 0; d < 3; ++d) v[d] += wgt * (pe[d * ne + e] - pc[d * nc + c]);
         }
-        for (int d = 0; d < 3; ++d) v[d] = v[d] / g->cell_area[c];
+        for (int d = 0; d < 3; ++d) v[d] = v[d] * (1.0 / g->cell_area[c]);
         double r = v[0] * rc[c] + v[1] * rc[nc + c] + v[2] * rc[2 * nc + c];
         for (int d = 0; d < 3; ++d) vc[d * nc + c] = v[d] - r * rc[d * nc + c];
     }
@@ -195,12 +199,12 @@ or_model *or_create(const or_grid *g, int N, const double *zh, const double *pi_
         int64_t v1 = g->edge_verts[e], v2 = g->edge_verts[ne + e];
         for (int k = 0; k < N; ++k) {
             AT(m->dz_e, k, ne, e) = 0.5 * (AT(m->dz, k, nc, c1) + AT(m->dz, k, nc, c2));
-            AT(m->sn, k, ne, e) = (AT(m->z, k, nc, c2) - AT(m->z, k, nc, c1)) / g->dual_length[e];
+            AT(m->sn, k, ne, e) = (AT(m->z, k, nc, c2) - AT(m->z, k, nc, c1)) * (1.0 / g->dual_length[e]);
         }
         for (int i = 0; i <= N; ++i) {
             if (i > 0 && i < N) AT(m->gw_e, i, ne, e) = 0.5 * (AT(m->gw, i, nc, c1) + AT(m->gw, i, nc, c2));
-            AT(m->snh, i, ne, e) = (AT(m->zh, i, nc, c2) - AT(m->zh, i, nc, c1)) / g->dual_length[e];
-            AT(m->sth, i, ne, e) = (AT(m->wv, i, nv, v2) - AT(m->wv, i, nv, v1)) / g->edge_length[e];
+            AT(m->snh, i, ne, e) = (AT(m->zh, i, nc, c2) - AT(m->zh, i, nc, c1)) * (1.0 / g->dual_length[e]);
+            AT(m->sth, i, ne, e) = (AT(m->wv, i, nv, v2) - AT(m->wv, i, nv, v1)) * (1.0 / g->edge_length[e]);
         }
         m->fe[e] = 2.0 * p->omega * g->edge_x[2 * ne + e];
     }
@@ -282,7 +286,7 @@ static void vt_phase(or_model *m, const double *vn, const double *w, double *tvn
                 double wgt = g->cell_sign[j * nc + c] * g->edge_length[e] * u[e];
                 for (int d = 0; d < 3; ++d) v[d] += wgt * (a * (g->edge_x[d * ne + e] - xc[d]));
             }
-            for (int d = 0; d < 3; ++d) v[d] = v[d] / g->cell_area[c];
+            for (int d = 0; d < 3; ++d) v[d] = v[d] * (1.0 / g->cell_area[c]);
             double r = v[0] * xc[0] + v[1] * xc[1] + v[2] * xc[2];
             AT(m->pcx, k, nc, c) = v[0] - r * xc[0];
             AT(m->pcy, k, nc, c) = v[1] - r * xc[1];
@@ -348,7 +352,7 @@ static void vt_phase(or_model *m, const double *vn, const double *w, double *tvn
         int64_t c1 = g->edge_cells[e], c2 = g->edge_cells[ne + e];
         int64_t v1 = g->edge_verts[e], v2 = g->edge_verts[ne + e];
         for (int k = 0; k < N; ++k) {
-            double gradk = (AT(m->kc, k, nc, c2) - AT(m->kc, k, nc, c1)) / g->dual_length[e];
+            double gradk = (AT(m->kc, k, nc, c2) - AT(m->kc, k, nc, c1)) * (1.0 / g->dual_length[e]);
             double zeta_e = 0.5 * (AT(m->zv, k, nv, v1) + AT(m->zv, k, nv, v2));
             double of1 = 0.5 * (AT(m->omega, k, nc, c1) + AT(m->omega, k + 1, nc, c1));
             double of2 = 0.5 * (AT(m->omega, k, nc, c2) + AT(m->omega, k + 1, nc, c2));
@@ -364,8 +368,8 @@ static void vt_phase(or_model *m, const double *vn, const double *w, double *tvn
         int64_t c1 = g->edge_cells[e], c2 = g->edge_cells[ne + e];
         int64_t v1 = g->edge_verts[e], v2 = g->edge_verts[ne + e];
         for (int i = 1; i < N; ++i) {
-            double gw_ = (AT(w, i, nc, c2) - AT(w, i, nc, c1)) / g->dual_length[e];
-            double tw_ = (AT(m->wv, i, nv, v2) - AT(m->wv, i, nv, v1)) / g->edge_length[e];
+            double gw_ = (AT(w, i, nc, c2) - AT(w, i, nc, c1)) * (1.0 / g->dual_length[e]);
+            double tw_ = (AT(m->wv, i, nv, v2) - AT(m->wv, i, nv, v1)) * (1.0 / g->edge_length[e]);
             AT(m->ae, i, ne, e) = AT(m->vnh, i, ne, e) * gw_ + AT(m->vth, i, ne, e) * tw_;
         }
     }
@@ -407,7 +411,7 @@ static void pgrad(or_model *m, const double *px, double *gp) {
     for (int64_t e = 0; e < ne; ++e) {
         int64_t c1 = g->edge_cells[e], c2 = g->edge_cells[ne + e];
         for (int k = 0; k < N; ++k) {
-            double gl = (AT(px, k, nc, c2) - AT(px, k, nc, c1)) / g->dual_length[e];
+            double gl = (AT(px, k, nc, c2) - AT(px, k, nc, c1)) * (1.0 / g->dual_length[e]);
             double dz2 = 0.5 * (AT(m->dpz, k, nc, c1) + AT(m->dpz, k, nc, c2));
             AT(gp, k, ne, e) = gl - AT(m->sn, k, ne, e) * dz2;
         }
@@ -632,7 +636,7 @@ static void substep(or_model *m, double dt, int nsub) {
             double the_s = 0.5 * (AT(m->thvs, k, nc, c1) + AT(m->thvs, k, nc, c2));
             double tend = (1.0 - cv) * AT(m->tvn0, k, ne, e) + cv * AT(m->tvn1, k, ne, e) -
                           p->cpd * the_s * AT(m->gp, k, ne, e);
-            double gdiv = (AT(m->dvs, k, nc, c2) - AT(m->dvs, k, nc, c1)) / g->dual_length[e];
+            double gdiv = (AT(m->dvs, k, nc, c2) - AT(m->dvs, k, nc, c1)) * (1.0 / g->dual_length[e]);
             AT(m->vnn, k, ne, e) = AT(m->vn, k, ne, e) + dt * tend + p->div_damp * abar * gdiv;
         }
     }

@@ -14,11 +14,12 @@
  * an ICON-style substep (vector-invariant momentum equation, Exner pressure,
  * predictor-corrector horizontal step, vertically implicit w/Exner solve):
  *
- *   operators, per level, sums in slot order:
- *     D(F)_c = sum_j s(c,e_j) l_ej F_ej / A_c          G(p)_e = (p_c2 - p_c1)/d_e
- *     T(q)_e = (q_v2 - q_v1)/l_e                      Z(u)_v = sum_ring sigma d_e u_e / A_v
- *     M(q)_c = sum_j q_ej / 3    E(p)_e = (p_c1+p_c2)/2    P(p)_v = sum_ring p_c / valence
- *     Perot vector V_c = radial-free part of sum_j s l u a (x_e - x_c) / A_c,
+ *   operators, per level, sums in slot order; each fixed metric divisor enters
+ *   as its reciprocal (1/x, one IEEE quotient) times the sum or difference:
+ *     D(F)_c = (1/A_c) sum_j s(c,e_j) l_ej F_ej        G(p)_e = (p_c2 - p_c1) (1/d_e)
+ *     T(q)_e = (q_v2 - q_v1) (1/l_e)                   Z(u)_v = (1/A_v) sum_ring sigma d_e u_e
+ *     M(q)_c = (1/3) sum_j q_ej   E(p)_e = (p_c1+p_c2)/2   P(p)_v = (1/valence) sum_ring p_c
+ *     Perot vector V_c = radial-free part of (1/A_c) sum_j s l u a (x_e - x_c),
  *     vt_e = (V_c1 + V_c2)/2 . t_e
  *   vertical: z_k = (zh_k + zh_k+1)/2, dz_k = zh_k - zh_k+1, linear interpolation
  *     to half levels with g_i = (z_i-1 - zh_i)/(z_i-1 - z_i); boundary half levels

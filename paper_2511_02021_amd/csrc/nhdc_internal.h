@@ -15,20 +15,23 @@ constexpr int MAX_INST = 64;    // instances of one batched launch
 
 // Stencil coefficients in one precision.  The FP64 form reads the double
 // set; the mixed form's FP32 stencils read float copies of the same values.
+// Fixed metric divisors are stored as their reciprocals (the IEEE quotient
+// 1/x in FP64, as the operators scale by them).
 template <class T>
 struct Geo {
     T *c_sl = nullptr;    // [3][nc] s(c,e_j) * l_ej
     T *c_dv = nullptr;    // [9][nc] a*(x_ej - x_c), row j*3+d
     T *c_x = nullptr;     // [3][nc] unit cell centre (radial direction)
-    T *c_area = nullptr;  // [nc] cell area
-    T *e_de = nullptr;    // [ne] dual length d_e
-    T *e_le = nullptr;    // [ne] primal length l_e
+    T *c_area = nullptr;  // [nc] cell area (mass sums)
+    T *c_ia = nullptr;    // [nc] 1 / cell area
+    T *e_ide = nullptr;   // [ne] 1 / dual length d_e
+    T *e_ile = nullptr;   // [ne] 1 / primal length l_e
     T *e_t = nullptr;     // [3][ne] edge tangent
     T *fe = nullptr;      // [ne] Coriolis parameter 2 Omega z_e
     T *v_sd = nullptr;    // [6][nv] sigma(v,e_j) * d_ej (0 on the pentagon pad)
     T *v_m = nullptr;     // [6][nv] 1 on ring slots, 0 on the pad
-    T *v_val = nullptr;   // [nv] valence
-    T *v_area = nullptr;  // [nv] dual area
+    T *v_ival = nullptr;  // [nv] 1 / valence
+    T *v_ia = nullptr;    // [nv] 1 / dual area
 };
 
 struct Grid {

@@ -485,7 +485,14 @@ int nhdc_upload_grid(nhdc_ctx *ctx, const nhdc_grid *g, const nhdc_vertical *v,
 
     // ---- stencil coefficients on the host (each formed exactly as the
     // operators form it, so device sums see the same operands) ----
-    std::vector<double> c_sl(3 * nc), c_dv(9 * nc), v_sd(6 * nv), v_m(6 * nv), v_val(nv), fe(ne);
+    std::vector<double> c_sl(3 * nc), c_dv(9 * nc), v_sd(6 * nv), v_m(6 * nv), v_ival(nv), fe(ne);
+    std::vector<double> c_ia(nc), e_ide(ne), e_ile(ne), v_ia(nv);
+    for (int64_t c = 0; c < nc; ++c) c_ia[c] = 1.0 / g->cell_area[c];
+    for (int64_t e = 0; e < ne; ++e) {
+        e_ide[e] = 1.0 / g->dual_length[e];
+        e_ile[e] = 1.0 / g->edge_length[e];
+    }
+    for (int64_t v = 0; v < nv; ++v) v_ia[v] = 1.0 / g->vert_area[v];
     std::vector<int32_t> v_e(6 * nv), v_c(6 * nv);
     for (int64_t c = 0; c < nc; ++c) {
         const double xc[3] = {g->cell_x[c], g->cell_x[nc + c], g->cell_x[2 * nc + c]};
@@ -497,7 +504,7 @@ int nhdc_upload_grid(nhdc_ctx *ctx, const nhdc_grid *g, const nhdc_vertical *v,
     }
     for (int64_t vtx = 0; vtx < nv; ++vtx) {
         int val = g->vert_valence[vtx];
-        v_val[vtx] = double(val);
+        v_ival[vtx] = 1.0 / double(val);
         for (int j = 0; j < 6; ++j) {
             bool real = j < val;
             int64_t e = real ? g->vert_edges[j * nv + vtx] : g->vert_edges[vtx];
@@ -540,14 +547,15 @@ int nhdc_upload_grid(nhdc_ctx *ctx, const nhdc_grid *g, const nhdc_vertical *v,
     if ((rc = upload(ctx, &D.c_dv, c_dv.data(), 9 * nc))) return rc;
     if ((rc = upload(ctx, &D.c_x, g->cell_x, 3 * nc))) return rc;
     if ((rc = upload(ctx, &D.c_area, g->cell_area, nc))) return rc;
-    if ((rc = upload(ctx, &D.e_de, g->dual_length, ne))) return rc;
-    if ((rc = upload(ctx, &D.e_le, g->edge_length, ne))) return rc;
+    if ((rc = upload(ctx, &D.c_ia, c_ia.data(), nc))) return rc;
+    if ((rc = upload(ctx, &D.e_ide, e_ide.data(), ne))) return rc;
+    if ((rc = upload(ctx, &D.e_ile, e_ile.data(), ne))) return rc;
     if ((rc = upload(ctx, &D.e_t, g->edge_tangent, 3 * ne))) return rc;
     if ((rc = upload(ctx, &D.fe, fe.data(), ne))) return rc;
     if ((rc = upload(ctx, &D.v_sd, v_sd.data(), 6 * nv))) return rc;
     if ((rc = upload(ctx, &D.v_m, v_m.data(), 6 * nv))) return rc;
-    if ((rc = upload(ctx, &D.v_val, v_val.data(), nv))) return rc;
-    if ((rc = upload(ctx, &D.v_area, g->vert_area, nv))) return rc;
+    if ((rc = upload(ctx, &D.v_ival, v_ival.data(), nv))) return rc;
+    if ((rc = upload(ctx, &D.v_ia, v_ia.data(), nv))) return rc;
     const int64_t NC = int64_t(N) * nc, NC1 = int64_t(N + 1) * nc, NE = int64_t(N) * ne;
     const int64_t NV1 = int64_t(N + 1) * nv;
     if ((rc = upload(ctx, &G.zh, v->zh, NC1))) return rc;
@@ -560,15 +568,15 @@ int nhdc_upload_grid(nhdc_ctx *ctx, const nhdc_grid *g, const nhdc_vertical *v,
         if ((rc = upload_f32(ctx, &F.c_sl, D.c_sl, 3 * nc))) return rc;
         if ((rc = upload_f32(ctx, &F.c_dv, D.c_dv, 9 * nc))) return rc;
         if ((rc = upload_f32(ctx, &F.c_x, D.c_x, 3 * nc))) return rc;
-        if ((rc = upload_f32(ctx, &F.c_area, D.c_area, nc))) return rc;
-        if ((rc = upload_f32(ctx, &F.e_de, D.e_de, ne))) return rc;
-        if ((rc = upload_f32(ctx, &F.e_le, D.e_le, ne))) return rc;
+        if ((rc = upload_f32(ctx, &F.c_ia, D.c_ia, nc))) return rc;
+        if ((rc = upload_f32(ctx, &F.e_ide, D.e_ide, ne))) return rc;
+        if ((rc = upload_f32(ctx, &F.e_ile, D.e_ile, ne))) return rc;
         if ((rc = upload_f32(ctx, &F.e_t, D.e_t, 3 * ne))) return rc;
         if ((rc = upload_f32(ctx, &F.fe, D.fe, ne))) return rc;
         if ((rc = upload_f32(ctx, &F.v_sd, D.v_sd, 6 * nv))) return rc;
         if ((rc = upload_f32(ctx, &F.v_m, D.v_m, 6 * nv))) return rc;
-        if ((rc = upload_f32(ctx, &F.v_val, D.v_val, nv))) return rc;
-        if ((rc = upload_f32(ctx, &F.v_area, D.v_area, nv))) return rc;
+        if ((rc = upload_f32(ctx, &F.v_ival, D.v_ival, nv))) return rc;
+        if ((rc = upload_f32(ctx, &F.v_ia, D.v_ia, nv))) return rc;
     }
 
     // ---- state, accumulators and work arrays ----

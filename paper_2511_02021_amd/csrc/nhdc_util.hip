@@ -17,7 +17,7 @@ __device__ __forceinline__ int64_t lin() { return int64_t(blockIdx.x) * BLOCK + 
 inline unsigned nb(int64_t n) { return unsigned((n + BLOCK - 1) / BLOCK); }
 
 __global__ void k_metrics_vert(int64_t nv, int64_t nc, int N, const int32_t *__restrict__ v_c,
-                               const double *__restrict__ v_m, const double *__restrict__ v_val,
+                               const double *__restrict__ v_m, const double *__restrict__ v_ival,
                                const double *__restrict__ zh, double *__restrict__ zhv) {
     int64_t v = lin();
     if (v >= nv) return;
@@ -25,7 +25,7 @@ __global__ void k_metrics_vert(int64_t nv, int64_t nc, int N, const int32_t *__r
         const double *z = zh + int64_t(i) * nc;
         double s = 0.0;
         for (int j = 0; j < 6; ++j) s += v_m[j * nv + v] * z[v_c[j * nv + v]];
-        zhv[int64_t(i) * nv + v] = s / v_val[v];
+        zhv[int64_t(i) * nv + v] = s * v_ival[v];
     }
 }
 
@@ -113,7 +113,7 @@ __global__ void k_finite(int64_t n, const double *__restrict__ x, int *__restric
 
 hipError_t launch_metrics(const Grid &g, hipStream_t st) {
     hipLaunchKernelGGL(k_metrics_vert, dim3(nb(g.nv)), dim3(BLOCK), 0, st, g.nv, g.nc, g.N, g.v_c,
-                       g.gd.v_m, g.gd.v_val, g.zh, g.zhv);
+                       g.gd.v_m, g.gd.v_ival, g.zh, g.zhv);
     return hipGetLastError();
 }
 
