@@ -179,8 +179,12 @@ int nhdc_autotune(nhdc_ctx *ctx, double dt, int nsubsteps, const char *cache_pat
  * bitwise those of stepping each instance alone with the same tiles. */
 typedef struct nhdc_batch nhdc_batch;
 
-/* Borrow n (1..64) contexts, all on one device and of one precision, each
- * with grid and state; they must outlive the batch. */
+#define NHDC_MAX_INST 64
+
+/* Borrow n (1..NHDC_MAX_INST) contexts, all on one device and of one
+ * precision, each with grid and state; they must outlive the batch.
+ * NHDC_EINVAL for n out of range, a repeated or unready context, or mixed
+ * devices or precisions. */
 int nhdc_batch_create(nhdc_batch **out, nhdc_ctx *const *instances, int n);
 /* nsteps steps of (dt[i], nsubsteps) for every instance i, enqueued on stream. */
 int nhdc_batch_step(nhdc_batch *b, const double *dt, int nsubsteps, int nsteps, void *stream);

@@ -11,7 +11,7 @@
 namespace nhdc {
 
 constexpr int BLOCK = 256;      // lanes per workgroup (4 wavefronts)
-constexpr int MAX_INST = 64;    // instances of one batched launch
+constexpr int MAX_INST = NHDC_MAX_INST;  // instances of one batched launch
 
 // Stencil coefficients in one precision.  The FP64 form reads the double
 // set; the mixed form's FP32 stencils read float copies of the same values.

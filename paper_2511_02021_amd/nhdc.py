@@ -13,6 +13,7 @@ import numpy as np
 from . import _build
 
 NHDC_FP64, NHDC_MIXED = 0, 1
+MAX_INST = 64  # NHDC_MAX_INST: instances of one batch
 PRECISIONS = {"fp64": NHDC_FP64, "mixed": NHDC_MIXED}
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EGRID", -5: "ESTATE", -6: "EUNSTABLE"}
 

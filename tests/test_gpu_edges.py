@@ -1,0 +1,117 @@
+"""Edge cases of the HIP path through the C-ABI: the smallest grids (a single
+ragged block), the fewest and the most levels the library takes, substep
+counts, extreme level tiles, a batch at its instance limit, and the
+properties that hold at the largest benchmark sizes where the oracle cannot
+follow.  FP64 results are compared with the oracle (or with the same
+instance run alone) bit for bit."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2511_02021_amd.inputs import case as CS
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("vn", "w", "rho", "pi", "theta_v", "pi_prev")
+
+
+def _nhdc():
+    from paper_2511_02021_amd import nhdc
+    return nhdc
+
+
+def _case(k, n_lev, tag=0, dt=None):
+    deep = n_lev > 60
+    return CS.make_case(k, n_lev, z_top=75000.0 if deep else 30000.0, stretch=1.6 if deep else 1.0,
+                        terrain_seed=[9, k, n_lev, tag], noise_seed=[8, k, n_lev, tag],
+                        dt=dt if dt is not None else 300.0 / (k + 1))
+
+
+def _gpu(case, steps, nsub=5, tiles=None):
+    d = _nhdc().Dycore(case)
+    if tiles:
+        d.set_tiles(*tiles)
+    for _ in range(steps):
+        d.step(case.dt, nsub)
+    s, f = d.get_state(), d.mass_flux()
+    d.close()
+    return s, f
+
+
+def _oracle(case, steps, nsub=5):
+    m = oracle.Model(case)
+    for _ in range(steps):
+        m.step(case.dt, nsub)
+    return m.state(), m.flux()
+
+
+def _same(a, b, label):
+    bad = {f: int(np.count_nonzero(a[f] != b[f])) for f in FIELDS}
+    print(label, "differing entries", bad, flush=True)
+    assert not any(bad.values()), (label, bad)
+
+
+@pytest.mark.parametrize("k,n_lev", [(0, 2), (1, 3), (2, 7), (1, 256)])
+def test_small_ragged_and_deep_grids_bitwise(k, n_lev):
+    """R2B0 (80 cells: one partial block per kind), R2B1/R2B2 with ragged
+    tails, the minimum of two levels and the library's maximum of 256."""
+    c = _case(k, n_lev)
+    gs, gf = _gpu(c, 3)
+    os_, of = _oracle(c, 3)
+    _same(gs, os_, f"R2B{k}x{n_lev}")
+    assert np.array_equal(gf[0], of[0]) and np.array_equal(gf[1], of[1])
+
+
+@pytest.mark.parametrize("nsub", [1, 2, 3, 7])
+def test_substep_counts_bitwise(nsub):
+    c = _case(2, 10, tag=nsub)
+    gs, gf = _gpu(c, 2, nsub=nsub)
+    os_, of = _oracle(c, 2, nsub=nsub)
+    _same(gs, os_, f"nsub={nsub}")
+    assert np.array_equal(gf[0], of[0]) and np.array_equal(gf[1], of[1])
+
+
+def test_extreme_level_tiles_are_result_neutral():
+    c = _case(3, 20)
+    ref, rf = _gpu(c, 2)
+    for tiles in ((1, 1, 1), (300, 300, 300), (3, 19, 2), (20, 21, 1)):
+        s, f = _gpu(c, 2, tiles=tiles)
+        _same(s, ref, f"tiles {tiles}")
+        assert np.array_equal(f[0], rf[0]) and np.array_equal(f[1], rf[1])
+
+
+def test_batch_at_the_instance_limit():
+    """64 uneven small instances in one launch per kernel (graph replay): each
+    equals the same instance run alone; a 65th is refused."""
+    nhdc = _nhdc()
+    rng = np.random.default_rng([2, 99])
+    shapes = [(int(rng.integers(0, 2)), int(rng.integers(2, 13))) for _ in range(nhdc.MAX_INST)]
+    cases = [_case(k, n, tag=i) for i, (k, n) in enumerate(shapes)]
+    ds = [nhdc.Dycore(c) for c in cases]
+    b = nhdc.Batch(ds)
+    b.step([c.dt for c in cases], 5, nsteps=2)
+    for i, (c, d) in enumerate(zip(cases, ds)):
+        alone, _ = _gpu(c, 2)
+        _same(d.get_state(), alone, f"instance {i} R2B{shapes[i][0]}x{shapes[i][1]}")
+    b.close()
+    extra = nhdc.Dycore(cases[0])
+    with pytest.raises(nhdc.NhdcError) as ei:
+        nhdc.Batch(ds + [extra])
+    assert ei.value.code == -1
+    for d in ds + [extra]:
+        d.close()
+
+
+def test_full_size_r2b7_mixed_properties():
+    """The R2B7x90 benchmark workload in the FP32-mixed form: one step stays
+    finite and conserves dry mass and rho*theta_v to FP64 round-off (the
+    oracle does not run at this size)."""
+    c = CS.config_case(3)
+    d = _nhdc().Dycore(c, precision="mixed")
+    m0, r0 = d.diag()
+    d.step(c.dt, c.nsub)
+    d.check_finite()
+    m1, r1 = d.diag()
+    d.close()
+    print(f"R2B7x90 mixed: mass {m1 / m0 - 1:.2e}  rho*theta_v {r1 / r0 - 1:.2e}", flush=True)
+    assert abs(m1 / m0 - 1) <= 1e-13 and abs(r1 / r0 - 1) <= 1e-13
