@@ -75,12 +75,16 @@ def algorithmic_bytes(nc, ne, nv, N, prec="fp64", nsub=5):
     return {k: sum(v) / len(v) for k, v in t.items()}
 
 
+KERNEL_SOURCES = ("nhdc_step.inc", "nhdc_fp64.hip", "nhdc_mixed.hip", "nhdc_internal.h")
+
+
 def kernel_source_hash():
+    """Identifies the device code of the step kernels (counter summaries taken
+    on other sources no longer describe them)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2511_02021_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h", ".inc")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -96,6 +100,30 @@ def measured_traffic(kernel, src_hash, precision):
     if not m or not b or m.group(1) != src_hash:
         return None
     return float(b.group(1))
+
+
+LAUNCHES_PER_STEP = {"vt_edge": 2, "vertex": 2, "cell_vt": 2, "edge_pred": 1, "column_pred": 1,
+                     "edge_corr": 1, "column_corr": 1}  # per substep
+
+
+def step_traffic(src_hash, precision, nsub):
+    """HBM bytes of one whole step from the committed counter summary (every
+    kernel's counted bytes per launch x its launches), if it was taken on the
+    current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"dycore_{precision}_r2b6x90_hbm_counters.txt")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"kernel_source_sha256_16:\s*(\w+)", txt)
+    if not m or m.group(1) != src_hash:
+        return None
+    total = 0.0
+    for k, n in LAUNCHES_PER_STEP.items():
+        b = re.search(rf"^{k}\s+.*?hbm_bytes_per_launch=([0-9.eE+]+)", txt, re.M)
+        if not b:
+            return None
+        total += float(b.group(1)) * n * nsub
+    return total
 
 
 def cpu_baseline(case):
@@ -235,6 +263,9 @@ def bench_default(args, torch, nhdc, CS):
                 "traffic": measured_traffic(dom, src_hash, "fp64"),
                 "alg_bytes_per_launch": int(kern[dom]["alg_bytes"]),
                 "avg_launch_ms": round(kern[dom]["avg_ms"], 5)}
+    step_bytes = step_traffic(src_hash, "fp64", case.nsub)
+    if step_bytes is not None:
+        roofline["step_hbm_GBs"] = round(step_bytes / (forms["fp64"]["ms_per_step"] / 1e3) / 1e9, 1)
     if not args.copy_calibration:  # counter runs keep a single copy: the calibration one
         copy_gbs = copy_bandwidth(torch)
         roofline["copy_GBs"] = round(copy_gbs, 1)
@@ -269,6 +300,7 @@ def bench_default(args, torch, nhdc, CS):
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": forms["fp64"]["ms_per_step"],
+        "simulated_s_per_wall_s": case.dt / (forms["fp64"]["ms_per_step"] / 1e3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
