@@ -80,6 +80,8 @@ typedef struct nhgrid_view {
     const double *edge_tangent;  /* [3][n_edges] t_e */
     const double *edge_length;   /* [n_edges] primal length l_e [m] */
     const double *dual_length;   /* [n_edges] dual length d_e [m] */
+    const double *dual_frac;     /* [n_edges] where the dual arc c1 -> c2 crosses the edge
+                                    midpoint, as a fraction of d_e from c1 */
     const double *vert_x;        /* [3][n_verts] unit vectors */
     const double *vert_area;     /* [n_verts] dual area [m^2] */
     /* maps from the current numbering to canonical ids */

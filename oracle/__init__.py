@@ -11,8 +11,8 @@ from . import build as _build
 _LIB = None
 _GRID_PTRS = ("cell_edges", "cell_verts", "cell_cells", "cell_sign", "edge_cells", "edge_verts",
               "vert_edges", "vert_cells", "vert_sign", "vert_valence", "cell_x", "cell_area",
-              "edge_x", "edge_normal", "edge_tangent", "edge_length", "dual_length", "vert_x",
-              "vert_area")
+              "edge_x", "edge_normal", "edge_tangent", "edge_length", "dual_length", "dual_frac",
+              "vert_x", "vert_area")
 
 
 class OrGrid(C.Structure):
@@ -22,7 +22,7 @@ class OrGrid(C.Structure):
 
 class OrParams(C.Structure):
     _fields_ = [(n, C.c_double) for n in ("radius", "omega", "grav", "rd", "cpd", "p00", "beta",
-                                          "wgt_corr", "extrap", "div_damp")]
+                                          "wgt_corr", "extrap", "div_damp")] + [("upwind", C.c_int)]
 
 
 def lib():
@@ -47,6 +47,10 @@ def lib():
                   "or_op_vert_avg"):
             getattr(L, f).argtypes = [vp, vp, vp]
             getattr(L, f).restype = None
+        L.or_op_cell_grad.argtypes = [vp, vp, vp, vp]
+        L.or_op_cell_grad.restype = None
+        L.or_op_upwind.argtypes = [vp] * 5 + [d, vp]
+        L.or_op_upwind.restype = None
         L.or_op_perot.argtypes = [vp] * 7
         L.or_op_perot.restype = None
         L.or_thomas.argtypes = [i] + [vp] * 5
@@ -84,7 +88,7 @@ class _GridHandle:
 
 def params_struct(p):
     return OrParams(p.radius, p.omega, p.grav, p.rd, p.cpd, p.p00, p.beta, p.wgt_corr, p.extrap,
-                    p.div_damp)
+                    p.div_damp, int(p.upwind))
 
 
 class Model:
@@ -188,6 +192,26 @@ def cell_avg(grid, q):
 
 def vert_avg(grid, p):
     return _op("or_op_vert_avg", grid, p, grid.n_verts)
+
+
+def cell_grad(grid, p, radial_c=None):
+    """Green-Gauss horizontal gradient of a cell field, [3][n_cells] per metre;
+    radial_c (default: the unit cell centres) is the direction removed."""
+    h = _GridHandle(grid)
+    p = _f64(p)
+    rc = _f64(grid.cell_x if radial_c is None else radial_c)
+    out = np.empty((3, grid.n_cells))
+    lib().or_op_cell_grad(h.ref, _p(p), _p(rc), _p(out))
+    return out
+
+
+def upwind(grid, p, grad, u, vt, dt):
+    """Second-order upwind edge values of a cell field (one level)."""
+    h = _GridHandle(grid)
+    p, grad, u, vt = (_f64(a) for a in (p, grad, u, vt))
+    out = np.empty(grid.n_edges)
+    lib().or_op_upwind(h.ref, _p(p), _p(grad), _p(u), _p(vt), float(dt), _p(out))
+    return out
 
 
 def perot(grid, pos_c, pos_e, radial_c, u):

@@ -38,6 +38,8 @@ struct or_model {
     double *tvn0, *tw0, *wcc0, *tvn1, *tw1, *wcc1;
     double *gp, *dpz, *pix, *the, *rhoe, *flx, *hfl, *divr, *divt, *vns, *dvs;
     double *ws, *rhos, *pis, *thvs, *vnn, *vflux, *rho_i, *thv_i, *twm;
+    double *grad_r, *grad_t; /* [N][3][nc] cell gradients of rho and theta_v (upwind option) */
+    double *rhoe_u, *the_u;  /* [N][ne] upwind edge values (upwind option) */
 };
 
 #define AT(a, k, n, i) ((a)[(int64_t)(k) * (n) + (i)])
@@ -108,6 +110,39 @@ void or_op_vert_avg(const or_grid *g, const double *p, double *out) {
     }
 }
 
+void or_op_cell_grad(const or_grid *g, const double *p, const double *rc, double *out) {
+    const int64_t nc = g->nc, ne = g->ne;
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < nc; ++c) {
+        double v[3] = {0.0, 0.0, 0.0};
+        for (int j = 0; j < 3; ++j) {
+            int64_t e = g->cell_edges[j * nc + c];
+            double p1 = p[g->edge_cells[e]], p2 = p[g->edge_cells[ne + e]];
+            double pe = p1 + g->dual_frac[e] * (p2 - p1);
+            double wgt = g->cell_sign[j * nc + c] * g->edge_length[e] * pe;
+            for (int d = 0; d < 3; ++d) v[d] += wgt * g->edge_normal[d * ne + e];
+        }
+        for (int d = 0; d < 3; ++d) v[d] = v[d] * (1.0 / g->cell_area[c]);
+        double r = v[0] * rc[c] + v[1] * rc[nc + c] + v[2] * rc[2 * nc + c];
+        for (int d = 0; d < 3; ++d) out[d * nc + c] = v[d] - r * rc[d * nc + c];
+    }
+}
+
+void or_op_upwind(const or_grid *g, const double *p, const double *grad, const double *u,
+                  const double *vt, double dt, double *out) {
+    const int64_t nc = g->nc, ne = g->ne;
+    const double a = g->radius;
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < ne; ++e) {
+        int64_t up = u[e] >= 0.0 ? g->edge_cells[e] : g->edge_cells[ne + e];
+        double d[3];
+        for (int x = 0; x < 3; ++x)
+            d[x] = a * (g->edge_x[x * ne + e] - g->cell_x[x * nc + up]) -
+                   0.5 * dt * (u[e] * g->edge_normal[x * ne + e] + vt[e] * g->edge_tangent[x * ne + e]);
+        out[e] = p[up] + (grad[up] * d[0] + grad[nc + up] * d[1] + grad[2 * nc + up] * d[2]);
+    }
+}
+
 void or_op_perot(const or_grid *g, const double *pc, const double *pe, const double *rc,
                  const double *u, double *vc, double *vt) {
     const int64_t nc = g->nc, ne = g->ne;
@@ -166,6 +201,12 @@ or_model *or_create(const or_grid *g, int N, const double *zh, const double *pi_
     ok &= (m->zv = alloc(NV)) != NULL;
     ok &= (m->wv = alloc(NV1)) != NULL;
     ok &= (m->fe = alloc(ne)) != NULL;
+    if (p->upwind) {
+        ok &= (m->grad_r = alloc(3 * NC)) != NULL;
+        ok &= (m->grad_t = alloc(3 * NC)) != NULL;
+        ok &= (m->rhoe_u = alloc(NE)) != NULL;
+        ok &= (m->the_u = alloc(NE)) != NULL;
+    }
     if (!ok) {
         or_free(m);
         return NULL;
@@ -220,7 +261,8 @@ void or_free(or_model *m) {
                      m->omega, m->wv, m->pcx, m->pcy, m->pcz, m->ke, m->ae, m->tvn0, m->tw0,
                      m->wcc0, m->tvn1, m->tw1, m->wcc1, m->gp, m->dpz, m->pix, m->the, m->rhoe,
                      m->flx, m->hfl, m->divr, m->divt, m->vns, m->dvs, m->ws, m->rhos, m->pis,
-                     m->thvs, m->vnn, m->vflux, m->rho_i, m->thv_i, m->twm};
+                     m->thvs, m->vnn, m->vflux, m->rho_i, m->thv_i, m->twm, m->grad_r,
+                     m->grad_t, m->rhoe_u, m->the_u};
     for (size_t i = 0; i < sizeof(all) / sizeof(*all); ++i) free(all[i]);
     free(m);
 }
@@ -564,17 +606,40 @@ static void column_phase(or_model *m, double dt, const double *rho_i, const doub
     }
 }
 
-/* edge fluxes of mass and rho*theta_v and their cell divergences per unit height */
-static void flux_phase(or_model *m, const double *vnx) {
+/* cell gradients of rho and theta_v of state n, level by level (upwind option) */
+static void gradient_phase(or_model *m) {
+    const int64_t nc = m->g.nc;
+    for (int k = 0; k < m->N; ++k) {
+        or_op_cell_grad(&m->g, m->rho + (int64_t)k * nc, m->g.cell_x, m->grad_r + (int64_t)k * 3 * nc);
+        or_op_cell_grad(&m->g, m->thv + (int64_t)k * nc, m->g.cell_x, m->grad_t + (int64_t)k * 3 * nc);
+    }
+}
+
+/* edge fluxes of mass and rho*theta_v, with the flux velocity vnx, and their
+ * cell divergences per unit height.  Edge values of rho and theta_v: the
+ * centred averages of state n, or (upwind) the upwind cell's value plus its
+ * gradient dotted with the displacement to the back-trajectory midpoint, the
+ * trajectory following (vnx, vt) over the substep dt. */
+static void flux_phase(or_model *m, const double *vnx, double dt) {
     const or_grid *g = &m->g;
     const int64_t nc = g->nc, ne = g->ne;
     const int N = m->N;
+    const double *rhoe = m->rhoe, *the = m->the;
+    if (m->p.upwind) {
+        for (int k = 0; k < N; ++k) {
+            const int64_t oe = (int64_t)k * ne, oc = (int64_t)k * nc;
+            or_op_upwind(g, m->rho + oc, m->grad_r + 3 * oc, vnx + oe, m->vt + oe, dt, m->rhoe_u + oe);
+            or_op_upwind(g, m->thv + oc, m->grad_t + 3 * oc, vnx + oe, m->vt + oe, dt, m->the_u + oe);
+        }
+        rhoe = m->rhoe_u;
+        the = m->the_u;
+    }
 #pragma omp parallel for schedule(static)
     for (int64_t e = 0; e < ne; ++e)
         for (int k = 0; k < N; ++k) {
-            double f = AT(m->rhoe, k, ne, e) * AT(vnx, k, ne, e) * AT(m->dz_e, k, ne, e);
+            double f = AT(rhoe, k, ne, e) * AT(vnx, k, ne, e) * AT(m->dz_e, k, ne, e);
             AT(m->flx, k, ne, e) = f;
-            AT(m->hfl, k, ne, e) = AT(m->the, k, ne, e) * f;
+            AT(m->hfl, k, ne, e) = AT(the, k, ne, e) * f;
         }
     for (int k = 0; k < N; ++k) {
         or_op_div(g, m->flx + (int64_t)k * ne, m->divr + (int64_t)k * nc);
@@ -621,7 +686,8 @@ static void substep(or_model *m, double dt, int nsub) {
                                          p->cpd * AT(m->the, k, ne, e) * AT(m->gp, k, ne, e));
         }
     }
-    flux_phase(m, m->vns);
+    if (p->upwind) gradient_phase(m);
+    flux_phase(m, m->vns, dt);
     column_phase(m, dt, m->rho, m->thv, m->tw0, m->wcc0, m->ws, m->rhos, m->pis, m->thvs, NULL);
 
     /* corrector: tendencies of the predicted state */
@@ -640,7 +706,7 @@ static void substep(or_model *m, double dt, int nsub) {
             AT(m->vnn, k, ne, e) = AT(m->vn, k, ne, e) + dt * tend + p->div_damp * abar * gdiv;
         }
     }
-    flux_phase(m, m->vnn);
+    flux_phase(m, m->vnn, dt);
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < NC; ++i) {
         m->rho_i[i] = 0.5 * (m->rho[i] + m->rhos[i]);

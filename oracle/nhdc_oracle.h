@@ -33,6 +33,14 @@
  *     the predicted state; corrector vn with averaged tendencies and
  *     divergence damping; fluxes; column solve about state n with interface
  *     values averaged between n and *; FP64 mass-flux accumulation.
+ *   edge values of rho and theta_v in the fluxes: the centred average E, or
+ *     (option) second-order upwind: psi_up + grad(psi)_up . d, where up is
+ *     the cell the normal flux comes from, grad the cell's Green-Gauss
+ *     gradient (1/A_c) sum_j s l psi_ej n (radial part removed) with psi_ej
+ *     interpolated along the dual arc to the edge midpoint, and d the
+ *     displacement from the upwind cell centre to the midpoint of the edge
+ *     midpoint's back trajectory over the substep, a (x_e - x_up) -
+ *     dt/2 (vn n + vt t).
  *   column solve: explicit parts, tridiagonal system in w on interior half
  *     levels (Thomas, no pivoting), then rho, Exner, theta_v updates; theta_v
  *     from the linearised equation of state so that rho*theta_v is in flux form.
@@ -63,6 +71,7 @@ typedef struct or_grid {
     const double *cell_x, *cell_area;                    /* [3][nc], [nc] */
     const double *edge_x, *edge_normal, *edge_tangent;   /* [3][ne] */
     const double *edge_length, *dual_length;             /* [ne] */
+    const double *dual_frac;  /* [ne] the edge midpoint's position along the dual arc c1 -> c2 */
     const double *vert_x, *vert_area;                    /* [3][nv], [nv] */
 } or_grid;
 
@@ -72,6 +81,9 @@ typedef struct or_params {
     double wgt_corr;  /* corrector weight of the new tendency */
     double extrap;    /* Exner-perturbation extrapolation factor */
     double div_damp;  /* divergence damping coefficient */
+    int upwind;       /* edge values of rho and theta_v in the fluxes: 0 centred average,
+                         1 second-order upwind (cell gradient at the upwind cell, evaluated
+                         at the back-trajectory midpoint of the edge) */
 } or_params;
 
 typedef struct or_model or_model;
@@ -105,6 +117,17 @@ void or_op_tgrad(const or_grid *g, const double *q_v, double *out_e);
 void or_op_curl(const or_grid *g, const double *u_e, double *out_v);
 void or_op_cell_avg(const or_grid *g, const double *q_e, double *out_c);
 void or_op_vert_avg(const or_grid *g, const double *p_c, double *out_v);
+/* horizontal gradient of a cell field: Green-Gauss over the cell's edges
+ * with edge values interpolated along the dual arc to the edge midpoint,
+ * p_c1 + f (p_c2 - p_c1), minus its component along the cell's radial unit
+ * vector radial_c [3][nc] (the model passes the unit cell centres):
+ * out [3][nc], per metre */
+void or_op_cell_grad(const or_grid *g, const double *p_c, const double *radial_c, double *out);
+/* second-order upwind edge values of a cell field with its gradient [3][nc]:
+ * psi_up + grad_up . (a (x_e - x_up) - dt/2 (u n + vt t)), up = c1 if u >= 0
+ * else c2; u, vt the normal and tangential velocity [ne]; out [ne] */
+void or_op_upwind(const or_grid *g, const double *p_c, const double *grad, const double *u,
+                  const double *vt, double dt, double *out_e);
 /* Perot reconstruction with explicit positions [3][n] (metres) and cell radial
  * unit vectors: out_vc [3][nc] cell vectors, out_vt [ne] tangential velocity. */
 void or_op_perot(const or_grid *g, const double *pos_c, const double *pos_e,

@@ -41,6 +41,7 @@ class Params:
     wgt_corr: float = 0.75          # weight of the corrector tendency
     extrap: float = 1.0 / 3.0       # Exner extrapolation factor
     div_damp: float = 0.01          # second-order divergence damping coefficient
+    upwind: int = 0                 # edge rho, theta_v in fluxes: 0 centred, 1 second-order upwind
 
     @property
     def cvd(self):

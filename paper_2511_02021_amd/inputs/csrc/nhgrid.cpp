@@ -83,7 +83,7 @@ struct nhgrid {
     std::vector<int32_t> vert_edges, vert_cells, vert_valence;
     std::vector<int8_t> vert_sign;
     std::vector<double> cell_x, cell_area, edge_x, edge_normal, edge_tangent, edge_length,
-        dual_length, vert_x, vert_area;
+        dual_length, dual_frac, vert_x, vert_area;
     std::vector<int32_t> canon_cell, canon_edge, canon_vert;
 };
 
@@ -263,6 +263,7 @@ extern "C" int nhgrid_build(int k, double radius, nhgrid **out) {
         g->edge_tangent.assign(3 * ne, 0.0);
         g->edge_length.assign(ne, 0.0);
         g->dual_length.assign(ne, 0.0);
+        g->dual_frac.assign(ne, 0.0);
         g->edge_verts.assign(2 * ne, -1);
         for (int64_t e = 0; e < ne; ++e) {
             V3 va = vx[eva[e]], vb = vx[evb[e]];
@@ -286,6 +287,8 @@ extern "C" int nhgrid_build(int k, double radius, nhgrid **out) {
             g->edge_tangent[2 * ne + e] = t.z;
             g->edge_length[e] = a * angle(va, vb);
             g->dual_length[e] = a * angle(c1, c2);
+            // the dual arc c1 -> c2 crosses the primal edge at its midpoint
+            g->dual_frac[e] = angle(c1, xe) / angle(c1, c2);
         }
 
         // ---- vertex rings: counter-clockwise from the lowest-id incident edge ----
@@ -438,6 +441,7 @@ void apply(nhgrid *g, const std::vector<int32_t> &pc, const std::vector<int32_t>
     permute_rows(g->edge_tangent, ne, 3, pe);
     permute_rows(g->edge_length, ne, 1, pe);
     permute_rows(g->dual_length, ne, 1, pe);
+    permute_rows(g->dual_frac, ne, 1, pe);
     permute_rows(g->canon_edge, ne, 1, pe);
     permute_rows(g->vert_edges, nv, 6, pv);
     permute_rows(g->vert_cells, nv, 6, pv);
@@ -550,6 +554,7 @@ extern "C" int nhgrid_get_view(const nhgrid *g, nhgrid_view *v) {
     v->edge_tangent = g->edge_tangent.data();
     v->edge_length = g->edge_length.data();
     v->dual_length = g->dual_length.data();
+    v->dual_frac = g->dual_frac.data();
     v->vert_x = g->vert_x.data();
     v->vert_area = g->vert_area.data();
     v->canon_cell = g->canon_cell.data();

@@ -22,8 +22,8 @@ class _View(C.Structure):
         (name, C.c_void_p) for name in (
             "cell_edges", "cell_verts", "cell_cells", "cell_sign", "edge_cells", "edge_verts",
             "vert_edges", "vert_cells", "vert_sign", "vert_valence", "cell_x", "cell_area",
-            "edge_x", "edge_normal", "edge_tangent", "edge_length", "dual_length", "vert_x",
-            "vert_area", "canon_cell", "canon_edge", "canon_vert")]
+            "edge_x", "edge_normal", "edge_tangent", "edge_length", "dual_length", "dual_frac",
+            "vert_x", "vert_area", "canon_cell", "canon_edge", "canon_vert")]
 
 
 _LIB = None
@@ -76,6 +76,7 @@ class Grid:
     edge_tangent: np.ndarray
     edge_length: np.ndarray
     dual_length: np.ndarray
+    dual_frac: np.ndarray
     vert_x: np.ndarray
     vert_area: np.ndarray
     canon_cell: np.ndarray
@@ -110,6 +111,7 @@ def _snapshot(h):
         edge_x=_copy(v.edge_x, f64, (3, ne)), edge_normal=_copy(v.edge_normal, f64, (3, ne)),
         edge_tangent=_copy(v.edge_tangent, f64, (3, ne)),
         edge_length=_copy(v.edge_length, f64, (ne,)), dual_length=_copy(v.dual_length, f64, (ne,)),
+        dual_frac=_copy(v.dual_frac, f64, (ne,)),
         vert_x=_copy(v.vert_x, f64, (3, nv)), vert_area=_copy(v.vert_area, f64, (nv,)),
         canon_cell=_copy(v.canon_cell, i32, (nc,)), canon_edge=_copy(v.canon_edge, i32, (ne,)),
         canon_vert=_copy(v.canon_vert, i32, (nv,)))

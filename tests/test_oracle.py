@@ -107,6 +107,10 @@ def _planar_patch(n=12, jitter=0.08, seed=0):
     tng = np.cross(np.array([0, 0, 1.0])[:, None], nrm, axis=0)
     interior = edge_cells[1] >= 0
     edge_cells[1, ~interior] = edge_cells[0, ~interior]
+    # the dual segment c1 -> c2 passes through the edge midpoint (circumcentres)
+    dual = np.linalg.norm(xc[:, edge_cells[1]] - xc[:, edge_cells[0]], axis=0)
+    frac = np.where(interior, np.linalg.norm(xe - xc[:, edge_cells[0]], axis=0) /
+                    np.where(interior, dual, 1.0), 0.5)
     sign = np.where(edge_cells[0, cell_edges] == np.arange(nc), 1, -1).astype(np.int8)
     z32 = np.zeros((6, 1), np.int32)
     gr = types.SimpleNamespace(
@@ -116,6 +120,7 @@ def _planar_patch(n=12, jitter=0.08, seed=0):
         vert_edges=z32, vert_cells=z32, vert_sign=np.zeros((6, 1), np.int8),
         vert_valence=np.zeros(1, np.int32), cell_x=xc, cell_area=area, edge_x=xe,
         edge_normal=nrm, edge_tangent=tng, edge_length=length, dual_length=np.ones(ne),
+        dual_frac=frac,
         vert_x=np.zeros((3, 1)), vert_area=np.ones(1))
     return gr, interior
 
@@ -465,3 +470,114 @@ def test_flux_accumulators_average_the_substeps():
     rho_chk = c.rho - c.dt * (div + (wacc[:-1] - wacc[1:]) / dz)
     assert np.abs(rho_chk - s["rho"]).max() <= 1e-12 * np.abs(c.rho).max()
     assert np.all(wacc[0] == 0) and np.all(wacc[-1] == 0)
+
+
+# ---------------------------------------------------------------------------
+# second-order upwind edge values (the flux option)
+
+def test_cell_gradient_exact_for_linear_field_on_a_plane():
+    """Green-Gauss with edge values interpolated along the dual segment to the
+    edge midpoint is exact for a linear field on any planar triangulation."""
+    gr, interior = _planar_patch()
+    G2 = np.array([0.7, -1.9, 0.0])
+    psi = G2 @ gr.cell_x
+    up = np.tile(np.array([0.0, 0.0, 1.0])[:, None], (1, gr.n_cells))
+    g = oracle.cell_grad(gr, psi, up)
+    inner = np.all(interior[gr.cell_edges], axis=0)
+    assert inner.sum() > 100
+    assert np.abs(g[:, inner] - G2[:, None]).max() <= 1e-12 * np.abs(G2).max()
+
+
+def test_upwind_edge_value_exact_for_linear_field_on_a_plane():
+    """psi_up + grad_up . d reproduces a linear field at the back-trajectory
+    midpoint of every interior edge whose upwind cell is interior."""
+    gr, interior = _planar_patch(seed=3)
+    G2 = np.array([-0.4, 1.1, 0.0])
+    psi = G2 @ gr.cell_x
+    up = np.tile(np.array([0.0, 0.0, 1.0])[:, None], (1, gr.n_cells))
+    g = oracle.cell_grad(gr, psi, up)
+    rng = np.random.default_rng(5)
+    u, vt, dt = rng.standard_normal(gr.n_edges), rng.standard_normal(gr.n_edges), 0.3
+    rec = oracle.upwind(gr, psi, g, u, vt, dt)
+    P = gr.edge_x - 0.5 * dt * (u * gr.edge_normal + vt * gr.edge_tangent)
+    ucell = np.where(u >= 0, gr.edge_cells[0], gr.edge_cells[1])
+    inner = np.all(interior[gr.cell_edges], axis=0)
+    ok = interior & inner[ucell]
+    assert ok.sum() > 100
+    assert np.abs(rec[ok] - G2 @ P[:, ok]).max() <= 1e-12
+
+
+def test_upwind_takes_the_upwind_cell():
+    g = G.build_grid(3, order="sfc")
+    rng = np.random.default_rng(2)
+    psi = rng.standard_normal(g.n_cells)
+    u = rng.standard_normal(g.n_edges)
+    u[::7] = 0.0                               # zero flux velocity counts as from c1
+    zero = np.zeros((3, g.n_cells))
+    rec = oracle.upwind(g, psi, zero, u, rng.standard_normal(g.n_edges), 60.0)
+    expect = np.where(u >= 0, psi[g.edge_cells[0]], psi[g.edge_cells[1]])
+    assert np.array_equal(rec, expect)
+
+
+def _linear_on_sphere(k, vec):
+    g = G.build_grid(k, order="sfc")
+    psi = vec @ (A * g.cell_x)
+    return g, psi
+
+
+def test_cell_gradient_and_upwind_values_converge_on_the_sphere():
+    """For psi = c . x: the gradient converges to the tangential part of c at
+    first order, a constant field's gradient vanishes at second order, and the
+    upwind value converges to psi at the back-trajectory midpoint at second
+    order (error / mean dual length falls at first order)."""
+    vec = np.array([0.3, -0.5, 0.8]) * 1e-3
+    eg, ec, eu = [], [], []
+    for k in (2, 3, 4, 5):
+        g, psi = _linear_on_sphere(k, vec)
+        gr = oracle.cell_grad(g, psi)
+        t = vec[:, None] - (vec @ g.cell_x)[None, :] * g.cell_x
+        eg.append(np.abs(gr - t).max() / np.linalg.norm(vec))
+        h = g.dual_length.mean()
+        ec.append(np.abs(oracle.cell_grad(g, np.full(g.n_cells, 1.7))).max() * h / 1.7)
+        rng = np.random.default_rng(k)
+        u, vt = 20 * rng.standard_normal(g.n_edges), 20 * rng.standard_normal(g.n_edges)
+        dt = 300.0 / 2 ** (k - 2)
+        rec = oracle.upwind(g, psi, gr, u, vt, dt)
+        P = A * g.edge_x - 0.5 * dt * (u * g.edge_normal + vt * g.edge_tangent)
+        eu.append(np.abs(rec - vec @ P).max() / (np.linalg.norm(vec) * h))
+    rate = lambda e: np.log2(e[-2] / e[-1])
+    assert rate(eg) >= 0.9 and eg[-1] < 1e-2, eg
+    assert rate(ec) >= 1.8, ec
+    assert rate(eu) >= 0.9 and eu[-1] < 5e-3, eu
+
+
+@pytest.mark.parametrize("which", ["flat", "terrain"])
+def test_upwind_option_conserves_mass_and_rho_theta(which):
+    c = CS.config_case(1) if which == "flat" else CS.config_case(2, k=3, n_lev=30)
+    p = CS.Params(upwind=1)
+    m = oracle.Model(c, params=p)
+    M0, R0 = m.diag()
+    for _ in range(20):
+        m.step(c.dt, c.nsub)
+    M, R = m.diag()
+    s = m.state()
+    assert np.abs(s["vn"]).max() > 0.5
+    assert abs(M / M0 - 1) <= 1e-13 and abs(R / R0 - 1) <= 1e-13
+    # the option changes the fluxes, hence the solution
+    m0 = oracle.Model(c)
+    for _ in range(20):
+        m0.step(c.dt, c.nsub)
+    assert not np.array_equal(m0.state()["rho"], s["rho"])
+
+
+def test_upwind_option_keeps_the_rest_state():
+    p = CS.Params(div_damp=0.0, upwind=1)
+    c = CS.make_case(3, 30, z_top=75000.0, stretch=1.6, sigma=0.0, dt=300.0, params=p)
+    s0 = dict(rho=c.rho, pi=c.pi, theta_v=c.theta_v)
+    m = oracle.Model(c)
+    for _ in range(20):
+        m.step(c.dt, c.nsub)
+    s = m.state()
+    assert np.abs(s["vn"]).max() <= 1e-11 and np.abs(s["w"]).max() <= 1e-11
+    for f in s0:
+        assert np.abs(s[f] / s0[f] - 1).max() <= 1e-13, f
