@@ -71,6 +71,8 @@ def algorithmic_bytes(nc, ne, nv, N, prec="fp64", nsub=5):
         #   -> w, rho, thv, pi, px, wacc (+ pi_prev on the last substep)
         "column_corr": [2 * E * 8 + 5 * C * 8 + C1 * 8 + 2 * C * 8 + 3 * C1 * r + C1 * 8 + C1 * 8
                         + C1 * 8 + 4 * C * 8 + C * 8 / nsub + C1 * 8 + gc],
+        # (upwind option) rho, thv -> their gradients, 3 components each
+        "cell_grad": [2 * C * 8 + 6 * C * 8 + gc + ne * (8 + 3 * 8)],
     }
     return {k: sum(v) / len(v) for k, v in t.items()}
 
@@ -248,6 +250,18 @@ def bench_default(args, torch, nhdc, CS):
         tables[prec] = kernel_table(d, case, args.timing_steps, stream, prec)
         d.close()
     forms["mixed"]["speedup_vs_fp64"] = forms["fp64"]["ms_per_step"] / forms["mixed"]["ms_per_step"]
+    # the second-order upwind option of the flux edge values, FP64, same workload
+    import dataclasses
+    upc = dataclasses.replace(case, params=dataclasses.replace(case.params, upwind=1))
+    d = nhdc.Dycore(upc, precision="fp64")
+    ms = timed_steps(torch, lambda: d.step(upc.dt, upc.nsub, stream), args.steps, args.warmup, stream)
+    d.check_finite()
+    up = kernel_table(d, upc, args.timing_steps, stream, "fp64")
+    d.close()
+    forms["fp64_upwind"] = {"value": units_per_step * args.steps / (ms / 1e3), "ms_per_step": ms / args.steps,
+                            "cost_vs_centred": (ms / args.steps) / forms["fp64"]["ms_per_step"],
+                            "kernels": {k: {"avg_ms": round(v["avg_ms"], 5)} for k, v in up.items()}}
+    log(f"fp64 upwind: {ms / args.steps:.3f} ms/step, {forms['fp64_upwind']['value']:.4e} cell-level updates/s")
     if args.error_steps > 0:
         log(f"per-field error, {args.error_steps} steps ...")
         forms["mixed"]["per_field_error"] = error_table(nhdc, case, args.error_steps)
@@ -415,14 +429,22 @@ PROFILE_CMDS = {
 
 
 def _kernel_id(name):
-    """rocprofv3 kernel name -> (kernel id as in kernel_stats, precision)."""
-    m = re.search(r"k_(vt_edge|vertex|cell_vt|edge_pred|edge_corr|column)<(double|float)(?:, (true|false))?>",
-                  name)
+    """rocprofv3 kernel name -> (kernel id as in kernel_stats, precision); the
+    builds of the upwind option get the suffix _upwind."""
+    m = re.search(r"k_(vt_edge|vertex|cell_vt|edge_pred|edge_corr|column|cell_grad)"
+                  r"<(double|float)((?:, (?:true|false))*)>", name)
     if not m:
         return None, None
     k = m.group(1)
-    if k == "column":
-        k = "column_corr" if m.group(3) == "true" else "column_pred"
+    flags = re.findall(r"true|false", m.group(3))
+    upwind = k == "cell_grad"
+    if k == "column":  # flags: corrector, upwind build
+        k = "column_corr" if flags[0] == "true" else "column_pred"
+        upwind = flags[1] == "true"
+    elif k in ("edge_pred", "edge_corr"):  # flag: upwind build
+        upwind = flags[0] == "true"
+    if upwind and k != "cell_grad":
+        k += "_upwind"
     return k, ("fp64" if m.group(2) == "double" else "mixed")
 
 
@@ -470,7 +492,11 @@ def profile_summary(src, dst):
         agg[(k, prec)][1] += int(r["Calls"])
     lines += ["", "## per kernel id, against the HIP-event averages bench.py measured in the same run",
               f"{'kernel':14s} {'form':6s} {'rocprof_avg_us':>15s} {'hip_event_avg_us':>17s} {'diff%':>7s}"]
-    ev = {"fp64": runs["trace"]["kernels"], "mixed": runs["trace"]["forms"]["mixed"].get("kernels", {})}
+    ev = {"fp64": dict(runs["trace"]["kernels"]),
+          "mixed": runs["trace"]["forms"]["mixed"].get("kernels", {})}
+    for k, v in runs["trace"]["forms"].get("fp64_upwind", {}).get("kernels", {}).items():
+        if k == "cell_grad" or k in ("edge_pred", "edge_corr", "column_pred", "column_corr"):
+            ev["fp64"][k if k == "cell_grad" else k + "_upwind"] = v
     for (k, prec), (tot, n) in sorted(agg.items(), key=lambda kv: (kv[0][1], -kv[1][0])):
         a = tot / n / 1e3
         e = ev.get(prec, {}).get(k, {}).get("avg_ms")
@@ -524,7 +550,8 @@ def profile_summary(src, dst):
             rd = sum(fv) / len(fv)
             wr = sum(wv) / len(wv)
             hbm = rd * 1024 * fs + wr * 1024 * ws
-            base = k if k in alg else "cell_vt"
+            base = k.replace("_upwind", "")
+            base = base if base in alg else "cell_vt"
             a = alg[base]
             lines.append(f"{k:14s} {len(fv):3d} {rd:12.1f} {wr:12.1f}  hbm_bytes_per_launch={hbm:.4e}  "
                          f"alg_bytes_per_launch={a:.4e}  {hbm / (nc * N):8.1f}  {a / (nc * N):8.1f}  "

@@ -82,6 +82,10 @@ typedef struct nhdc_grid {
     const double *edge_length;   /* [n_edges] primal length [m] */
     const double *dual_length;   /* [n_edges] distance between the two circumcentres [m] */
     const double *vert_area;     /* [n_verts] dual area [m^2] */
+    /* read only with the upwind option (may be NULL otherwise): */
+    const double *edge_normal;   /* [3][n_edges] unit normal n_e (from c1 towards c2) */
+    const double *dual_frac;     /* [n_edges] position of the edge midpoint on the dual
+                                    arc c1 -> c2, as a fraction of its length (0..1) */
 } nhdc_grid;
 
 /* Vertical coordinate and reference profile of one column set (host arrays). */
@@ -101,6 +105,12 @@ typedef struct nhdc_params {
     double wgt_corr;  /* weight of the predicted-state tendency in the corrector */
     double extrap;    /* extrapolation factor of the Exner perturbation */
     double div_damp;  /* second-order divergence damping coefficient (times mean cell area) */
+    int32_t upwind;   /* edge values of rho and theta_v in the mass and theta fluxes:
+                         0 the centred average of the two cells; 1 second-order upwind:
+                         the upwind cell's value plus its horizontal gradient (Green-Gauss,
+                         edge values interpolated along the dual arc to the edge midpoint)
+                         dotted with the displacement to the midpoint of the edge
+                         midpoint's back trajectory over the substep, dt/2 (vn n + vt t) */
 } nhdc_params;
 
 /* Prognostic state; pointers are host or device memory per `on_device`.

@@ -47,6 +47,11 @@ struct Grid {
     int32_t *v_c = nullptr;       // [6][nv] vertex ring cells (pad -> slot 0)
     Geo<double> gd;
     Geo<float> gf;
+    // second-order upwind option (FP64; allocated only with the option)
+    double *e_frac = nullptr;     // [ne] edge midpoint's position on the dual arc c1 -> c2
+    double *e_n = nullptr;        // [3][ne] edge normal
+    double *e_d1 = nullptr;       // [3][ne] a (x_e - x_c1)
+    double *e_d2 = nullptr;       // [3][ne] a (x_e - x_c2)
     double *zh = nullptr;         // [N+1][nc] half-level heights
     double *zhv = nullptr;        // [N+1][nv] vertex average of zh
     double *pi_ref = nullptr;     // [N][nc]
@@ -93,10 +98,12 @@ struct Work {
     double *thvs = nullptr;   // [N][nc] predicted theta_v
     double *cp = nullptr, *dp = nullptr;  // [N+1][nc] Thomas factors
     double *rh = nullptr, *ph = nullptr;  // [N][nc] explicit rho and Exner parts
+    double *gr = nullptr, *gt = nullptr;  // [3][N][nc] cell gradients of rho, theta_v (upwind)
 };
 
 struct Params {
     double omega, grav, rd, cpd, p00, beta, wgt_corr, extrap, div_damp;
+    int32_t upwind;  // 1: second-order upwind edge values of rho and theta_v in the fluxes
 };
 
 // Everything one kernel needs about one instance (lives in device memory).
@@ -133,7 +140,7 @@ struct Tune {
 };
 
 enum KernelId { K_VT_EDGE = 0, K_VERTEX, K_CELL_VT, K_EDGE_PRED, K_COLUMN_PRED, K_EDGE_CORR,
-                K_COLUMN_CORR, K_NUM };
+                K_COLUMN_CORR, K_CELL_GRAD, K_NUM };
 extern const char *const kKernelNames[K_NUM];
 
 // Event timing of kernel launches within one step call.
@@ -150,6 +157,7 @@ struct Launcher {
     int precision = NHDC_FP64;
     int n = 0;
     void *d_insts = nullptr;       // Inst<double>[n] or Inst<float>[n] in device memory
+    bool upwind = false;           // some instance uses the second-order upwind option
     Map maps[KIND_NUM];
     int64_t nblocks[KIND_NUM] = {0};
 };

@@ -107,6 +107,8 @@ int upload_insts(Launcher &L, const std::vector<nhdc_ctx *> &ctxs, std::string &
     if (e != hipSuccess) return hip_fail(err, e, "instance descriptors: hipMemcpy");
     L.precision = prec;
     L.n = n;
+    L.upwind = false;
+    for (auto *c : ctxs) L.upwind = L.upwind || c->p.upwind != 0;
     return NHDC_OK;
 }
 
@@ -413,6 +415,10 @@ int alloc_work(nhdc_ctx *ctx, Work<RT> &W) {
         if ((rc = dalloc(ctx, q, NC1))) return rc;
     for (auto q : d_e)
         if ((rc = dalloc(ctx, q, NE))) return rc;
+    if (ctx->p.upwind) {
+        if ((rc = dalloc(ctx, &W.gr, 3 * NC))) return rc;
+        if ((rc = dalloc(ctx, &W.gt, 3 * NC))) return rc;
+    }
     return NHDC_OK;
 }
 
@@ -464,8 +470,16 @@ int nhdc_upload_grid(nhdc_ctx *ctx, const nhdc_grid *g, const nhdc_vertical *v,
         if (!q) return set_err(ctx, NHDC_EINVAL, "upload_grid: NULL array");
     if (!(prm->beta >= 0.5 && prm->beta <= 1.0) || !(prm->cpd > prm->rd && prm->rd > 0) ||
         !(prm->grav > 0) || !std::isfinite(prm->omega) || !std::isfinite(prm->extrap) ||
-        !std::isfinite(prm->wgt_corr) || !std::isfinite(prm->div_damp))
+        !std::isfinite(prm->wgt_corr) || !std::isfinite(prm->div_damp) ||
+        (prm->upwind != 0 && prm->upwind != 1))
         return set_err(ctx, NHDC_EINVAL, "upload_grid: bad parameters");
+    if (prm->upwind) {
+        if (!g->edge_normal || !g->dual_frac)
+            return set_err(ctx, NHDC_EINVAL, "upload_grid: the upwind option needs edge_normal and dual_frac");
+        for (int64_t e = 0; e < g->n_edges; ++e)
+            if (!(g->dual_frac[e] > 0.0 && g->dual_frac[e] < 1.0))
+                return set_err(ctx, NHDC_EGRID, "grid: dual_frac outside (0, 1)");
+    }
     int rc = validate(ctx, g, v);
     if (rc) return rc;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
@@ -481,7 +495,7 @@ int nhdc_upload_grid(nhdc_ctx *ctx, const nhdc_grid *g, const nhdc_vertical *v,
     G.radius = a;
     G.abar = 4.0 * 3.14159265358979323846 * a * a / double(nc);
     ctx->p = Params{prm->omega, prm->grav, prm->rd, prm->cpd, prm->p00, prm->beta,
-                    prm->wgt_corr, prm->extrap, prm->div_damp};
+                    prm->wgt_corr, prm->extrap, prm->div_damp, prm->upwind};
 
     // ---- stencil coefficients on the host (each formed exactly as the
     // operators form it, so device sums see the same operands) ----
@@ -562,6 +576,22 @@ int nhdc_upload_grid(nhdc_ctx *ctx, const nhdc_grid *g, const nhdc_vertical *v,
     if ((rc = upload(ctx, &G.pi_ref, v->pi_ref, NC))) return rc;
     if ((rc = upload(ctx, &G.theta_ref, v->theta_ref, NC))) return rc;
     if ((rc = dalloc(ctx, &G.zhv, NV1))) return rc;
+    if (prm->upwind) {
+        // displacements from the two cell centres to the edge midpoint, formed
+        // as the flux reconstruction forms them
+        std::vector<double> d1(3 * ne), d2(3 * ne);
+        for (int64_t e = 0; e < ne; ++e) {
+            const int64_t c1 = g->edge_cells[e], c2 = g->edge_cells[ne + e];
+            for (int x = 0; x < 3; ++x) {
+                d1[x * ne + e] = a * (g->edge_x[x * ne + e] - g->cell_x[x * nc + c1]);
+                d2[x * ne + e] = a * (g->edge_x[x * ne + e] - g->cell_x[x * nc + c2]);
+            }
+        }
+        if ((rc = upload(ctx, &G.e_frac, g->dual_frac, ne))) return rc;
+        if ((rc = upload(ctx, &G.e_n, g->edge_normal, 3 * ne))) return rc;
+        if ((rc = upload(ctx, &G.e_d1, d1.data(), 3 * ne))) return rc;
+        if ((rc = upload(ctx, &G.e_d2, d2.data(), 3 * ne))) return rc;
+    }
     HIP_TRY(ctx, launch_metrics(G, nullptr));
     if (ctx->precision == NHDC_MIXED) {
         Geo<float> &F = G.gf;

@@ -36,7 +36,8 @@ class _Grid(C.Structure):
                 ("radius", C.c_double)] + [(n, C.c_void_p) for n in (
                     "cell_edges", "cell_sign", "edge_cells", "edge_verts", "vert_edges",
                     "vert_cells", "vert_sign", "vert_valence", "cell_x", "cell_area", "edge_x",
-                    "edge_tangent", "edge_length", "dual_length", "vert_area")]
+                    "edge_tangent", "edge_length", "dual_length", "vert_area", "edge_normal",
+                    "dual_frac")]
 
 
 class _Vertical(C.Structure):
@@ -46,7 +47,7 @@ class _Vertical(C.Structure):
 
 class _Params(C.Structure):
     _fields_ = [(n, C.c_double) for n in ("omega", "grav", "rd", "cpd", "p00", "beta", "wgt_corr",
-                                          "extrap", "div_damp")]
+                                          "extrap", "div_damp")] + [("upwind", C.c_int32)]
 
 
 class _State(C.Structure):
@@ -118,7 +119,8 @@ def _stream_ptr(stream):
 
 
 def params_struct(p):
-    return _Params(p.omega, p.grav, p.rd, p.cpd, p.p00, p.beta, p.wgt_corr, p.extrap, p.div_damp)
+    return _Params(p.omega, p.grav, p.rd, p.cpd, p.p00, p.beta, p.wgt_corr, p.extrap, p.div_damp,
+                   int(p.upwind))
 
 
 class Dycore:
@@ -151,7 +153,8 @@ class Dycore:
                    arr("cell_x", np.float64), arr("cell_area", np.float64),
                    arr("edge_x", np.float64), arr("edge_tangent", np.float64),
                    arr("edge_length", np.float64), arr("dual_length", np.float64),
-                   arr("vert_area", np.float64))
+                   arr("vert_area", np.float64), arr("edge_normal", np.float64),
+                   arr("dual_frac", np.float64))
         zh = np.ascontiguousarray(case.zh, dtype=np.float64)
         pr = np.ascontiguousarray(case.pi_ref, dtype=np.float64)
         tr = np.ascontiguousarray(case.theta_ref, dtype=np.float64)
