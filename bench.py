@@ -74,6 +74,15 @@ def algorithmic_bytes(nc, ne, nv, N, prec="fp64", nsub=5):
         # (upwind option) rho, thv -> their gradients, 3 components each
         "cell_grad": [2 * C * 8 + 6 * C * 8 + gc + ne * (8 + 3 * 8)],
     }
+    # builds of the upwind option: the edge kernels also read the six gradient
+    # fields and the edge's displacements, normal and tangent; the predictor
+    # also reads rho and writes both fluxes, which its column then reads in
+    # place of the predicted vn
+    upg = 6 * C * 8 + ne * 12 * 8
+    t["edge_pred_upwind"] = [t["edge_pred"][0] + upg + C * 8 + 2 * E * 8]
+    t["edge_corr_upwind"] = [t["edge_corr"][0] + upg]
+    t["column_pred_upwind"] = [t["column_pred"][0] + E * 8]
+    t["column_corr_upwind"] = list(t["column_corr"])
     return {k: sum(v) / len(v) for k, v in t.items()}
 
 
@@ -185,6 +194,8 @@ def kernel_table(d, case, steps, stream, precision):
     stats = d.kernel_stats()
     d.set_timing(False)
     alg = algorithmic_bytes(g.n_cells, g.n_edges, g.n_verts, case.n_lev, precision)
+    if case.params.upwind:
+        alg = {k: alg.get(k + "_upwind", v) for k, v in alg.items()}
     kern = {k: {"avg_ms": v[0] / v[1], "launches": v[1], "total": v[0]} for k, v in stats.items()
             if v[1]}
     tot = sum(x["total"] for x in kern.values())
@@ -260,7 +271,8 @@ def bench_default(args, torch, nhdc, CS):
     d.close()
     forms["fp64_upwind"] = {"value": units_per_step * args.steps / (ms / 1e3), "ms_per_step": ms / args.steps,
                             "cost_vs_centred": (ms / args.steps) / forms["fp64"]["ms_per_step"],
-                            "kernels": {k: {"avg_ms": round(v["avg_ms"], 5)} for k, v in up.items()}}
+                            "kernels": {k: {"avg_ms": round(v["avg_ms"], 5), "alg_GBs": round(v["alg_GBs"], 1)}
+                                        for k, v in up.items()}}
     log(f"fp64 upwind: {ms / args.steps:.3f} ms/step, {forms['fp64_upwind']['value']:.4e} cell-level updates/s")
     if args.error_steps > 0:
         log(f"per-field error, {args.error_steps} steps ...")
@@ -544,14 +556,13 @@ def profile_summary(src, dst):
                  "units: B/cl = bytes per cell-level (one cell at one full level) per launch", "",
                  f"{'kernel':14s} {'n':>3s} {'fetch_KiB':>12s} {'write_KiB':>12s}  hbm_bytes_per_launch  "
                  f"alg_bytes_per_launch  hbm_B/cl  alg_B/cl  hbm/alg"]
-        for k in sorted(per, key=lambda x: list(alg).index(x.split("_pred")[0].split("_corr")[0])
-                        if x.split("_pred")[0].split("_corr")[0] in alg else 99):
+        order = list(alg)
+        for k in sorted(per, key=lambda x: order.index(x) if x in order else order.index("cell_vt")):
             fv, wv = per[k]
             rd = sum(fv) / len(fv)
             wr = sum(wv) / len(wv)
             hbm = rd * 1024 * fs + wr * 1024 * ws
-            base = k.replace("_upwind", "")
-            base = base if base in alg else "cell_vt"
+            base = k if k in alg else "cell_vt"
             a = alg[base]
             lines.append(f"{k:14s} {len(fv):3d} {rd:12.1f} {wr:12.1f}  hbm_bytes_per_launch={hbm:.4e}  "
                          f"alg_bytes_per_launch={a:.4e}  {hbm / (nc * N):8.1f}  {a / (nc * N):8.1f}  "
