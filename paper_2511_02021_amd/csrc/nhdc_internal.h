@@ -98,7 +98,7 @@ struct Work {
     double *thvs = nullptr;   // [N][nc] predicted theta_v
     double *cp = nullptr, *dp = nullptr;  // [N+1][nc] Thomas factors
     double *rh = nullptr, *ph = nullptr;  // [N][nc] explicit rho and Exner parts
-    double *gr = nullptr, *gt = nullptr;  // [3][N][nc] cell gradients of rho, theta_v (upwind)
+    double *gq = nullptr;  // [N][nc][6] cell gradients of rho, then theta_v (upwind)
 };
 
 struct Params {

@@ -416,8 +416,7 @@ int alloc_work(nhdc_ctx *ctx, Work<RT> &W) {
     for (auto q : d_e)
         if ((rc = dalloc(ctx, q, NE))) return rc;
     if (ctx->p.upwind) {
-        if ((rc = dalloc(ctx, &W.gr, 3 * NC))) return rc;
-        if ((rc = dalloc(ctx, &W.gt, 3 * NC))) return rc;
+        if ((rc = dalloc(ctx, &W.gq, 6 * NC))) return rc;
     }
     return NHDC_OK;
 }
