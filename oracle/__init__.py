@@ -22,7 +22,8 @@ class OrGrid(C.Structure):
 
 class OrParams(C.Structure):
     _fields_ = [(n, C.c_double) for n in ("radius", "omega", "grav", "rd", "cpd", "p00", "beta",
-                                          "wgt_corr", "extrap", "div_damp")] + [("upwind", C.c_int)]
+                                          "wgt_corr", "extrap", "div_damp")] + [("upwind", C.c_int)] + [
+        ("div_damp4", C.c_double), ("smag", C.c_double), ("w_damp", C.c_void_p)]
 
 
 def lib():
@@ -51,6 +52,11 @@ def lib():
         L.or_op_cell_grad.restype = None
         L.or_op_upwind.argtypes = [vp] * 5 + [d, vp]
         L.or_op_upwind.restype = None
+        for f in ("or_op_vector_laplacian", "or_op_graddiv2"):
+            getattr(L, f).argtypes = [vp, vp, vp]
+            getattr(L, f).restype = None
+        L.or_op_deformation.argtypes = [vp] * 4
+        L.or_op_deformation.restype = None
         L.or_op_perot.argtypes = [vp] * 7
         L.or_op_perot.restype = None
         L.or_thomas.argtypes = [i] + [vp] * 5
@@ -86,9 +92,11 @@ class _GridHandle:
         return C.byref(self.s)
 
 
-def params_struct(p):
+def params_struct(p, w_damp=None):
+    """or_params of a case's Params; w_damp (a C-contiguous FP64 array the
+    caller keeps alive) is the per-half-level Rayleigh rate of w, or None."""
     return OrParams(p.radius, p.omega, p.grav, p.rd, p.cpd, p.p00, p.beta, p.wgt_corr, p.extrap,
-                    p.div_damp, int(p.upwind))
+                    p.div_damp, int(p.upwind), p.div_damp4, p.smag, _p(w_damp))
 
 
 class Model:
@@ -100,7 +108,8 @@ class Model:
         self.N = case.n_lev
         self.params = params if params is not None else case.params
         self._g = _GridHandle(case.grid)
-        self._pp = params_struct(self.params)
+        self._wd = None if case.w_damp is None else _f64(case.w_damp)
+        self._pp = params_struct(self.params, self._wd)
         self._keep = [_f64(case.zh), _f64(case.pi_ref), _f64(case.theta_ref)]
         self.pi_ref = self._keep[1]
         self.h = lib().or_create(self._g.ref, self.N, *[_p(a) for a in self._keep],
@@ -214,6 +223,25 @@ def upwind(grid, p, grad, u, vt, dt):
     return out
 
 
+def vector_laplacian(grid, u):
+    """G(D(u)) - T(Z(u)) of an edge field (one level)."""
+    return _op("or_op_vector_laplacian", grid, u, grid.n_edges)
+
+
+def graddiv2(grid, u):
+    """G(D(G(D(u)))) of an edge field (one level)."""
+    return _op("or_op_graddiv2", grid, u, grid.n_edges)
+
+
+def deformation(grid, u, vt):
+    """Horizontal deformation magnitude per cell of the edge velocities u n + vt t."""
+    h = _GridHandle(grid)
+    u, vt = _f64(u), _f64(vt)
+    out = np.empty(grid.n_cells)
+    lib().or_op_deformation(h.ref, _p(u), _p(vt), _p(out))
+    return out
+
+
 def perot(grid, pos_c, pos_e, radial_c, u):
     h = _GridHandle(grid)
     pos_c, pos_e, radial_c, u = (_f64(a) for a in (pos_c, pos_e, radial_c, u))
@@ -232,12 +260,13 @@ def thomas(a, b, c, r):
 
 
 def column(params, dt, zh, pi_ref, theta_ref, pi_n, rho_n, thv_n, rho_i, thv_i, w_n, tw, wcc,
-           div_rho, div_th):
+           div_rho, div_th, w_damp=None):
     N = len(pi_ref)
     ins = [_f64(a) for a in (zh, pi_ref, theta_ref, pi_n, rho_n, thv_n, rho_i, thv_i, w_n, tw, wcc,
                              div_rho, div_th)]
     w, rho, pi, thv, fl = np.empty(N + 1), np.empty(N), np.empty(N), np.empty(N), np.empty(N + 1)
-    pp = params_struct(params)
+    wd = None if w_damp is None else _f64(w_damp)
+    pp = params_struct(params, wd)
     rc = lib().or_column(N, float(dt), C.byref(pp), *[_p(a) for a in ins], _p(w), _p(rho), _p(pi),
                          _p(thv), _p(fl))
     if rc != 0:

@@ -40,6 +40,8 @@ struct or_model {
     double *ws, *rhos, *pis, *thvs, *vnn, *vflux, *rho_i, *thv_i, *twm;
     double *grad_r, *grad_t; /* [N][3][nc] cell gradients of rho and theta_v (upwind option) */
     double *rhoe_u, *the_u;  /* [N][ne] upwind edge values (upwind option) */
+    double *g4;              /* [N][ne] G(D(G(D(vn*)))) (fourth-order divergence damping) */
+    double *kh, *lap;        /* [N][nc] Smagorinsky K_c, [N][ne] vector Laplacian of vn */
 };
 
 #define AT(a, k, n, i) ((a)[(int64_t)(k) * (n) + (i)])
@@ -172,9 +174,76 @@ void or_op_perot(const or_grid *g, const double *pc, const double *pe, const dou
 /* model set-up: metrics derived from the half-level heights                  */
 /* ------------------------------------------------------------------------ */
 
+void or_op_vector_laplacian(const or_grid *g, const double *u, double *out) {
+    const int64_t nc = g->nc, ne = g->ne, nv = g->nv;
+    double *d = alloc(nc), *z = alloc(nv), *gd = alloc(ne), *tz = alloc(ne);
+    or_op_div(g, u, d);
+    or_op_curl(g, u, z);
+    or_op_grad(g, d, gd);
+    or_op_tgrad(g, z, tz);
+    for (int64_t e = 0; e < ne; ++e) out[e] = gd[e] - tz[e];
+    free(d);
+    free(z);
+    free(gd);
+    free(tz);
+}
+
+void or_op_graddiv2(const or_grid *g, const double *u, double *out) {
+    const int64_t nc = g->nc, ne = g->ne;
+    double *d = alloc(nc), *gd = alloc(ne), *d2 = alloc(nc);
+    or_op_div(g, u, d);
+    or_op_grad(g, d, gd);
+    or_op_div(g, gd, d2);
+    or_op_grad(g, d2, out);
+    free(d);
+    free(gd);
+    free(d2);
+}
+
+void or_op_deformation(const or_grid *g, const double *u, const double *vt, double *out) {
+    const int64_t nc = g->nc, ne = g->ne;
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < nc; ++c) {
+        /* Green-Gauss velocity-gradient tensor G[a][b] = (1/A) sum_j s l V_a n_b */
+        double G[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+        for (int j = 0; j < 3; ++j) {
+            int64_t e = g->cell_edges[j * nc + c];
+            double sl = g->cell_sign[j * nc + c] * g->edge_length[e];
+            for (int a = 0; a < 3; ++a) {
+                double va = u[e] * g->edge_normal[a * ne + e] + vt[e] * g->edge_tangent[a * ne + e];
+                double wa = sl * va;
+                for (int b = 0; b < 3; ++b) G[a][b] += wa * g->edge_normal[b * ne + e];
+            }
+        }
+        double ia = 1.0 / g->cell_area[c];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) G[a][b] = G[a][b] * ia;
+        /* projection on the tangent plane: M = P G P, P = I - x x^T */
+        const double x[3] = {g->cell_x[c], g->cell_x[nc + c], g->cell_x[2 * nc + c]};
+        double q[3], H[3][3], r[3], M[3][3];
+        for (int b = 0; b < 3; ++b) q[b] = x[0] * G[0][b] + x[1] * G[1][b] + x[2] * G[2][b];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) H[a][b] = G[a][b] - x[a] * q[b];
+        for (int a = 0; a < 3; ++a) r[a] = H[a][0] * x[0] + H[a][1] * x[1] + H[a][2] * x[2];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) M[a][b] = H[a][b] - r[a] * x[b];
+        /* tension^2 + shear^2 = 2 |sym M|^2 - (tr M)^2 */
+        double tr = M[0][0] + M[1][1] + M[2][2];
+        double s2 = 0.0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double sab = 0.5 * (M[a][b] + M[b][a]);
+                s2 += sab * sab;
+            }
+        double d2 = 2.0 * s2 - tr * tr;
+        out[c] = d2 > 0.0 ? sqrt(d2) : 0.0;
+    }
+}
+
 or_model *or_create(const or_grid *g, int N, const double *zh, const double *pi_ref,
                     const double *theta_ref, const or_params *p) {
     if (!g || !zh || !pi_ref || !theta_ref || !p || N < 2 || N > OR_MAX_LEV) return NULL;
+    if ((p->upwind || p->smag > 0.0) && !g->edge_normal) return NULL;
     or_model *m = (or_model *)calloc(1, sizeof(or_model));
     if (!m) return NULL;
     m->g = *g;
@@ -206,6 +275,11 @@ or_model *or_create(const or_grid *g, int N, const double *zh, const double *pi_
         ok &= (m->grad_t = alloc(3 * NC)) != NULL;
         ok &= (m->rhoe_u = alloc(NE)) != NULL;
         ok &= (m->the_u = alloc(NE)) != NULL;
+    }
+    if (p->div_damp4 != 0.0) ok &= (m->g4 = alloc(NE)) != NULL;
+    if (p->smag > 0.0) {
+        ok &= (m->kh = alloc(NC)) != NULL;
+        ok &= (m->lap = alloc(NE)) != NULL;
     }
     if (!ok) {
         or_free(m);
@@ -262,7 +336,7 @@ void or_free(or_model *m) {
                      m->wcc0, m->tvn1, m->tw1, m->wcc1, m->gp, m->dpz, m->pix, m->the, m->rhoe,
                      m->flx, m->hfl, m->divr, m->divt, m->vns, m->dvs, m->ws, m->rhos, m->pis,
                      m->thvs, m->vnn, m->vflux, m->rho_i, m->thv_i, m->twm, m->grad_r,
-                     m->grad_t, m->rhoe_u, m->the_u};
+                     m->grad_t, m->rhoe_u, m->the_u, m->g4, m->kh, m->lap};
     for (size_t i = 0; i < sizeof(all) / sizeof(*all); ++i) free(all[i]);
     free(m);
 }
@@ -309,14 +383,12 @@ int or_get_flux(const or_model *m, double *facc, double *wacc) {
 /* velocity tendencies                                                       */
 /* ------------------------------------------------------------------------ */
 
-static void vt_phase(or_model *m, const double *vn, const double *w, double *tvn, double *tw,
-                     double *wcc) {
+/* tangential velocity m->vt from the Perot reconstruction, level by level */
+static void perot_phase(or_model *m, const double *vn) {
     const or_grid *g = &m->g;
-    const int64_t nc = g->nc, ne = g->ne, nv = g->nv;
+    const int64_t nc = g->nc, ne = g->ne;
     const int N = m->N;
     const double a = g->radius;
-
-    /* 1. tangential velocity from the Perot reconstruction, level by level */
     for (int k = 0; k < N; ++k) {
         const double *u = vn + (int64_t)k * ne;
 #pragma omp parallel for schedule(static)
@@ -344,6 +416,16 @@ static void vt_phase(or_model *m, const double *vn, const double *w, double *tvn
                                   vz * g->edge_tangent[2 * ne + e];
         }
     }
+}
+
+static void vt_phase(or_model *m, const double *vn, const double *w, double *tvn, double *tw,
+                     double *wcc) {
+    const or_grid *g = &m->g;
+    const int64_t nc = g->nc, ne = g->ne, nv = g->nv;
+    const int N = m->N;
+
+    /* 1. tangential velocity from the Perot reconstruction */
+    perot_phase(m, vn);
     /* 2. vn and vt at half levels; kinetic energy at edges */
 #pragma omp parallel for schedule(static)
     for (int64_t e = 0; e < ne; ++e) {
@@ -538,6 +620,9 @@ int or_column(int N, double dt, const or_params *p, const double *zh, const doub
     or_thomas(N - 1, ta, tb, tc, tr, wp + 1);
     wp[0] = 0.0;
     wp[N] = wcc[N];
+    /* Rayleigh sponge: the solved w is damped before the level updates use it */
+    if (p->w_damp)
+        for (int i = 1; i < N; ++i) wp[i] = wp[i] * (1.0 / (1.0 + dt * p->w_damp[i]));
     for (int i = 0; i <= N; ++i) w_out[i] = wp[i];
     /* implicit vertical mass flux: zero at the lid and the ground */
     double fl[OR_MAX_LEV + 1];
@@ -695,6 +780,11 @@ static void substep(or_model *m, double dt, int nsub) {
     /* divergence of vn* for the damping term */
     for (int k = 0; k < N; ++k) or_op_div(g, m->vns + (int64_t)k * ne, m->dvs + (int64_t)k * nc);
     const double abar = 4.0 * 3.14159265358979323846 * g->radius * g->radius / (double)nc;
+    /* fourth-order divergence damping operator of vn* */
+    const int damp4 = p->div_damp4 != 0.0;
+    if (damp4)
+        for (int k = 0; k < N; ++k) or_op_graddiv2(g, m->vns + (int64_t)k * ne, m->g4 + (int64_t)k * ne);
+    const double c4 = p->div_damp4 * abar * abar;
 #pragma omp parallel for schedule(static)
     for (int64_t e = 0; e < ne; ++e) {
         int64_t c1 = g->edge_cells[e], c2 = g->edge_cells[ne + e];
@@ -703,7 +793,9 @@ static void substep(or_model *m, double dt, int nsub) {
             double tend = (1.0 - cv) * AT(m->tvn0, k, ne, e) + cv * AT(m->tvn1, k, ne, e) -
                           p->cpd * the_s * AT(m->gp, k, ne, e);
             double gdiv = (AT(m->dvs, k, nc, c2) - AT(m->dvs, k, nc, c1)) * (1.0 / g->dual_length[e]);
-            AT(m->vnn, k, ne, e) = AT(m->vn, k, ne, e) + dt * tend + p->div_damp * abar * gdiv;
+            double v = AT(m->vn, k, ne, e) + dt * tend + p->div_damp * abar * gdiv;
+            if (damp4) v = v - c4 * AT(m->g4, k, ne, e);
+            AT(m->vnn, k, ne, e) = v;
         }
     }
     flux_phase(m, m->vnn, dt);
@@ -732,6 +824,31 @@ static void substep(or_model *m, double dt, int nsub) {
     for (int64_t i = 0; i < NC1; ++i) m->wacc[i] += m->vflux[i] / nsub;
 }
 
+/* Smagorinsky diffusion of vn over the step dt, level by level: the cell
+ * coefficient from the deformation of (vn, vt), its edge mean capped for
+ * stability, times the vector Laplacian of the same vn. */
+static void diffusion_phase(or_model *m, double dt) {
+    const or_grid *g = &m->g;
+    const int64_t nc = g->nc, ne = g->ne;
+    const int N = m->N;
+    const double abar = 4.0 * 3.14159265358979323846 * g->radius * g->radius / (double)nc;
+    const double kmax = abar / (25.0 * dt);
+    const double cs2 = m->p.smag * m->p.smag;
+    perot_phase(m, m->vn);
+    for (int k = 0; k < N; ++k) {
+        double *u = m->vn + (int64_t)k * ne, *kh = m->kh + (int64_t)k * nc;
+        double *lap = m->lap + (int64_t)k * ne;
+        or_op_deformation(g, u, m->vt + (int64_t)k * ne, kh);
+        for (int64_t c = 0; c < nc; ++c) kh[c] = cs2 * g->cell_area[c] * kh[c];
+        or_op_vector_laplacian(g, u, lap);
+        for (int64_t e = 0; e < ne; ++e) {
+            double ke = 0.5 * (kh[g->edge_cells[e]] + kh[g->edge_cells[ne + e]]);
+            ke = ke < kmax ? ke : kmax;
+            u[e] = u[e] + dt * ke * lap[e];
+        }
+    }
+}
+
 int or_step(or_model *m, double dt, int nsub) {
     if (!m || !(dt > 0) || !isfinite(dt) || nsub < 1) return -1;
     const int64_t N = m->N;
@@ -739,6 +856,7 @@ int or_step(or_model *m, double dt, int nsub) {
     memset(m->wacc, 0, sizeof(double) * (N + 1) * m->g.nc);
     const double dts = dt / nsub;
     for (int s = 0; s < nsub; ++s) substep(m, dts, nsub);
+    if (m->p.smag > 0.0) diffusion_phase(m, dt);
     return 0;
 }
 

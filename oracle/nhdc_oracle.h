@@ -44,6 +44,18 @@
  *   column solve: explicit parts, tridiagonal system in w on interior half
  *     levels (Thomas, no pivoting), then rho, Exner, theta_v updates; theta_v
  *     from the linearised equation of state so that rho*theta_v is in flux form.
+ *   damping and diffusion around the substep (each optional, off by default):
+ *     fourth-order divergence damping in the corrector, -c4 Abar^2
+ *       G(D(G(D(vn*)))) next to the second-order term c Abar G(D(vn*));
+ *     a Rayleigh sponge on w in both column solves: the solved w at interior
+ *       half level i is multiplied by 1/(1 + dt r_i) before the mass, Exner
+ *       and theta_v updates use it (r_i a given rate profile, 1/s);
+ *     Smagorinsky diffusion of vn once per step, after the substeps, with the
+ *       step's dt: vn += dt K_e L(vn), L(vn) = G(D(vn)) - T(Z(vn)) the C-grid
+ *       vector Laplacian, K_e the mean of the two cells' K_c = c_s^2 A_c |Def|
+ *       capped at Abar/(25 dt); |Def|^2 = tension^2 + shear^2 of the cell's
+ *       velocity-gradient tensor (Green-Gauss over its edges of vn n + vt t,
+ *       projected on the cell's tangent plane).
  *
  * Every array is FP64, level-major [k][entity]; connectivity slot-major.
  * Built with -O2 -ffp-contract=off (no fused multiply-add), OpenMP over
@@ -84,6 +96,9 @@ typedef struct or_params {
     int upwind;       /* edge values of rho and theta_v in the fluxes: 0 centred average,
                          1 second-order upwind (cell gradient at the upwind cell, evaluated
                          at the back-trajectory midpoint of the edge) */
+    double div_damp4; /* fourth-order divergence damping coefficient (times Abar^2); 0 off */
+    double smag;      /* Smagorinsky constant c_s of the horizontal diffusion of vn; 0 off */
+    const double *w_damp; /* [N+1] Rayleigh damping rate of w per half level [1/s]; NULL off */
 } or_params;
 
 typedef struct or_model or_model;
@@ -128,6 +143,15 @@ void or_op_cell_grad(const or_grid *g, const double *p_c, const double *radial_c
  * else c2; u, vt the normal and tangential velocity [ne]; out [ne] */
 void or_op_upwind(const or_grid *g, const double *p_c, const double *grad, const double *u,
                   const double *vt, double dt, double *out_e);
+/* the C-grid vector Laplacian G(D(u)) - T(Z(u)) of an edge field [ne] -> [ne] */
+void or_op_vector_laplacian(const or_grid *g, const double *u, double *out_e);
+/* the fourth-order divergence operator G(D(G(D(u)))) of an edge field [ne] -> [ne] */
+void or_op_graddiv2(const or_grid *g, const double *u, double *out_e);
+/* horizontal deformation magnitude per cell (tension^2 + shear^2)^(1/2) of the
+ * edge velocities u n + vt t: the Green-Gauss tensor (1/A) sum_j s l (u n + vt t) n^T,
+ * projected on the cell's tangent plane by P = I - x x^T (x the unit cell
+ * centre), |Def|^2 = 2 |sym(P G P)|^2 - tr(P G P)^2.  Needs edge_normal. */
+void or_op_deformation(const or_grid *g, const double *u, const double *vt, double *out_c);
 /* Perot reconstruction with explicit positions [3][n] (metres) and cell radial
  * unit vectors: out_vc [3][nc] cell vectors, out_vt [ne] tangential velocity. */
 void or_op_perot(const or_grid *g, const double *pos_c, const double *pos_e,

@@ -42,6 +42,8 @@ class Params:
     extrap: float = 1.0 / 3.0       # Exner extrapolation factor
     div_damp: float = 0.01          # second-order divergence damping coefficient
     upwind: int = 0                 # edge rho, theta_v in fluxes: 0 centred, 1 second-order upwind
+    div_damp4: float = 0.0          # fourth-order divergence damping coefficient (0: off)
+    smag: float = 0.0               # Smagorinsky constant of the diffusion of vn (0: off)
 
     @property
     def cvd(self):
@@ -71,6 +73,8 @@ class Case:
     pi: np.ndarray          # [N, nc] Exner pressure
     theta_v: np.ndarray     # [N, nc]
     h: np.ndarray           # [nc] surface height
+    zeta: np.ndarray = None  # [N+1] flat coordinate of the half levels
+    w_damp: np.ndarray = None  # [N+1] Rayleigh damping rate of w per half level [1/s], or None
     meta: dict = field(default_factory=dict)
 
     @property
@@ -212,7 +216,7 @@ def make_case(k, n_lev, z_top=30000.0, stretch=1.0, terrain_seed=None, noise_see
         (vn,) = G.permute_grid_fields(g, [vn], "edge")
     return Case(grid=g, n_lev=n_lev, params=params, dt=dt, nsub=nsub, zh=zh, pi_ref=pi_ref,
                 theta_ref=theta_ref, vn=vn, w=w, rho=rho, pi=pi, theta_v=theta_v, h=h,
-                meta=dict(meta or {}))
+                zeta=np.ascontiguousarray(zeta), meta=dict(meta or {}))
 
 
 # Named workloads.  dt of R2B7/R2B8 keeps the horizontal sound Courant number
@@ -260,3 +264,28 @@ def batch_cases(n=16, order="sfc"):
 
 def with_params(case, **kw):
     return replace(case, params=replace(case.params, **kw))
+
+
+def sponge_profile(zeta, rate, z_base):
+    """Rayleigh damping rate of w at the half levels of the flat coordinate
+    zeta: Klemp's profile, rate * sin^2(pi/2 (zeta - z_base)/(z_top - z_base))
+    above z_base, 0 below (z_top = zeta[0], the lid)."""
+    zeta = np.asarray(zeta, dtype=np.float64)
+    x = np.clip((zeta - z_base) / (zeta[0] - z_base), 0.0, 1.0)
+    return np.ascontiguousarray(rate * np.sin(0.5 * np.pi * x) ** 2)
+
+
+# damping and diffusion around the substep, all three on: fourth-order
+# divergence damping, a sponge over the top third of a 75 km column (rate
+# 0.05 /s at the lid), Smagorinsky diffusion of vn with c_s = 0.15
+DAMPED = dict(div_damp4=0.0025, smag=0.15, sponge_rate=0.05, sponge_base=50000.0)
+
+
+def with_damping(case, div_damp4=DAMPED["div_damp4"], smag=DAMPED["smag"],
+                 sponge_rate=DAMPED["sponge_rate"], sponge_base=DAMPED["sponge_base"]):
+    """The case with the damping and diffusion options set (a rate of 0 or a
+    base at or above the lid leaves the sponge off)."""
+    wd = None
+    if sponge_rate > 0.0 and sponge_base < case.zeta[0]:
+        wd = sponge_profile(case.zeta, sponge_rate, sponge_base)
+    return replace(case, params=replace(case.params, div_damp4=div_damp4, smag=smag), w_damp=wd)

@@ -209,13 +209,12 @@ def _random_column(N, seed):
                    div_th=div_th)
 
 
-@pytest.mark.parametrize("N,seed", [(3, 0), (5, 1), (8, 2), (20, 3), (90, 4)])
-def test_column_matches_dense_solve_of_implicit_equations(N, seed):
-    """Solve the implicit w / mass / rho*theta_v / linearised-EOS equations as
-    one dense linear system (no substitution, no Thomas) and compare."""
-    p, col = _random_column(N, seed)
-    dt = 60.0
-    out = oracle.column(p, dt, **col)
+def _dense_column(p, dt, col):
+    """The implicit w / mass / rho*theta_v / linearised-EOS equations of one
+    column as one dense linear system (no substitution, no Thomas), solved;
+    also returns a function giving rho, rho*theta_v and the Exner
+    perturbation from the mass, rho*theta_v and state equations for a given w."""
+    N = len(col["pi_ref"])
     zh, prf, trf = col["zh"], col["pi_ref"], col["theta_ref"]
     z = 0.5 * (zh[:-1] + zh[1:])
     dz = zh[:-1] - zh[1:]
@@ -263,10 +262,31 @@ def test_column_matches_dense_solve_of_implicit_equations(N, seed):
         M[iq(k), ix(k)] = -fac
         rhs[iq(k)] = ppn[k] - fac * rtn[k]
     sol = np.linalg.solve(M, rhs)
-    w = sol[:nw]
-    rho = sol[nw:nw + N]
-    X = sol[nw + N:nw + 2 * N]
-    q = sol[nw + 2 * N:]
+
+    def levels(wi):
+        """rho, rho*theta_v, pi' of the level updates with interior w = wi."""
+        fl = np.zeros(N + 1)
+        fl[1:N] = rhoh * ((1 - b) * wn[1:N] + b * wi - wcc[1:N])
+        rho = col["rho_n"] - dt * (col["div_rho"] + (fl[:-1] - fl[1:]) / dz)
+        fh = np.zeros(N + 1)
+        fh[1:N] = thh * fl[1:N]
+        X = rtn - dt * (col["div_th"] + (fh[:-1] - fh[1:]) / dz)
+        q = ppn + (p.rd / p.cvd) * col["pi_n"] / rtn * (X - rtn)
+        return rho, X, q
+
+    return sol[:nw], sol[nw:nw + N], sol[nw + N:nw + 2 * N], sol[nw + 2 * N:], levels
+
+
+@pytest.mark.parametrize("N,seed", [(3, 0), (5, 1), (8, 2), (20, 3), (90, 4)])
+def test_column_matches_dense_solve_of_implicit_equations(N, seed):
+    """Solve the implicit w / mass / rho*theta_v / linearised-EOS equations as
+    one dense linear system (no substitution, no Thomas) and compare."""
+    p, col = _random_column(N, seed)
+    dt = 60.0
+    out = oracle.column(p, dt, **col)
+    prf, dz = col["pi_ref"], col["zh"][:-1] - col["zh"][1:]
+    wcc = col["wcc"]
+    w, rho, X, q, _ = _dense_column(p, dt, col)
     tol = 1e-11
     assert np.abs(out["w"][1:N] - w).max() <= tol * max(np.abs(w).max(), 1e-3)
     assert out["w"][0] == 0.0 and out["w"][N] == wcc[N]
@@ -581,3 +601,196 @@ def test_upwind_option_keeps_the_rest_state():
     assert np.abs(s["vn"]).max() <= 1e-11 and np.abs(s["w"]).max() <= 1e-11
     for f in s0:
         assert np.abs(s[f] / s0[f] - 1).max() <= 1e-13, f
+
+
+# ---------------------------------------------------------------------------
+# damping and diffusion around the substep (options)
+
+def _w_products(g):
+    """C-grid inner products: edges weighted by l_e d_e, cells by A_c,
+    vertices by the dual area."""
+    we = g.edge_length * g.dual_length
+    return (lambda u, v: float(np.sum(we * u * v)),
+            lambda p, q: float(np.sum(g.cell_area * p * q)),
+            lambda p, q: float(np.sum(g.vert_area * p * q)))
+
+
+def test_operators_of_the_damping_are_symmetric_and_dissipative(g4):
+    """In the C-grid inner products G = -D* and T = Z*, so the vector
+    Laplacian L = G D - T Z is symmetric with <L u, u> = -|D u|^2 - |Z u|^2,
+    and the fourth-order operator (G D)^2 is symmetric with
+    <(G D)^2 u, u> = |G D u|^2 (identities of the discrete operators)."""
+    ew, cw, vw = _w_products(g4)
+    rng = np.random.default_rng(11)
+    u, v = rng.standard_normal(g4.n_edges), rng.standard_normal(g4.n_edges)
+    Lu, Lv = oracle.vector_laplacian(g4, u), oracle.vector_laplacian(g4, v)
+    scale = ew(Lu, Lu) ** 0.5 * ew(v, v) ** 0.5
+    assert abs(ew(Lu, v) - ew(u, Lv)) <= 1e-12 * scale
+    du, zu = oracle.div(g4, u), oracle.curl(g4, u)
+    e_lap = -cw(du, du) - vw(zu, zu)
+    assert ew(Lu, u) < 0 and abs(ew(Lu, u) - e_lap) <= 1e-12 * abs(e_lap)
+    Qu, Qv = oracle.graddiv2(g4, u), oracle.graddiv2(g4, v)
+    scale = ew(Qu, Qu) ** 0.5 * ew(v, v) ** 0.5
+    assert abs(ew(Qu, v) - ew(u, Qv)) <= 1e-12 * scale
+    gdu = oracle.grad(g4, du)
+    assert ew(Qu, u) > 0 and abs(ew(Qu, u) - ew(gdu, gdu)) <= 1e-12 * ew(gdu, gdu)
+
+
+def test_fourth_order_damping_leaves_rotational_flow_alone(g4):
+    """D T = 0 on the C-grid, so (G D)^2 of a rotational field T(psi) is
+    round-off next to its value on a divergent field of the same size."""
+    rng = np.random.default_rng(12)
+    psi = rng.standard_normal(g4.n_verts)
+    ur = oracle.tgrad(g4, psi)
+    ud = oracle.grad(g4, rng.standard_normal(g4.n_cells))
+    ud *= np.linalg.norm(ur) / np.linalg.norm(ud)
+    assert np.abs(oracle.graddiv2(g4, ur)).max() <= 1e-12 * np.abs(oracle.graddiv2(g4, ud)).max()
+
+
+def test_divergence_of_gradient_exact_for_quadratic_on_regular_lattice():
+    """On an equilateral lattice (circumcentre = centroid, dual segment bisected
+    by the edge) D(G(x^2 + y^2)) = 4 at every cell whose edges are interior."""
+    gr, interior = _planar_patch(jitter=0.0)
+    gr.dual_length = np.linalg.norm(gr.cell_x[:, gr.edge_cells[1]] - gr.cell_x[:, gr.edge_cells[0]],
+                                    axis=0)
+    gr.dual_length[~interior] = 1.0
+    q = (gr.cell_x[:2] ** 2).sum(0)
+    lap = oracle.div(gr, oracle.grad(gr, q))
+    inner = np.all(interior[gr.cell_edges], axis=0)
+    assert inner.sum() > 100
+    assert np.abs(lap[inner] - 4.0).max() <= 1e-11
+
+
+def test_deformation_exact_for_linear_field_on_a_plane():
+    """For v = M x on a jittered planar patch with the exact edge velocities,
+    |Def| = ((M00 - M11)^2 + (M01 + M10)^2)^(1/2) at interior cells; pure
+    rotation and pure expansion have none."""
+    gr, interior = _planar_patch(seed=7)
+    gr.cell_x = np.tile(np.array([0.0, 0.0, 1.0])[:, None], (1, gr.n_cells))  # radial direction
+    inner = np.all(interior[gr.cell_edges], axis=0)
+    rng = np.random.default_rng(4)
+    for M2 in (rng.standard_normal((2, 2)), np.array([[0.0, -1.3], [1.3, 0.0]]), 0.7 * np.eye(2)):
+        M = np.zeros((3, 3))
+        M[:2, :2] = M2
+        V = M @ gr.edge_x
+        u, vt = (V * gr.edge_normal).sum(0), (V * gr.edge_tangent).sum(0)
+        d = oracle.deformation(gr, u, vt)
+        exact = np.hypot(M2[0, 0] - M2[1, 1], M2[0, 1] + M2[1, 0])
+        # compared as squares: near zero the square root lifts round-off to its root
+        assert np.abs(d[inner] ** 2 - exact ** 2).max() <= 1e-12 * np.abs(M2).max() ** 2, M2
+
+
+def test_deformation_of_solid_body_rotation_vanishes_with_resolution():
+    """Solid-body rotation has no deformation.  With the exact edge velocities
+    the cell deformation falls at first order (max norm); with the model's
+    reconstructed tangential velocity, whose first-order error does not cancel
+    at the grid's irregular cells, its RMS still falls."""
+    u0, ex, rec = 20.0, [], []
+    for k in (2, 3, 4, 5):
+        c = CS.make_case(k, 2, z_top=2000.0, sigma=0.0, order="sfc")
+        g = c.grid
+        _, vn, vt_exact = _solid_body(g, u0)
+        _, _, _, vt = oracle.Model(c).vt(np.tile(vn, (2, 1)), np.zeros((3, g.n_cells)))
+        ex.append(np.abs(oracle.deformation(g, vn, vt_exact)).max() / (u0 / A))
+        rec.append(np.sqrt(np.mean(oracle.deformation(g, vn, vt[0]) ** 2)) / (u0 / A))
+    ex, rec = np.array(ex), np.array(rec)
+    assert np.all(ex[1:] < ex[:-1]) and np.log2(ex[-2] / ex[-1]) > 0.9 and ex[-1] < 1e-2, ex
+    assert np.all(rec[1:] < rec[:-1]) and np.log2(rec[0] / rec[-1]) > 1.2, rec
+
+
+@pytest.mark.parametrize("N,seed", [(5, 1), (20, 3), (90, 4)])
+def test_column_sponge_damps_the_solved_w(N, seed):
+    """With a Rayleigh rate r_i the column's w is the implicit solution times
+    1/(1 + dt r_i) at interior half levels, and rho, theta_v and pi follow
+    from the un-substituted mass, rho*theta_v and state equations with that w."""
+    p, col = _random_column(N, seed)
+    dt = 60.0
+    rate = np.zeros(N + 1)
+    rate[: N // 2 + 1] = np.linspace(0.02, 0.0, N // 2 + 1)
+    out = oracle.column(p, dt, **col, w_damp=rate)
+    w, _, _, _, levels = _dense_column(p, dt, col)
+    wd = w / (1.0 + dt * rate[1:N])
+    rho, X, q = levels(wd)
+    tol = 1e-11
+    assert np.abs(out["w"][1:N] - wd).max() <= tol * max(np.abs(wd).max(), 1e-3)
+    assert out["w"][0] == 0.0 and out["w"][N] == col["wcc"][N]
+    assert np.abs(out["rho"] - rho).max() <= tol * np.abs(rho).max()
+    assert np.abs(out["pi"] - (col["pi_ref"] + q)).max() <= tol * np.abs(col["pi_ref"]).max()
+    assert np.abs(out["theta_v"] - X / rho).max() <= tol * np.abs(X / rho).max()
+    # a zero rate is no sponge, to the bit
+    base = oracle.column(p, dt, **col)
+    zero = oracle.column(p, dt, **col, w_damp=np.zeros(N + 1))
+    for f in base:
+        assert np.array_equal(base[f], zero[f]), f
+
+
+def test_sponge_profile():
+    zeta = CS.flat_coordinate(90, 75000.0, 1.6)
+    r = CS.sponge_profile(zeta, 0.05, 50000.0)
+    assert r[0] == pytest.approx(0.05) and np.all(r[zeta <= 50000.0] == 0.0)
+    assert np.all(np.diff(r[zeta > 50000.0]) < 0)        # rising towards the lid
+
+
+@pytest.mark.parametrize("which", ["flat", "terrain"])
+def test_damping_options_conserve_mass_and_rho_theta(which):
+    """Fourth-order divergence damping, the w sponge and the diffusion of vn
+    leave the flux form intact."""
+    base = CS.config_case(1) if which == "flat" else CS.config_case(2, k=3, n_lev=30)
+    c = CS.with_damping(base, sponge_base=15000.0 if which == "flat" else 50000.0)
+    assert c.w_damp is not None and c.params.smag > 0 and c.params.div_damp4 > 0
+    m = oracle.Model(c)
+    M0, R0 = m.diag()
+    for _ in range(20):
+        m.step(c.dt, c.nsub)
+    M, R = m.diag()
+    s = m.state()
+    assert np.all(np.isfinite(s["vn"])) and np.abs(s["vn"]).max() > 0.1
+    assert abs(M / M0 - 1) <= 1e-13 and abs(R / R0 - 1) <= 1e-13
+    m0 = oracle.Model(base)
+    for _ in range(20):
+        m0.step(base.dt, base.nsub)
+    for f in ("vn", "w", "rho"):
+        assert not np.array_equal(m0.state()[f], s[f]), f
+
+
+def test_damping_options_keep_the_rest_state():
+    p = CS.Params(div_damp=0.0)
+    c = CS.with_damping(CS.make_case(3, 30, z_top=75000.0, stretch=1.6, sigma=0.0, dt=300.0,
+                                     params=p))
+    s0 = dict(rho=c.rho, pi=c.pi, theta_v=c.theta_v)
+    m = oracle.Model(c)
+    for _ in range(20):
+        m.step(c.dt, c.nsub)
+    s = m.state()
+    assert np.abs(s["vn"]).max() <= 1e-11 and np.abs(s["w"]).max() <= 1e-11
+    for f in s0:
+        assert np.abs(s[f] / s0[f] - 1).max() <= 1e-13, f
+
+
+def test_each_damping_option_removes_energy_where_it_acts():
+    """Against the same run without it: the diffusion lowers the horizontal
+    kinetic energy, the fourth-order damping the divergence variance, and the
+    sponge the vertical kinetic energy above its base."""
+    base = CS.config_case(2, k=3, n_lev=30)
+    g = base.grid
+    we = g.edge_length * g.dual_length
+    off = dict(div_damp4=0.0, smag=0.0, sponge_rate=0.0)
+
+    def run(case, steps=10):
+        m = oracle.Model(case)
+        for _ in range(steps):
+            m.step(case.dt, case.nsub)
+        return m.state()
+
+    s0 = run(base)
+    ke = lambda s: float(np.sum(we * s["vn"] ** 2))
+    sd = run(CS.with_damping(base, **{**off, "smag": 0.15}))
+    assert ke(sd) < ke(s0)
+    dv = lambda s: float(sum(np.sum(g.cell_area * oracle.div(g, s["vn"][k]) ** 2)
+                             for k in range(base.n_lev)))
+    s4 = run(CS.with_damping(base, **{**off, "div_damp4": 0.0025}))
+    assert dv(s4) < dv(s0)
+    cs = CS.with_damping(base, **{**off, "sponge_rate": 0.05})
+    top = cs.zeta > 50000.0
+    ss = run(cs)
+    assert np.sum(ss["w"][top] ** 2) < np.sum(s0["w"][top] ** 2)
