@@ -83,6 +83,16 @@ def algorithmic_bytes(nc, ne, nv, N, prec="fp64", nsub=5):
     t["edge_corr_upwind"] = [t["edge_corr"][0] + upg]
     t["column_pred_upwind"] = [t["column_pred"][0] + E * 8]
     t["column_corr_upwind"] = list(t["column_corr"])
+    # damping and diffusion options: D(G(div vn*)) per cell; the once-per-step
+    # diffusion's cell pass (vn, vt -> div, coefficient) and edge pass
+    # (coefficient, div, vorticity, vn -> vn); the corrector's edges also
+    # gather D(G(div vn*)); the sponge's rate profile is N+1 values
+    t["div4"] = [2 * C * r + nc * (3 * 4 + 3 * 4 + 3 * r + r) + ne * r]
+    t["smag_cell"] = [E * 8 + E * r + 2 * C * r + gc + nc * 3 * r + ne * 3 * (8 + r)]
+    t["smag_edge"] = [2 * C * r + V * r + 2 * E * 8 + ge + ne * r]
+    t["edge_corr_div4"] = [t["edge_corr"][0] + C * r]
+    t["column_pred_sponge"] = list(t["column_pred"])
+    t["column_corr_sponge"] = list(t["column_corr"])
     return {k: sum(v) / len(v) for k, v in t.items()}
 
 
@@ -196,6 +206,8 @@ def kernel_table(d, case, steps, stream, precision):
     alg = algorithmic_bytes(g.n_cells, g.n_edges, g.n_verts, case.n_lev, precision)
     if case.params.upwind:
         alg = {k: alg.get(k + "_upwind", v) for k, v in alg.items()}
+    if case.params.div_damp4:
+        alg["edge_corr"] = alg["edge_corr_div4"]
     kern = {k: {"avg_ms": v[0] / v[1], "launches": v[1], "total": v[0]} for k, v in stats.items()
             if v[1]}
     tot = sum(x["total"] for x in kern.values())
@@ -261,19 +273,33 @@ def bench_default(args, torch, nhdc, CS):
         tables[prec] = kernel_table(d, case, args.timing_steps, stream, prec)
         d.close()
     forms["mixed"]["speedup_vs_fp64"] = forms["fp64"]["ms_per_step"] / forms["mixed"]["ms_per_step"]
-    # the second-order upwind option of the flux edge values, FP64, same workload
     import dataclasses
-    upc = dataclasses.replace(case, params=dataclasses.replace(case.params, upwind=1))
-    d = nhdc.Dycore(upc, precision="fp64")
-    ms = timed_steps(torch, lambda: d.step(upc.dt, upc.nsub, stream), args.steps, args.warmup, stream)
-    d.check_finite()
-    up = kernel_table(d, upc, args.timing_steps, stream, "fp64")
-    d.close()
-    forms["fp64_upwind"] = {"value": units_per_step * args.steps / (ms / 1e3), "ms_per_step": ms / args.steps,
-                            "cost_vs_centred": (ms / args.steps) / forms["fp64"]["ms_per_step"],
-                            "kernels": {k: {"avg_ms": round(v["avg_ms"], 5), "alg_GBs": round(v["alg_GBs"], 1)}
-                                        for k, v in up.items()}}
-    log(f"fp64 upwind: {ms / args.steps:.3f} ms/step, {forms['fp64_upwind']['value']:.4e} cell-level updates/s")
+
+    def option_form(label, ocase):
+        """The FP64 step with an option set, same workload and timing."""
+        d = nhdc.Dycore(ocase, precision="fp64")
+        ms = timed_steps(torch, lambda: d.step(ocase.dt, ocase.nsub, stream), args.steps,
+                         args.warmup, stream)
+        d.check_finite()
+        tab = kernel_table(d, ocase, args.timing_steps, stream, "fp64")
+        d.close()
+        out = {"value": units_per_step * args.steps / (ms / 1e3), "ms_per_step": ms / args.steps,
+               "cost_vs_plain": (ms / args.steps) / forms["fp64"]["ms_per_step"],
+               "kernels": {k: {"avg_ms": round(v["avg_ms"], 5), "alg_GBs": round(v["alg_GBs"], 1)}
+                           for k, v in tab.items()}}
+        log(f"fp64 {label}: {ms / args.steps:.3f} ms/step, {out['value']:.4e} cell-level updates/s")
+        return out
+
+    extra = [f for f in args.forms.split(",") if f]
+    if "upwind" in extra:  # second-order upwind edge values of rho and theta_v
+        forms["fp64_upwind"] = option_form("upwind", dataclasses.replace(
+            case, params=dataclasses.replace(case.params, upwind=1)))
+    if "damped" in extra:  # fourth-order divergence damping, w sponge, Smagorinsky diffusion
+        dc = CS.with_damping(case)
+        forms["fp64_damped"] = option_form("damped", dc)
+        forms["fp64_damped"]["options"] = {"div_damp4": dc.params.div_damp4, "smag": dc.params.smag,
+                                           "sponge_rate_at_lid": float(dc.w_damp[0]),
+                                           "sponge_base_m": CS.DAMPED["sponge_base"]}
     if args.error_steps > 0:
         log(f"per-field error, {args.error_steps} steps ...")
         forms["mixed"]["per_field_error"] = error_table(nhdc, case, args.error_steps)
@@ -438,21 +464,28 @@ PROFILE_CMDS = {
              "-- python3 -u bench.py --steps 2 --warmup 1 --timing-steps 1 --error-steps 0 "
              "--no-cpu-baseline --copy-calibration > gpurun_out/prof_write.json",
 }
+for _k in list(PROFILE_CMDS):  # the damping options' kernels in runs of their own
+    PROFILE_CMDS[_k] = PROFILE_CMDS[_k].replace("--no-cpu-baseline", "--no-cpu-baseline --forms upwind")
+    PROFILE_CMDS["d" + _k] = (PROFILE_CMDS[_k].replace("--forms upwind", "--forms damped")
+                              .replace(f"prof_{_k}", f"prof_d{_k}").replace(f"-o {_k}", f"-o d{_k}"))
+DAMPED_KERNELS = ("div4", "smag_cell", "smag_edge", "column_pred_sponge", "column_corr_sponge")
 
 
 def _kernel_id(name):
     """rocprofv3 kernel name -> (kernel id as in kernel_stats, precision); the
     builds of the upwind option get the suffix _upwind."""
-    m = re.search(r"k_(vt_edge|vertex|cell_vt|edge_pred|edge_corr|column|cell_grad)"
-                  r"<(double|float)((?:, (?:true|false))*)>", name)
+    m = re.search(r"k_(vt_edge|vertex|cell_vt|edge_pred|edge_corr|column|cell_grad|div4|smag_cell|"
+                  r"smag_edge)<(double|float)((?:, (?:true|false))*)>", name)
     if not m:
         return None, None
     k = m.group(1)
     flags = re.findall(r"true|false", m.group(3))
     upwind = k == "cell_grad"
-    if k == "column":  # flags: corrector, upwind build
+    if k == "column":  # flags: corrector, upwind build, sponge build
         k = "column_corr" if flags[0] == "true" else "column_pred"
         upwind = flags[1] == "true"
+        if flags[2] == "true":
+            k += "_sponge"
     elif k in ("edge_pred", "edge_corr"):  # flag: upwind build
         upwind = flags[0] == "true"
     if upwind and k != "cell_grad":
@@ -472,7 +505,8 @@ def profile_summary(src, dst):
         with open(path) as f:
             return list(csv.DictReader(f))
 
-    runs = {k: json.load(open(os.path.join(src, f"prof_{k}.json"))) for k in PROFILE_CMDS}
+    runs = {k: json.load(open(os.path.join(src, f"prof_{k}.json"))) for k in PROFILE_CMDS
+            if not k.startswith("d") or os.path.exists(os.path.join(src, f"prof_{k}.json"))}
     hashes = {r["kernel_source_sha256_16"] for r in runs.values()}
     if len(hashes) != 1:
         raise SystemExit(f"profiled runs used different kernel sources: {hashes}")
@@ -569,7 +603,60 @@ def profile_summary(src, dst):
                          f"{hbm / a:7.2f}")
         with open(os.path.join(dst, f"dycore_{prec}_r2b6x90_hbm_counters.txt"), "w") as f:
             f.write("\n".join(lines) + "\n")
+    if all(k in runs for k in ("dtrace", "dfetch", "dwrite")):
+        damped_summary(src, dst, runs, src_hash, wl, nc, ne, nv, N, rows, counter)
     print(f"wrote summaries for kernel sources {src_hash} to {dst}")
+
+
+def damped_summary(src, dst, runs, src_hash, wl, nc, ne, nv, N, rows, counter):
+    """Durations and HBM bytes of the kernels only the damping options run
+    (fourth-order damping, the diffusion's two passes, the sponge's column
+    builds), from runs that time the damped form next to the plain ones."""
+    from collections import defaultdict
+    alg = algorithmic_bytes(nc, ne, nv, N, "fp64")
+    stats = rows(os.path.join(src, "prof_dtrace", "dtrace_kernel_stats.csv"))
+    dur = {}
+    for r in stats:
+        k, prec = _kernel_id(r["Name"])
+        if prec == "fp64" and k in DAMPED_KERNELS:
+            dur[k] = (float(r["AverageNs"]) / 1e3, int(r["Calls"]))
+    fetch, write = counter("dfetch", "FETCH_SIZE"), counter("dwrite", "WRITE_SIZE")
+    copy = [k for k in fetch if "copyBuffer" in k]
+    cf, cw = fetch[copy[0]][-1], write[copy[0]][-1]
+    fs, ws = (1 << 30) / (cf * 1024), (1 << 30) / (cw * 1024)
+    per = defaultdict(lambda: [[], []])
+    for kname, vals in fetch.items():
+        k, p = _kernel_id(kname)
+        if p == "fp64" and k in DAMPED_KERNELS:
+            per[k][0] += vals
+            per[k][1] += write.get(kname, [])
+    ev = runs["dtrace"]["forms"].get("fp64_damped", {}).get("kernels", {})
+    evid = {"div4": "div4", "smag_cell": "smag_cell", "smag_edge": "smag_edge",
+            "column_pred_sponge": "column_pred", "column_corr_sponge": "column_corr"}
+    opts = runs["dtrace"]["forms"].get("fp64_damped", {}).get("options", {})
+    lines = [f"# rocprofv3: kernels of the damping and diffusion options, fp64 form, {wl}",
+             f"options: {json.dumps(opts, sort_keys=True)}",
+             f"kernel_source_sha256_16: {src_hash}",
+             f"command (trace): {PROFILE_CMDS['dtrace']}",
+             f"command (FETCH_SIZE pass): {PROFILE_CMDS['dfetch']}",
+             f"command (WRITE_SIZE pass): {PROFILE_CMDS['dwrite']}",
+             f"summarised by: python3 bench.py --profile-summary gpurun_out",
+             f"calibration: FETCH_SIZE x {fs:.3f}, WRITE_SIZE x {ws:.3f} (the 1 GiB device copy of the same run)",
+             "units: B/cl = bytes per cell-level per launch", "",
+             f"{'kernel':20s} {'calls':>5s} {'rocprof_us':>10s} {'hip_event_us':>12s} {'hbm_B/cl':>9s} "
+             f"{'alg_B/cl':>9s} {'hbm/alg':>7s} {'alg_GB/s':>9s}"]
+    for k in DAMPED_KERNELS:
+        if k not in dur or k not in per:
+            continue
+        us, calls = dur[k]
+        fv, wv = per[k]
+        hbm = sum(fv) / len(fv) * 1024 * fs + sum(wv) / len(wv) * 1024 * ws
+        a = alg[k]
+        e = ev.get(evid[k], {}).get("avg_ms")
+        lines.append(f"{k:20s} {calls:5d} {us:10.2f} {('%.2f' % (e * 1e3)) if e else '-':>12s} "
+                     f"{hbm / (nc * N):9.1f} {a / (nc * N):9.1f} {hbm / a:7.2f} {a / (us * 1e3):9.1f}")
+    with open(os.path.join(dst, "dycore_damped_r2b6x90_kernels.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
 
 
 def main():
@@ -581,6 +668,8 @@ def main():
     ap.add_argument("--timing-steps", type=int, default=4)
     ap.add_argument("--error-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default="upwind,damped",
+                    help="options timed next to the FP64 and mixed forms: upwind, damped")
     ap.add_argument("--profile-summary", metavar="DIR",
                     help="reduce the rocprofv3 CSVs under DIR to the summaries in profiles/ and exit")
     ap.add_argument("--copy-calibration", action="store_true",

@@ -94,6 +94,11 @@ typedef struct nhdc_vertical {
     const double *zh;          /* [N+1][n_cells] half-level heights, strictly decreasing in i */
     const double *pi_ref;      /* [N][n_cells] reference Exner pressure at full levels */
     const double *theta_ref;   /* [N][n_cells] reference potential temperature at full levels */
+    const double *w_damp;      /* [N+1] Rayleigh damping rate of w per half level [1/s], >= 0,
+                                  or NULL for no sponge.  Each column solve (predictor and
+                                  corrector) multiplies its solved w at interior half level i by
+                                  1/(1 + dt_s w_damp[i]) before the mass, Exner and theta_v
+                                  updates use it, so the sponge keeps the flux form. */
 } nhdc_vertical;
 
 #define NHDC_MAX_LEV 256
@@ -111,6 +116,14 @@ typedef struct nhdc_params {
                          edge values interpolated along the dual arc to the edge midpoint)
                          dotted with the displacement to the midpoint of the edge
                          midpoint's back trajectory over the substep, dt/2 (vn n + vt t) */
+    double div_damp4; /* fourth-order divergence damping coefficient c4 >= 0 (0: off): the
+                         corrector adds -c4 Abar^2 G(D(G(D(vn*)))) to vn, Abar the mean cell
+                         area, G the normal gradient and D the divergence of the C-grid */
+    double smag;      /* Smagorinsky constant c_s >= 0 (0: off): after the substeps of each
+                         step, vn += dt K_e (G(D(vn)) - T(Z(vn))) with K_e the mean of its two
+                         cells' c_s^2 A_c |Def|, capped at Abar/(25 dt); |Def| is the
+                         tension-shear magnitude of the cell's Green-Gauss velocity-gradient
+                         tensor of vn n + vt t on the tangent plane.  Needs edge_normal. */
 } nhdc_params;
 
 /* Prognostic state; pointers are host or device memory per `on_device`.

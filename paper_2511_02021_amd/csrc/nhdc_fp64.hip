@@ -14,4 +14,8 @@ namespace nhdc {
 hipError_t launch_substep_fp64(const Launcher &L, const Sub &sub, Timing *tm, hipStream_t st) {
     return substep<double>(L, sub, tm, st);
 }
+
+hipError_t launch_diffusion_fp64(const Launcher &L, const Sub &sub, Timing *tm, hipStream_t st) {
+    return diffusion<double>(L, sub, tm, st);
+}
 }  // namespace nhdc

@@ -52,6 +52,8 @@ struct Grid {
     double *e_n = nullptr;        // [3][ne] edge normal
     double *e_d1 = nullptr;       // [3][ne] a (x_e - x_c1)
     double *e_d2 = nullptr;       // [3][ne] a (x_e - x_c2)
+    // sponge option: Rayleigh damping rate of w per half level [N+1] (or null)
+    double *w_damp = nullptr;
     double *zh = nullptr;         // [N+1][nc] half-level heights
     double *zhv = nullptr;        // [N+1][nv] vertex average of zh
     double *pi_ref = nullptr;     // [N][nc]
@@ -99,11 +101,15 @@ struct Work {
     double *cp = nullptr, *dp = nullptr;  // [N+1][nc] Thomas factors
     double *rh = nullptr, *ph = nullptr;  // [N][nc] explicit rho and Exner parts
     double *gq = nullptr;  // [N][nc][6] cell gradients of rho, then theta_v (upwind)
+    RT *dd4 = nullptr;     // [N][nc] D(G(D(vn*))) (fourth-order divergence damping)
+    RT *kh = nullptr;      // [N][nc] Smagorinsky coefficient of the cell (diffusion)
 };
 
 struct Params {
     double omega, grav, rd, cpd, p00, beta, wgt_corr, extrap, div_damp;
-    int32_t upwind;  // 1: second-order upwind edge values of rho and theta_v in the fluxes
+    int32_t upwind;    // 1: second-order upwind edge values of rho and theta_v in the fluxes
+    double div_damp4;  // fourth-order divergence damping coefficient (0: off)
+    double smag;       // Smagorinsky constant of the diffusion of vn (0: off)
 };
 
 // Everything one kernel needs about one instance (lives in device memory).
@@ -140,7 +146,7 @@ struct Tune {
 };
 
 enum KernelId { K_VT_EDGE = 0, K_VERTEX, K_CELL_VT, K_EDGE_PRED, K_COLUMN_PRED, K_EDGE_CORR,
-                K_COLUMN_CORR, K_CELL_GRAD, K_NUM };
+                K_COLUMN_CORR, K_CELL_GRAD, K_DIV4, K_SMAG_CELL, K_SMAG_EDGE, K_NUM };
 extern const char *const kKernelNames[K_NUM];
 
 // Event timing of kernel launches within one step call.
@@ -158,6 +164,9 @@ struct Launcher {
     int n = 0;
     void *d_insts = nullptr;       // Inst<double>[n] or Inst<float>[n] in device memory
     bool upwind = false;           // some instance uses the second-order upwind option
+    bool div4 = false;             // some instance uses fourth-order divergence damping
+    bool smag = false;             // some instance uses the Smagorinsky diffusion
+    bool sponge = false;           // some instance has a Rayleigh sponge on w
     Map maps[KIND_NUM];
     int64_t nblocks[KIND_NUM] = {0};
 };
@@ -165,6 +174,9 @@ struct Launcher {
 // kernels (nhdc_fp64.hip / nhdc_mixed.hip)
 hipError_t launch_substep_fp64(const Launcher &L, const Sub &sub, Timing *tm, hipStream_t st);
 hipError_t launch_substep_mixed(const Launcher &L, const Sub &sub, Timing *tm, hipStream_t st);
+// the diffusion after the substeps of a step (sub.dt: the step's dt per instance)
+hipError_t launch_diffusion_fp64(const Launcher &L, const Sub &sub, Timing *tm, hipStream_t st);
+hipError_t launch_diffusion_mixed(const Launcher &L, const Sub &sub, Timing *tm, hipStream_t st);
 // set-up and diagnostics (nhdc_util.hip)
 hipError_t launch_metrics(const Grid &g, hipStream_t st);
 hipError_t launch_to_float(const double *src, float *dst, int64_t n, hipStream_t st);

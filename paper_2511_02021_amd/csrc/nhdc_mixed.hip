@@ -15,4 +15,8 @@ namespace nhdc {
 hipError_t launch_substep_mixed(const Launcher &L, const Sub &sub, Timing *tm, hipStream_t st) {
     return substep<float>(L, sub, tm, st);
 }
+
+hipError_t launch_diffusion_mixed(const Launcher &L, const Sub &sub, Timing *tm, hipStream_t st) {
+    return diffusion<float>(L, sub, tm, st);
+}
 }  // namespace nhdc

@@ -61,6 +61,13 @@ hipError_t run_step(const Launcher &L, const double *dt, int nsub, Timing *tm, h
                                                  : launch_substep_fp64(L, sub, tm, st);
         if (e != hipSuccess) return e;
     }
+    if (L.smag) {  // the diffusion of vn over the whole step
+        Sub sd = sub;
+        for (int i = 0; i < L.n; ++i) sd.dt[i] = dt[i];
+        hipError_t e = L.precision == NHDC_MIXED ? launch_diffusion_mixed(L, sd, tm, st)
+                                                 : launch_diffusion_fp64(L, sd, tm, st);
+        if (e != hipSuccess) return e;
+    }
     return hipSuccess;
 }
 
@@ -107,8 +114,13 @@ int upload_insts(Launcher &L, const std::vector<nhdc_ctx *> &ctxs, std::string &
     if (e != hipSuccess) return hip_fail(err, e, "instance descriptors: hipMemcpy");
     L.precision = prec;
     L.n = n;
-    L.upwind = false;
-    for (auto *c : ctxs) L.upwind = L.upwind || c->p.upwind != 0;
+    L.upwind = L.div4 = L.smag = L.sponge = false;
+    for (auto *c : ctxs) {
+        L.sponge = L.sponge || c->g.w_damp != nullptr;
+        L.upwind = L.upwind || c->p.upwind != 0;
+        L.div4 = L.div4 || c->p.div_damp4 != 0.0;
+        L.smag = L.smag || c->p.smag > 0.0;
+    }
     return NHDC_OK;
 }
 
@@ -418,6 +430,8 @@ int alloc_work(nhdc_ctx *ctx, Work<RT> &W) {
     if (ctx->p.upwind) {
         if ((rc = dalloc(ctx, &W.gq, 6 * NC))) return rc;
     }
+    if (ctx->p.div_damp4 != 0.0 && (rc = dalloc(ctx, &W.dd4, NC))) return rc;
+    if (ctx->p.smag > 0.0 && (rc = dalloc(ctx, &W.kh, NC))) return rc;
     return NHDC_OK;
 }
 
@@ -470,8 +484,11 @@ int nhdc_upload_grid(nhdc_ctx *ctx, const nhdc_grid *g, const nhdc_vertical *v,
     if (!(prm->beta >= 0.5 && prm->beta <= 1.0) || !(prm->cpd > prm->rd && prm->rd > 0) ||
         !(prm->grav > 0) || !std::isfinite(prm->omega) || !std::isfinite(prm->extrap) ||
         !std::isfinite(prm->wgt_corr) || !std::isfinite(prm->div_damp) ||
-        (prm->upwind != 0 && prm->upwind != 1))
+        (prm->upwind != 0 && prm->upwind != 1) || !(prm->div_damp4 >= 0.0) ||
+        !std::isfinite(prm->div_damp4) || !(prm->smag >= 0.0) || !std::isfinite(prm->smag))
         return set_err(ctx, NHDC_EINVAL, "upload_grid: bad parameters");
+    if (prm->smag > 0.0 && !g->edge_normal)
+        return set_err(ctx, NHDC_EINVAL, "upload_grid: the diffusion option needs edge_normal");
     if (prm->upwind) {
         if (!g->edge_normal || !g->dual_frac)
             return set_err(ctx, NHDC_EINVAL, "upload_grid: the upwind option needs edge_normal and dual_frac");
@@ -481,6 +498,10 @@ int nhdc_upload_grid(nhdc_ctx *ctx, const nhdc_grid *g, const nhdc_vertical *v,
     }
     int rc = validate(ctx, g, v);
     if (rc) return rc;
+    if (v->w_damp)
+        for (int i = 0; i <= v->n_lev; ++i)
+            if (!(v->w_damp[i] >= 0.0) || !std::isfinite(v->w_damp[i]))
+                return set_err(ctx, NHDC_EINVAL, "upload_grid: w_damp must be finite and >= 0");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
 
     const int64_t nc = g->n_cells, ne = g->n_edges, nv = g->n_verts;
@@ -494,7 +515,8 @@ int nhdc_upload_grid(nhdc_ctx *ctx, const nhdc_grid *g, const nhdc_vertical *v,
     G.radius = a;
     G.abar = 4.0 * 3.14159265358979323846 * a * a / double(nc);
     ctx->p = Params{prm->omega, prm->grav, prm->rd, prm->cpd, prm->p00, prm->beta,
-                    prm->wgt_corr, prm->extrap, prm->div_damp, prm->upwind};
+                    prm->wgt_corr, prm->extrap, prm->div_damp, prm->upwind, prm->div_damp4,
+                    prm->smag};
 
     // ---- stencil coefficients on the host (each formed exactly as the
     // operators form it, so device sums see the same operands) ----
@@ -587,10 +609,13 @@ int nhdc_upload_grid(nhdc_ctx *ctx, const nhdc_grid *g, const nhdc_vertical *v,
             }
         }
         if ((rc = upload(ctx, &G.e_frac, g->dual_frac, ne))) return rc;
-        if ((rc = upload(ctx, &G.e_n, g->edge_normal, 3 * ne))) return rc;
         if ((rc = upload(ctx, &G.e_d1, d1.data(), 3 * ne))) return rc;
         if ((rc = upload(ctx, &G.e_d2, d2.data(), 3 * ne))) return rc;
     }
+    if (prm->upwind || prm->smag > 0.0)
+        if ((rc = upload(ctx, &G.e_n, g->edge_normal, 3 * ne))) return rc;
+    if (v->w_damp)
+        if ((rc = upload(ctx, &G.w_damp, v->w_damp, int64_t(N) + 1))) return rc;
     HIP_TRY(ctx, launch_metrics(G, nullptr));
     if (ctx->precision == NHDC_MIXED) {
         Geo<float> &F = G.gf;

@@ -42,12 +42,13 @@ class _Grid(C.Structure):
 
 class _Vertical(C.Structure):
     _fields_ = [("n_lev", C.c_int32), ("zh", C.c_void_p), ("pi_ref", C.c_void_p),
-                ("theta_ref", C.c_void_p)]
+                ("theta_ref", C.c_void_p), ("w_damp", C.c_void_p)]
 
 
 class _Params(C.Structure):
     _fields_ = [(n, C.c_double) for n in ("omega", "grav", "rd", "cpd", "p00", "beta", "wgt_corr",
-                                          "extrap", "div_damp")] + [("upwind", C.c_int32)]
+                                          "extrap", "div_damp")] + [("upwind", C.c_int32)] + [
+        ("div_damp4", C.c_double), ("smag", C.c_double)]
 
 
 class _State(C.Structure):
@@ -120,7 +121,7 @@ def _stream_ptr(stream):
 
 def params_struct(p):
     return _Params(p.omega, p.grav, p.rd, p.cpd, p.p00, p.beta, p.wgt_corr, p.extrap, p.div_damp,
-                   int(p.upwind))
+                   int(p.upwind), p.div_damp4, p.smag)
 
 
 class Dycore:
@@ -158,7 +159,9 @@ class Dycore:
         zh = np.ascontiguousarray(case.zh, dtype=np.float64)
         pr = np.ascontiguousarray(case.pi_ref, dtype=np.float64)
         tr = np.ascontiguousarray(case.theta_ref, dtype=np.float64)
-        vs = _Vertical(self.N, _np_ptr(zh), _np_ptr(pr), _np_ptr(tr))
+        wd = None if case.w_damp is None else np.ascontiguousarray(case.w_damp, dtype=np.float64)
+        vs = _Vertical(self.N, _np_ptr(zh), _np_ptr(pr), _np_ptr(tr),
+                       None if wd is None else _np_ptr(wd))
         ps = params_struct(case.params)
         self._check(self.L.nhdc_upload_grid(self.h, C.byref(gs), C.byref(vs), C.byref(ps)))
         if init:
