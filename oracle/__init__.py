@@ -57,6 +57,14 @@ def lib():
             getattr(L, f).restype = None
         L.or_op_deformation.argtypes = [vp] * 4
         L.or_op_deformation.restype = None
+        L.or_op_tracer_grad.argtypes = [vp] * 3
+        L.or_op_tracer_grad.restype = None
+        L.or_op_tracer_recon.argtypes = [vp] * 4
+        L.or_op_tracer_recon.restype = None
+        L.or_ppm_faces.argtypes = [i, vp, vp, vp]
+        L.or_ppm_column.argtypes = [i, d] + [vp] * 6
+        L.or_tracers_set.argtypes = [vp, i, vp]
+        L.or_tracers_get.argtypes = [vp, vp]
         L.or_op_perot.argtypes = [vp] * 7
         L.or_op_perot.restype = None
         L.or_thomas.argtypes = [i] + [vp] * 5
@@ -117,6 +125,20 @@ class Model:
         if not self.h:
             raise RuntimeError("or_create failed")
         self.set_state(case.vn, case.w, case.rho, case.pi, case.theta_v)
+        self.nt = 0
+        if getattr(case, "tracers", None) is not None:
+            self.set_tracers(case.tracers)
+
+    def set_tracers(self, q):
+        q = _f64(q)
+        self.nt = q.shape[0] if q.size else 0
+        if lib().or_tracers_set(self.h, self.nt, _p(q) if self.nt else None) != 0:
+            raise RuntimeError("or_tracers_set failed")
+
+    def tracers(self):
+        out = np.empty((self.nt, self.N, self.grid.n_cells))
+        lib().or_tracers_get(self.h, _p(out))
+        return out
 
     def __del__(self):
         if getattr(self, "h", None):
@@ -240,6 +262,41 @@ def deformation(grid, u, vt):
     out = np.empty(grid.n_cells)
     lib().or_op_deformation(h.ref, _p(u), _p(vt), _p(out))
     return out
+
+
+def tracer_grad(grid, q):
+    """Difference-form Green-Gauss gradient of a cell field, [3][n_cells]."""
+    h = _GridHandle(grid)
+    q = _f64(q)
+    out = np.empty((3, grid.n_cells))
+    lib().or_op_tracer_grad(h.ref, _p(q), _p(out))
+    return out
+
+
+def tracer_recon(grid, q, grad):
+    """Linear reconstruction toward each of a cell's edges, [3][n_cells]."""
+    h = _GridHandle(grid)
+    q, grad = _f64(q), _f64(grad)
+    out = np.empty((3, grid.n_cells))
+    lib().or_op_tracer_recon(h.ref, _p(q), _p(grad), _p(out))
+    return out
+
+
+def ppm_faces(dz, q):
+    dz, q = _f64(dz), _f64(q)
+    a = np.empty(len(q) + 1)
+    if lib().or_ppm_faces(len(q), _p(dz), _p(q), _p(a)) != 0:
+        raise RuntimeError("or_ppm_faces failed")
+    return a
+
+
+def ppm_column(dt, dz, rho, W, q):
+    """Vertical PPM transport of one column: returns (q_out, rho_out)."""
+    dz, rho, W, q = (_f64(a) for a in (dz, rho, W, q))
+    qo, ro = np.empty(len(q)), np.empty(len(q))
+    if lib().or_ppm_column(len(q), float(dt), _p(dz), _p(rho), _p(W), _p(q), _p(qo), _p(ro)) != 0:
+        raise RuntimeError("or_ppm_column failed")
+    return qo, ro
 
 
 def perot(grid, pos_c, pos_e, radial_c, u):

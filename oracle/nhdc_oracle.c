@@ -42,6 +42,9 @@ struct or_model {
     double *rhoe_u, *the_u;  /* [N][ne] upwind edge values (upwind option) */
     double *g4;              /* [N][ne] G(D(G(D(vn*)))) (fourth-order divergence damping) */
     double *kh, *lap;        /* [N][nc] Smagorinsky K_c, [N][ne] vector Laplacian of vn */
+    /* tracers: nt mixing ratios [nt][N][nc], carried by the step's averaged mass fluxes */
+    int nt;
+    double *q, *rho0;        /* tracers; density at the start of the step [N][nc] */
 };
 
 #define AT(a, k, n, i) ((a)[(int64_t)(k) * (n) + (i)])
@@ -240,6 +243,98 @@ void or_op_deformation(const or_grid *g, const double *u, const double *vt, doub
     }
 }
 
+void or_op_tracer_grad(const or_grid *g, const double *q, double *out) {
+    const int64_t nc = g->nc;
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < nc; ++c) {
+        double v[3] = {0.0, 0.0, 0.0};
+        for (int j = 0; j < 3; ++j) {
+            int64_t e = g->cell_edges[j * nc + c];
+            int64_t c1 = g->edge_cells[e], c2 = g->edge_cells[g->ne + e];
+            int64_t nb = c1 == c ? c2 : c1;
+            /* the edge value's offset from this cell's value along the dual arc */
+            double wgt = c1 == c ? g->dual_frac[e] : 1.0 - g->dual_frac[e];
+            double dq = wgt * (q[nb] - q[c]);
+            double sl = g->cell_sign[j * nc + c] * g->edge_length[e];
+            for (int d = 0; d < 3; ++d) v[d] += (sl * dq) * g->edge_normal[d * g->ne + e];
+        }
+        double ia = 1.0 / g->cell_area[c];
+        for (int d = 0; d < 3; ++d) v[d] = v[d] * ia;
+        const double x[3] = {g->cell_x[c], g->cell_x[nc + c], g->cell_x[2 * nc + c]};
+        double r = v[0] * x[0] + v[1] * x[1] + v[2] * x[2];
+        for (int d = 0; d < 3; ++d) out[d * nc + c] = v[d] - r * x[d];
+    }
+}
+
+void or_op_tracer_recon(const or_grid *g, const double *q, const double *grad, double *out) {
+    const int64_t nc = g->nc, ne = g->ne;
+    const double a = g->radius;
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < nc; ++c)
+        for (int j = 0; j < 3; ++j) {
+            int64_t e = g->cell_edges[j * nc + c];
+            double s = 0.0;
+            for (int d = 0; d < 3; ++d)
+                s += grad[d * nc + c] * (a * (g->edge_x[d * ne + e] - g->cell_x[d * nc + c]));
+            out[j * nc + c] = q[c] + s;
+        }
+}
+
+int or_ppm_faces(int N, const double *dz, const double *q, double *a) {
+    if (N < 2) return -1;
+    a[0] = q[0];
+    a[N] = q[N - 1];
+    /* the two interfaces next to the lid and the ground: linear between centres */
+    for (int i = 1; i < N; ++i)
+        if (i == 1 || i == N - 1 || N < 4)
+            a[i] = q[i - 1] + (dz[i - 1] / (dz[i - 1] + dz[i])) * (q[i] - q[i - 1]);
+    /* interior interfaces: the cubic through four cell means on a non-uniform
+       grid (Colella and Woodward 1984, their interface and mean-slope formulas) */
+    for (int i = 2; i <= N - 2 && N >= 4; ++i) {
+        const int j = i - 1; /* interface between cells j and j+1 */
+        const double d0 = dz[j - 1], d1 = dz[j], d2 = dz[j + 1], d3 = dz[j + 2];
+        const double q0 = q[j - 1], q1 = q[j], q2 = q[j + 1], q3 = q[j + 2];
+        /* mean slopes of cells j and j+1 */
+        double sj = d1 / (d0 + d1 + d2) *
+                    ((2.0 * d0 + d1) / (d2 + d1) * (q2 - q1) + (d1 + 2.0 * d2) / (d0 + d1) * (q1 - q0));
+        double sk = d2 / (d1 + d2 + d3) *
+                    ((2.0 * d1 + d2) / (d3 + d2) * (q3 - q2) + (d2 + 2.0 * d3) / (d1 + d2) * (q2 - q1));
+        double lin = q1 + d1 / (d1 + d2) * (q2 - q1);
+        double t1 = 2.0 * d2 * d1 / (d1 + d2) * ((d0 + d1) / (2.0 * d1 + d2) - (d3 + d2) / (2.0 * d2 + d1)) *
+                    (q2 - q1);
+        double t2 = d1 * (d0 + d1) / (2.0 * d1 + d2) * sk;
+        double t3 = d2 * (d2 + d3) / (d1 + 2.0 * d2) * sj;
+        a[i] = lin + (t1 - t2 + t3) / (d0 + d1 + d2 + d3);
+    }
+    return 0;
+}
+
+int or_ppm_column(int N, double dt, const double *dz, const double *rho, const double *W,
+                  const double *q, double *q_out, double *rho_out) {
+    if (N < 2 || N > OR_MAX_LEV) return -1;
+    double a[OR_MAX_LEV + 1], G[OR_MAX_LEV + 1];
+    or_ppm_faces(N, dz, q, a);
+    G[0] = G[N] = 0.0;
+    for (int i = 1; i < N; ++i) {
+        /* upward flux (W > 0) sweeps the top of cell i, downward the bottom of cell i-1 */
+        const int up = W[i] > 0.0 ? i : i - 1;
+        const double aT = a[up], aB = a[up + 1];
+        const double da = aB - aT, a6 = 6.0 * (q[up] - 0.5 * (aT + aB));
+        double c = fabs(W[i]) * dt / (rho[up] * dz[up]);
+        c = c < 1.0 ? c : 1.0;
+        const double mean = W[i] > 0.0 ? aT + 0.5 * c * (da + a6 * (1.0 - (2.0 / 3.0) * c))
+                                       : aB - 0.5 * c * (da - a6 * (1.0 - (2.0 / 3.0) * c));
+        G[i] = W[i] * mean;
+    }
+    for (int k = 0; k < N; ++k) {
+        double rq = rho[k] * q[k] - dt * (G[k] - G[k + 1]) / dz[k];
+        double rn = rho[k] - dt * (W[k] - W[k + 1]) / dz[k];
+        q_out[k] = rq / rn;
+        if (rho_out) rho_out[k] = rn;
+    }
+    return 0;
+}
+
 or_model *or_create(const or_grid *g, int N, const double *zh, const double *pi_ref,
                     const double *theta_ref, const or_params *p) {
     if (!g || !zh || !pi_ref || !theta_ref || !p || N < 2 || N > OR_MAX_LEV) return NULL;
@@ -336,7 +431,7 @@ void or_free(or_model *m) {
                      m->wcc0, m->tvn1, m->tw1, m->wcc1, m->gp, m->dpz, m->pix, m->the, m->rhoe,
                      m->flx, m->hfl, m->divr, m->divt, m->vns, m->dvs, m->ws, m->rhos, m->pis,
                      m->thvs, m->vnn, m->vflux, m->rho_i, m->thv_i, m->twm, m->grad_r,
-                     m->grad_t, m->rhoe_u, m->the_u, m->g4, m->kh, m->lap};
+                     m->grad_t, m->rhoe_u, m->the_u, m->g4, m->kh, m->lap, m->q, m->rho0};
     for (size_t i = 0; i < sizeof(all) / sizeof(*all); ++i) free(all[i]);
     free(m);
 }
@@ -824,6 +919,88 @@ static void substep(or_model *m, double dt, int nsub) {
     for (int64_t i = 0; i < NC1; ++i) m->wacc[i] += m->vflux[i] / nsub;
 }
 
+/* Tracer transport over the step dt with the step's averaged mass fluxes:
+ * horizontal (flux form, upwind cell's linear reconstruction at the edge
+ * midpoint), then vertical (piecewise parabolic, mass-based Courant number),
+ * each with the density change of the same fluxes, from the density at the
+ * start of the step. */
+static void transport_phase(or_model *m, double dt) {
+    const or_grid *g = &m->g;
+    const int64_t nc = g->nc, ne = g->ne;
+    const int N = m->N;
+    const int64_t NC = (int64_t)N * nc;
+    double *grad = alloc(3 * nc), *rec = alloc(3 * nc), *tf = alloc(ne), *dT = alloc(nc),
+           *dF = alloc(nc), *qs = alloc(NC), *rs = alloc(NC);
+    for (int t = 0; t < m->nt; ++t) {
+        double *q = m->q + (int64_t)t * NC;
+        for (int k = 0; k < N; ++k) {
+            const double *qk = q + (int64_t)k * nc, *F = m->facc + (int64_t)k * ne;
+            or_op_tracer_grad(g, qk, grad);
+            or_op_tracer_recon(g, qk, grad, rec);
+            for (int64_t e = 0; e < ne; ++e) {
+                const int64_t up = F[e] >= 0.0 ? g->edge_cells[e] : g->edge_cells[ne + e];
+                int slot = 0;
+                while (g->cell_edges[slot * nc + up] != e) ++slot;
+                tf[e] = F[e] * rec[slot * nc + up];
+            }
+            or_op_div(g, tf, dT);
+            or_op_div(g, F, dF);
+            for (int64_t c = 0; c < nc; ++c) {
+                const double dzc = AT(m->dz, k, nc, c), r0 = AT(m->rho0, k, nc, c);
+                double hT = dT[c] / dzc, hF = dF[c] / dzc;
+                double rsc = r0 - dt * hF;
+                AT(rs, k, nc, c) = rsc;
+                AT(qs, k, nc, c) = (r0 * qk[c] - dt * hT) / rsc;
+            }
+        }
+#pragma omp parallel
+        {
+            double c_dz[OR_MAX_LEV], c_r[OR_MAX_LEV], c_q[OR_MAX_LEV], c_W[OR_MAX_LEV + 1],
+                c_o[OR_MAX_LEV];
+#pragma omp for schedule(static)
+            for (int64_t c = 0; c < nc; ++c) {
+                for (int k = 0; k < N; ++k) {
+                    c_dz[k] = AT(m->dz, k, nc, c);
+                    c_r[k] = AT(rs, k, nc, c);
+                    c_q[k] = AT(qs, k, nc, c);
+                }
+                for (int i = 0; i <= N; ++i) c_W[i] = AT(m->wacc, i, nc, c);
+                or_ppm_column(N, dt, c_dz, c_r, c_W, c_q, c_o, NULL);
+                for (int k = 0; k < N; ++k) AT(q, k, nc, c) = c_o[k];
+            }
+        }
+    }
+    free(grad);
+    free(rec);
+    free(tf);
+    free(dT);
+    free(dF);
+    free(qs);
+    free(rs);
+}
+
+int or_tracers_set(or_model *m, int nt, const double *q) {
+    if (!m || nt < 0 || (nt > 0 && !q) || (nt > 0 && (!m->g.edge_normal || !m->g.dual_frac)))
+        return -1;
+    const int64_t NC = (int64_t)m->N * m->g.nc;
+    free(m->q);
+    free(m->rho0);
+    m->q = m->rho0 = NULL;
+    m->nt = nt;
+    if (nt == 0) return 0;
+    m->q = alloc(nt * NC);
+    m->rho0 = alloc(NC);
+    if (!m->q || !m->rho0) return -1;
+    memcpy(m->q, q, sizeof(double) * nt * NC);
+    return 0;
+}
+
+int or_tracers_get(const or_model *m, double *q) {
+    if (!m || !q) return -1;
+    if (m->nt) memcpy(q, m->q, sizeof(double) * m->nt * (int64_t)m->N * m->g.nc);
+    return 0;
+}
+
 /* Smagorinsky diffusion of vn over the step dt, level by level: the cell
  * coefficient from the deformation of (vn, vt), its edge mean capped for
  * stability, times the vector Laplacian of the same vn. */
@@ -855,8 +1032,10 @@ int or_step(or_model *m, double dt, int nsub) {
     memset(m->facc, 0, sizeof(double) * N * m->g.ne);
     memset(m->wacc, 0, sizeof(double) * (N + 1) * m->g.nc);
     const double dts = dt / nsub;
+    if (m->nt) memcpy(m->rho0, m->rho, sizeof(double) * N * m->g.nc);
     for (int s = 0; s < nsub; ++s) substep(m, dts, nsub);
     if (m->p.smag > 0.0) diffusion_phase(m, dt);
+    if (m->nt) transport_phase(m, dt);
     return 0;
 }
 

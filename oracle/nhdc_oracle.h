@@ -56,6 +56,20 @@
  *       capped at Abar/(25 dt); |Def|^2 = tension^2 + shear^2 of the cell's
  *       velocity-gradient tensor (Green-Gauss over its edges of vn n + vt t,
  *       projected on the cell's tangent plane).
+ *   tracer transport (when tracers are set), once per step after the substeps,
+ *     with the step's averaged mass fluxes Facc (edges) and Wacc (half levels)
+ *     and the density rho^n at the start of the step:
+ *     horizontal: T_e = Facc_e r_up, r_up = q_up + grad(q)_up . a (x_e - x_up),
+ *       up = c1 if Facc_e >= 0 else c2, grad the Green-Gauss gradient in
+ *       difference form (1/A) sum_j s l w_j (q_nb - q_c) n (w_j the arc
+ *       fraction from the cell to the edge midpoint), radial part removed;
+ *       rho* = rho^n - dt D(Facc)/dz, (rho q)* = rho^n q - dt D(T)/dz;
+ *     vertical: piecewise parabolic on q* = (rho q)* / rho*: interface values
+ *       by the non-uniform-grid cubic of Colella and Woodward (1984) at
+ *       interfaces 2..N-2, linear next to the lid and the ground; flux
+ *       Wacc times the parabola's mean over the swept fraction
+ *       c = |Wacc| dt/(rho* dz) of the upwind cell (c capped at 1);
+ *       q^{n+1} = ((rho q)* - dt dG/dz) / (rho* - dt dWacc/dz).
  *
  * Every array is FP64, level-major [k][entity]; connectivity slot-major.
  * Built with -O2 -ffp-contract=off (no fused multiply-add), OpenMP over
@@ -114,6 +128,10 @@ int or_set_state(or_model *m, const double *vn, const double *w, const double *r
 int or_get_state(const or_model *m, double *vn, double *w, double *rho, double *pi,
                  double *theta_v, double *pi_prev);
 int or_get_flux(const or_model *m, double *facc, double *wacc);
+/* tracers: nt mixing ratios [nt][N][nc] (copied; nt = 0 removes them); they
+ * are transported at the end of every step */
+int or_tracers_set(or_model *m, int nt, const double *q);
+int or_tracers_get(const or_model *m, double *q);
 /* step(dt, nsub): nsub substeps of dt/nsub; the flux accumulators are zeroed first. */
 int or_step(or_model *m, double dt, int nsub);
 /* velocity tendencies of (vn, w) with the model's metrics; outputs [N][ne], [N+1][nc] x2.
@@ -152,6 +170,19 @@ void or_op_graddiv2(const or_grid *g, const double *u, double *out_e);
  * projected on the cell's tangent plane by P = I - x x^T (x the unit cell
  * centre), |Def|^2 = 2 |sym(P G P)|^2 - tr(P G P)^2.  Needs edge_normal. */
 void or_op_deformation(const or_grid *g, const double *u, const double *vt, double *out_c);
+/* difference-form Green-Gauss gradient of a cell field (tracer transport),
+ * radial part removed: out [3][nc]; needs edge_normal and dual_frac */
+void or_op_tracer_grad(const or_grid *g, const double *q, double *out);
+/* linear reconstruction of a cell field toward each of the cell's edges:
+ * out[j][c] = q_c + grad_c . a (x_e(j) - x_c) */
+void or_op_tracer_recon(const or_grid *g, const double *q, const double *grad, double *out);
+/* PPM interface values a[N+1] of a column of cell means q[N] with thicknesses dz[N] */
+int or_ppm_faces(int nlev, const double *dz, const double *q, double *a);
+/* vertical PPM transport of one column over dt: density rho[N], mass flux
+ * W[N+1] (upward positive, 0 at lid and ground), mixing ratio q[N] ->
+ * q_out[N] and (optional) rho_out[N] */
+int or_ppm_column(int nlev, double dt, const double *dz, const double *rho, const double *W,
+                  const double *q, double *q_out, double *rho_out);
 /* Perot reconstruction with explicit positions [3][n] (metres) and cell radial
  * unit vectors: out_vc [3][nc] cell vectors, out_vt [ne] tangential velocity. */
 void or_op_perot(const or_grid *g, const double *pos_c, const double *pos_e,

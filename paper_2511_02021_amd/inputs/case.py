@@ -75,6 +75,7 @@ class Case:
     h: np.ndarray           # [nc] surface height
     zeta: np.ndarray = None  # [N+1] flat coordinate of the half levels
     w_damp: np.ndarray = None  # [N+1] Rayleigh damping rate of w per half level [1/s], or None
+    tracers: np.ndarray = None  # [nt, N, nc] tracer mixing ratios, or None
     meta: dict = field(default_factory=dict)
 
     @property
@@ -264,6 +265,30 @@ def batch_cases(n=16, order="sfc"):
 
 def with_params(case, **kw):
     return replace(case, params=replace(case.params, **kw))
+
+
+TRACER_NAMES = ("one", "h2o", "o3", "co2")
+
+
+def tracer_set(case, names=TRACER_NAMES):
+    """Synthetic tracer mixing ratios [nt, N, nc] with the vertical and
+    meridional shapes of the paper's tracers (H2O, O3, CO2), plus a constant
+    one: water vapour decaying with height (scale 2.5 km, moist tropics),
+    ozone peaked near 25 km, carbon dioxide nearly uniform (1 % in P_3 of
+    latitude); heights are the full-level heights of each column."""
+    z = 0.5 * (case.zh[:-1] + case.zh[1:])
+    s = np.sin(latitude(case.grid))[None, :]
+    shapes = {
+        "one": np.ones_like(z),
+        "h2o": 0.015 * np.exp(-z / 2500.0) * (0.3 + 0.7 * (1.0 - s ** 2)),
+        "o3": 8e-6 * np.exp(-((z - 25000.0) / 7000.0) ** 2) * (1.0 + 0.3 * s),
+        "co2": 4.2e-4 * (1.0 + 0.01 * legendre(3, s)) * np.ones_like(z),
+    }
+    return np.ascontiguousarray(np.stack([shapes[n] for n in names]))
+
+
+def with_tracers(case, names=TRACER_NAMES):
+    return replace(case, tracers=tracer_set(case, names))
 
 
 def sponge_profile(zeta, rate, z_base):

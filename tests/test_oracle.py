@@ -794,3 +794,128 @@ def test_each_damping_option_removes_energy_where_it_acts():
     top = cs.zeta > 50000.0
     ss = run(cs)
     assert np.sum(ss["w"][top] ** 2) < np.sum(s0["w"][top] ** 2)
+
+
+# ---------------------------------------------------------------------------
+# tracer transport with the step's averaged mass fluxes
+
+def test_tracer_gradient_exact_for_linear_and_zero_for_constant(g4):
+    gr, interior = _planar_patch(seed=9)
+    up = gr.cell_x.copy()
+    G2 = np.array([1.3, -0.6, 0.0])
+    psi = G2 @ gr.cell_x
+    gr.cell_x = np.tile(np.array([0.0, 0.0, 1.0])[:, None], (1, gr.n_cells))  # radial direction
+    g = oracle.tracer_grad(gr, psi)
+    inner = np.all(interior[gr.cell_edges], axis=0)
+    assert np.abs(g[:, inner] - G2[:, None]).max() <= 1e-12 * np.abs(G2).max()
+    # the reconstruction toward each edge is the field at the edge midpoint
+    gr.cell_x = up
+    gr.radius = 1.0
+    rec = oracle.tracer_recon(gr, psi, g)
+    exact = np.stack([G2 @ gr.edge_x[:, gr.cell_edges[j]] for j in range(3)])
+    assert np.abs(rec[:, inner] - exact[:, inner]).max() <= 1e-12
+    # a constant has no gradient at all on the sphere
+    assert np.all(oracle.tracer_grad(g4, np.full(g4.n_cells, 2.5)) == 0.0)
+
+
+def _cubic_means(zt, zb, coef):
+    """Cell means of sum coef[p] z^p over [zb, zt]."""
+    P = np.polynomial.polynomial.Polynomial(coef).integ()
+    return (P(zt) - P(zb)) / (zt - zb)
+
+
+def test_ppm_interfaces_exact_for_cubic_means_on_stretched_levels():
+    rng = np.random.default_rng(21)
+    N = 24
+    dz = rng.uniform(100.0, 900.0, N)
+    zh = np.concatenate([np.cumsum(dz[::-1])[::-1], [0.0]])     # top to bottom
+    coef = [0.3, 2e-4, -1e-7, 4e-12]
+    q = _cubic_means(zh[:-1], zh[1:], coef)
+    a = oracle.ppm_faces(dz, q)
+    exact = np.polynomial.polynomial.Polynomial(coef)(zh)
+    assert np.abs(a[2:N - 1] - exact[2:N - 1]).max() <= 1e-11 * np.abs(exact).max()
+    # next to the lid and the ground: linear between the two cell centres
+    zc = 0.5 * (zh[:-1] + zh[1:])
+    for i in (1, N - 1):
+        lin = q[i - 1] + (q[i] - q[i - 1]) * (zc[i - 1] - zh[i]) / (zc[i - 1] - zc[i])
+        assert a[i] == pytest.approx(lin, rel=1e-14)
+    assert a[0] == q[0] and a[N] == q[N - 1]
+
+
+@pytest.mark.parametrize("w", [0.37, -0.52])
+def test_ppm_column_exact_for_quadratic_under_uniform_advection(w):
+    """Uniform levels, density 1 and mass flux w (m/s) in the interior: cells
+    whose parabolas and upwind neighbours are all interior take the exact
+    means of the profile shifted by w dt."""
+    N, dzv, dt = 30, 200.0, 250.0
+    dz = np.full(N, dzv)
+    zh = dzv * np.arange(N, -1, -1, dtype=float)
+    coef = [1.0, 3e-4, -2e-8]
+    q = _cubic_means(zh[:-1], zh[1:], coef)
+    W = np.full(N + 1, w)
+    W[0] = W[N] = 0.0
+    qo, ro = oracle.ppm_column(dt, dz, np.ones(N), W, q)
+    shifted = _cubic_means(zh[:-1] - w * dt, zh[1:] - w * dt, coef)
+    ok = slice(4, N - 4)
+    assert np.abs(qo[ok] - shifted[ok]).max() <= 1e-12 * np.abs(q).max()
+    assert np.all(ro[ok] == 1.0)
+
+
+def test_ppm_column_conserves_and_keeps_constants():
+    rng = np.random.default_rng(5)
+    N = 40
+    dz = rng.uniform(50.0, 800.0, N)
+    rho = rng.uniform(0.1, 1.2, N)
+    W = 0.05 * rng.standard_normal(N + 1)
+    W[0] = W[N] = 0.0
+    q = rng.uniform(0.0, 1.0, N)
+    dt = 60.0
+    qo, ro = oracle.ppm_column(dt, dz, rho, W, q)
+    assert abs(np.sum(ro * qo * dz) / np.sum(rho * q * dz) - 1) <= 1e-14
+    one, _ = oracle.ppm_column(dt, dz, rho, W, np.ones(N))
+    assert np.all(one == 1.0)
+
+
+def _tracer_case(which):
+    if which == "terrain":
+        return CS.with_tracers(CS.config_case(2, k=3, n_lev=30))
+    if which == "upwind+damped":
+        c = CS.with_damping(CS.config_case(2, k=3, n_lev=30))
+        return CS.with_tracers(CS.with_params(c, upwind=1))
+    return CS.with_tracers(CS.config_case(1, k=3))
+
+
+@pytest.mark.parametrize("which", ["flat", "terrain", "upwind+damped"])
+def test_tracers_keep_a_constant_and_conserve_mass(which):
+    """A constant tracer stays exactly constant (the tracer fluxes of q = 1
+    are the mass fluxes, to the bit); every tracer's mass is conserved to
+    round-off against the dycore's density."""
+    c = _tracer_case(which)
+    m = oracle.Model(c)
+    g = c.grid
+    vol = g.cell_area[None, :] * (c.zh[:-1] - c.zh[1:])
+
+    def masses():
+        rho = m.state()["rho"]
+        return np.array([np.sum(vol * rho * q) for q in m.tracers()])
+
+    M0 = masses()
+    for _ in range(10):
+        m.step(c.dt, c.nsub)
+    q = m.tracers()
+    assert np.all(q[0] == 1.0)
+    assert np.abs(masses() / M0 - 1).max() <= 1e-12
+    assert np.all(np.isfinite(q))
+    # tracers with structure moved
+    assert not np.array_equal(q[1], c.tracers[1])
+
+
+def test_tracer_at_rest_stays_put():
+    c = CS.with_tracers(CS.make_case(3, 30, z_top=75000.0, stretch=1.6, sigma=0.0, dt=300.0,
+                                     params=CS.Params(div_damp=0.0)))
+    m = oracle.Model(c)
+    for _ in range(5):
+        m.step(c.dt, c.nsub)
+    q = m.tracers()
+    for t in range(q.shape[0]):
+        assert np.abs(q[t] - c.tracers[t]).max() <= 1e-12 * np.abs(c.tracers[t]).max(), t
