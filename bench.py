@@ -39,7 +39,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(nc, ne, nv, N, prec="fp64", nsub=5):
+def algorithmic_bytes(nc, ne, nv, N, prec="fp64", nsub=5, nt=4):
     """Bytes each kernel must read and write once per launch: every input and
     output array once at its size (cached re-reads of gathered neighbours,
     register-carried levels and column scratch round trips not counted).
@@ -93,6 +93,15 @@ def algorithmic_bytes(nc, ne, nv, N, prec="fp64", nsub=5):
     t["edge_corr_div4"] = [t["edge_corr"][0] + C * r]
     t["column_pred_sponge"] = list(t["column_pred"])
     t["column_corr_sponge"] = list(t["column_corr"])
+    # tracers (nt of them, FP64): density kept at the start of the step;
+    # reconstruction toward the three edges; horizontal update (mass fluxes,
+    # densities, reconstructions, q -> q*, rho*); vertical PPM (q*, rho*,
+    # heights, vertical mass flux -> q)
+    t["tr_save"] = [2 * C * 8]
+    t["tr_recon"] = [nt * (C * 8 + 3 * C * 8) + nc * (3 * 4 * 2 + 3 * 8 + 9 * 8 + 3 * 8 + 8)
+                     + ne * (8 + 3 * 8)]
+    t["tr_horiz"] = [E * 8 + 2 * C * 8 + C1 * 8 + nt * (5 * C * 8) + nc * (3 * 4 * 3 + 3 * 8 + 8)]
+    t["tr_vert"] = [2 * C1 * 8 + C * 8 + nt * 2 * C * 8]
     return {k: sum(v) / len(v) for k, v in t.items()}
 
 
@@ -203,7 +212,8 @@ def kernel_table(d, case, steps, stream, precision):
         d.step(case.dt, case.nsub, stream)
     stats = d.kernel_stats()
     d.set_timing(False)
-    alg = algorithmic_bytes(g.n_cells, g.n_edges, g.n_verts, case.n_lev, precision)
+    nt = 0 if case.tracers is None else case.tracers.shape[0]
+    alg = algorithmic_bytes(g.n_cells, g.n_edges, g.n_verts, case.n_lev, precision, nt=nt)
     if case.params.upwind:
         alg = {k: alg.get(k + "_upwind", v) for k, v in alg.items()}
     if case.params.div_damp4:
@@ -300,6 +310,10 @@ def bench_default(args, torch, nhdc, CS):
         forms["fp64_damped"]["options"] = {"div_damp4": dc.params.div_damp4, "smag": dc.params.smag,
                                            "sponge_rate_at_lid": float(dc.w_damp[0]),
                                            "sponge_base_m": CS.DAMPED["sponge_base"]}
+    if "tracers" in extra:  # four tracers carried by the step's averaged mass fluxes
+        tc = CS.with_tracers(case)
+        forms["fp64_tracers"] = option_form("tracers", tc)
+        forms["fp64_tracers"]["tracers"] = list(CS.TRACER_NAMES)
     if args.error_steps > 0:
         log(f"per-field error, {args.error_steps} steps ...")
         forms["mixed"]["per_field_error"] = error_table(nhdc, case, args.error_steps)
@@ -466,16 +480,19 @@ PROFILE_CMDS = {
 }
 for _k in list(PROFILE_CMDS):  # the damping options' kernels in runs of their own
     PROFILE_CMDS[_k] = PROFILE_CMDS[_k].replace("--no-cpu-baseline", "--no-cpu-baseline --forms upwind")
-    PROFILE_CMDS["d" + _k] = (PROFILE_CMDS[_k].replace("--forms upwind", "--forms damped")
+    PROFILE_CMDS["d" + _k] = (PROFILE_CMDS[_k].replace("--forms upwind", "--forms damped,tracers")
                               .replace(f"prof_{_k}", f"prof_d{_k}").replace(f"-o {_k}", f"-o d{_k}"))
-DAMPED_KERNELS = ("div4", "smag_cell", "smag_edge", "column_pred_sponge", "column_corr_sponge")
+CS_TRACERS = ("one", "h2o", "o3", "co2")  # the tracer set the tracer form carries
+OPTION_KERNELS = ("div4", "smag_cell", "smag_edge", "column_pred_sponge", "column_corr_sponge",
+                  "tr_save", "tr_recon", "tr_horiz", "tr_vert")
 
 
 def _kernel_id(name):
     """rocprofv3 kernel name -> (kernel id as in kernel_stats, precision); the
     builds of the upwind option get the suffix _upwind."""
     m = re.search(r"k_(vt_edge|vertex|cell_vt|edge_pred|edge_corr|column|cell_grad|div4|smag_cell|"
-                  r"smag_edge)<(double|float)((?:, (?:true|false))*)>", name)
+                  r"smag_edge|tr_save|tr_recon|tr_horiz|tr_vert)<(double|float)((?:, (?:true|false))*)>",
+                  name)
     if not m:
         return None, None
     k = m.group(1)
@@ -609,16 +626,17 @@ def profile_summary(src, dst):
 
 
 def damped_summary(src, dst, runs, src_hash, wl, nc, ne, nv, N, rows, counter):
-    """Durations and HBM bytes of the kernels only the damping options run
-    (fourth-order damping, the diffusion's two passes, the sponge's column
-    builds), from runs that time the damped form next to the plain ones."""
+    """Durations and HBM bytes of the kernels only the options run (fourth-
+    order damping, the diffusion's two passes, the sponge's column builds,
+    the four tracer kernels with four tracers), from runs that time the
+    damped and tracer forms next to the plain ones."""
     from collections import defaultdict
     alg = algorithmic_bytes(nc, ne, nv, N, "fp64")
     stats = rows(os.path.join(src, "prof_dtrace", "dtrace_kernel_stats.csv"))
     dur = {}
     for r in stats:
         k, prec = _kernel_id(r["Name"])
-        if prec == "fp64" and k in DAMPED_KERNELS:
+        if prec == "fp64" and k in OPTION_KERNELS:
             dur[k] = (float(r["AverageNs"]) / 1e3, int(r["Calls"]))
     fetch, write = counter("dfetch", "FETCH_SIZE"), counter("dwrite", "WRITE_SIZE")
     copy = [k for k in fetch if "copyBuffer" in k]
@@ -627,14 +645,15 @@ def damped_summary(src, dst, runs, src_hash, wl, nc, ne, nv, N, rows, counter):
     per = defaultdict(lambda: [[], []])
     for kname, vals in fetch.items():
         k, p = _kernel_id(kname)
-        if p == "fp64" and k in DAMPED_KERNELS:
+        if p == "fp64" and k in OPTION_KERNELS:
             per[k][0] += vals
             per[k][1] += write.get(kname, [])
     ev = runs["dtrace"]["forms"].get("fp64_damped", {}).get("kernels", {})
     evid = {"div4": "div4", "smag_cell": "smag_cell", "smag_edge": "smag_edge",
             "column_pred_sponge": "column_pred", "column_corr_sponge": "column_corr"}
+    evt = runs["dtrace"]["forms"].get("fp64_tracers", {}).get("kernels", {})
     opts = runs["dtrace"]["forms"].get("fp64_damped", {}).get("options", {})
-    lines = [f"# rocprofv3: kernels of the damping and diffusion options, fp64 form, {wl}",
+    lines = [f"# rocprofv3: kernels of the damping, diffusion and tracer options, fp64 form, {wl}",
              f"options: {json.dumps(opts, sort_keys=True)}",
              f"kernel_source_sha256_16: {src_hash}",
              f"command (trace): {PROFILE_CMDS['dtrace']}",
@@ -645,17 +664,18 @@ def damped_summary(src, dst, runs, src_hash, wl, nc, ne, nv, N, rows, counter):
              "units: B/cl = bytes per cell-level per launch", "",
              f"{'kernel':20s} {'calls':>5s} {'rocprof_us':>10s} {'hip_event_us':>12s} {'hbm_B/cl':>9s} "
              f"{'alg_B/cl':>9s} {'hbm/alg':>7s} {'alg_GB/s':>9s}"]
-    for k in DAMPED_KERNELS:
+    for k in OPTION_KERNELS:
         if k not in dur or k not in per:
             continue
         us, calls = dur[k]
         fv, wv = per[k]
         hbm = sum(fv) / len(fv) * 1024 * fs + sum(wv) / len(wv) * 1024 * ws
         a = alg[k]
-        e = ev.get(evid[k], {}).get("avg_ms")
+        e = (evt.get(k, {}) if k.startswith("tr_") else ev.get(evid[k], {})).get("avg_ms")
         lines.append(f"{k:20s} {calls:5d} {us:10.2f} {('%.2f' % (e * 1e3)) if e else '-':>12s} "
                      f"{hbm / (nc * N):9.1f} {a / (nc * N):9.1f} {hbm / a:7.2f} {a / (us * 1e3):9.1f}")
-    with open(os.path.join(dst, "dycore_damped_r2b6x90_kernels.txt"), "w") as f:
+    lines.append("tracers: " + ", ".join(CS_TRACERS) + " (four, FP64)")
+    with open(os.path.join(dst, "dycore_options_r2b6x90_kernels.txt"), "w") as f:
         f.write("\n".join(lines) + "\n")
 
 
@@ -668,8 +688,8 @@ def main():
     ap.add_argument("--timing-steps", type=int, default=4)
     ap.add_argument("--error-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="upwind,damped",
-                    help="options timed next to the FP64 and mixed forms: upwind, damped")
+    ap.add_argument("--forms", default="upwind,damped,tracers",
+                    help="options timed next to the FP64 and mixed forms: upwind, damped, tracers")
     ap.add_argument("--profile-summary", metavar="DIR",
                     help="reduce the rocprofv3 CSVs under DIR to the summaries in profiles/ and exit")
     ap.add_argument("--copy-calibration", action="store_true",

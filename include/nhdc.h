@@ -158,6 +158,33 @@ int nhdc_step(nhdc_ctx *ctx, double dt, int nsubsteps, void *stream);
  * NULL members are skipped).  Host copies are complete when this returns. */
 int nhdc_get_state(nhdc_ctx *ctx, const nhdc_state_view *dst, void *stream);
 
+/* Tracers (option), up to NHDC_MAX_TRACERS mixing ratios q [n][N][n_cells]
+ * (host or device memory per on_device), copied; n = 0 removes them.  Each
+ * step transports them after its substeps with the step's averaged FP64 mass
+ * fluxes (the paper carries water vapour, carbon dioxide and ozone this way),
+ * in FP64 in both precision forms:
+ *   horizontal, flux form: the edge flux is Facc times the upwind cell's
+ *     linear reconstruction q_c + grad(q)_c . a (x_e - x_c), upwind = c1 when
+ *     Facc >= 0, grad the Green-Gauss gradient in difference form
+ *     (1/A) sum_j s l w_j (q_nb - q_c) n_j (w_j the fraction of the dual arc
+ *     from the cell to the edge midpoint), radial part removed; the density
+ *     takes the divergence of the same fluxes from its value at the start of
+ *     the step;
+ *   vertical, piecewise parabolic: interface values from the cubic through
+ *     four cell means on the stretched levels (linear next to the lid and the
+ *     ground), the flux Wacc times the parabola's mean over the swept
+ *     fraction |Wacc| dt / (rho dz) of the upwind cell (capped at 1).
+ * A constant tracer stays exactly constant and tracer mass is conserved.
+ * Needs a grid uploaded with edge_normal and dual_frac.  Calls the stream's
+ * and the device's pending work to finish first.  Refused (ESTATE) while the
+ * context is part of a live batch: set tracers before making the batch. */
+#define NHDC_MAX_TRACERS 16
+int nhdc_set_tracers(nhdc_ctx *ctx, int n_tracers, const double *q, int on_device, void *stream);
+/* Copy the tracers out ([n][N][n_cells]); nothing when there are none. */
+int nhdc_get_tracers(nhdc_ctx *ctx, double *q, int on_device, void *stream);
+/* Number of tracers of the context. */
+int nhdc_n_tracers(const nhdc_ctx *ctx);
+
 /* Substep-averaged FP64 mass fluxes of the last step: edge fluxes
  * rho*vn*dz [N][n_edges] (kg/m/s per unit edge length and layer) and
  * vertical fluxes at half levels [N+1][n_cells] (kg/m^2/s). */

@@ -111,6 +111,7 @@ int nhdc_batch_create(nhdc_batch **out, nhdc_ctx *const *inst, int n) {
         return NHDC_ENOMEM;
     }
     rebuild_maps(b->L, b->ctxs, b->tune);
+    for (auto *c : b->ctxs) ++c->in_batches;
     *out = b;
     return NHDC_OK;
 }
@@ -161,6 +162,7 @@ void nhdc_batch_destroy(nhdc_batch *b) {
         if (b->L.d_insts) (void)hipFree(b->L.d_insts);
         if (b->cap) (void)hipStreamDestroy(b->cap);
     }
+    for (auto *c : b->ctxs) --c->in_batches;
     delete b;
 }
 

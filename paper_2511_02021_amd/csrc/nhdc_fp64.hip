@@ -18,4 +18,8 @@ hipError_t launch_substep_fp64(const Launcher &L, const Sub &sub, Timing *tm, hi
 hipError_t launch_diffusion_fp64(const Launcher &L, const Sub &sub, Timing *tm, hipStream_t st) {
     return diffusion<double>(L, sub, tm, st);
 }
+
+hipError_t launch_tracers_fp64(const Launcher &L, const Sub &sub, int phase, Timing *tm, hipStream_t st) {
+    return tracers<double>(L, sub, phase, tm, st);
+}
 }  // namespace nhdc

@@ -45,6 +45,7 @@ struct Grid {
     int32_t *e_v = nullptr;       // [2][ne] edge -> v1, v2
     int32_t *v_e = nullptr;       // [6][nv] vertex ring edges (pad -> slot 0)
     int32_t *v_c = nullptr;       // [6][nv] vertex ring cells (pad -> slot 0)
+    int32_t *c_ns = nullptr;      // [3][nc] slot of the shared edge in the neighbour across slot j
     Geo<double> gd;
     Geo<float> gf;
     // second-order upwind option (FP64; allocated only with the option)
@@ -105,6 +106,17 @@ struct Work {
     RT *kh = nullptr;      // [N][nc] Smagorinsky coefficient of the cell (diffusion)
 };
 
+// Tracers (option): mixing ratios carried by the step's averaged mass fluxes,
+// FP64 in every form, and their scratch.
+struct Tracers {
+    int32_t nt = 0;
+    double *q = nullptr;     // [nt][N][nc] mixing ratios
+    double *rec = nullptr;   // [nt][3][N][nc] linear reconstruction toward edge slot j
+    double *qs = nullptr;    // [nt][N][nc] after the horizontal update
+    double *rs = nullptr;    // [N][nc] density after the horizontal update
+    double *rho0 = nullptr;  // [N][nc] density at the start of the step
+};
+
 struct Params {
     double omega, grav, rd, cpd, p00, beta, wgt_corr, extrap, div_damp;
     int32_t upwind;    // 1: second-order upwind edge values of rho and theta_v in the fluxes
@@ -119,6 +131,7 @@ struct Inst {
     State s;
     Work<RT> w;
     Params p;
+    Tracers tr;
 };
 
 // Entity kinds of a launch, each with its own block map.
@@ -146,7 +159,8 @@ struct Tune {
 };
 
 enum KernelId { K_VT_EDGE = 0, K_VERTEX, K_CELL_VT, K_EDGE_PRED, K_COLUMN_PRED, K_EDGE_CORR,
-                K_COLUMN_CORR, K_CELL_GRAD, K_DIV4, K_SMAG_CELL, K_SMAG_EDGE, K_NUM };
+                K_COLUMN_CORR, K_CELL_GRAD, K_DIV4, K_SMAG_CELL, K_SMAG_EDGE, K_TR_SAVE,
+                K_TR_RECON, K_TR_HORIZ, K_TR_VERT, K_NUM };
 extern const char *const kKernelNames[K_NUM];
 
 // Event timing of kernel launches within one step call.
@@ -167,6 +181,7 @@ struct Launcher {
     bool div4 = false;             // some instance uses fourth-order divergence damping
     bool smag = false;             // some instance uses the Smagorinsky diffusion
     bool sponge = false;           // some instance has a Rayleigh sponge on w
+    bool tracers = false;          // some instance carries tracers
     Map maps[KIND_NUM];
     int64_t nblocks[KIND_NUM] = {0};
 };
@@ -177,6 +192,10 @@ hipError_t launch_substep_mixed(const Launcher &L, const Sub &sub, Timing *tm, h
 // the diffusion after the substeps of a step (sub.dt: the step's dt per instance)
 hipError_t launch_diffusion_fp64(const Launcher &L, const Sub &sub, Timing *tm, hipStream_t st);
 hipError_t launch_diffusion_mixed(const Launcher &L, const Sub &sub, Timing *tm, hipStream_t st);
+// tracers: phase 0 keeps the density at the start of a step, phase 1
+// transports over the step (sub.dt: the step's dt per instance)
+hipError_t launch_tracers_fp64(const Launcher &L, const Sub &sub, int phase, Timing *tm, hipStream_t st);
+hipError_t launch_tracers_mixed(const Launcher &L, const Sub &sub, int phase, Timing *tm, hipStream_t st);
 // set-up and diagnostics (nhdc_util.hip)
 hipError_t launch_metrics(const Grid &g, hipStream_t st);
 hipError_t launch_to_float(const double *src, float *dst, int64_t n, hipStream_t st);
@@ -202,6 +221,9 @@ struct nhdc_ctx {
     nhdc::Work<double> wd;
     nhdc::Work<float> wf;
     nhdc::Params p{};
+    nhdc::Tracers tr;
+    std::vector<void *> tr_allocs;  // tracer arrays (freed when the tracers are replaced)
+    int in_batches = 0;             // live batches holding this context's descriptor
     nhdc::Tune tune;
     nhdc::Launcher L;
     nhdc::Timing tm;

@@ -19,4 +19,8 @@ hipError_t launch_substep_mixed(const Launcher &L, const Sub &sub, Timing *tm, h
 hipError_t launch_diffusion_mixed(const Launcher &L, const Sub &sub, Timing *tm, hipStream_t st) {
     return diffusion<float>(L, sub, tm, st);
 }
+
+hipError_t launch_tracers_mixed(const Launcher &L, const Sub &sub, int phase, Timing *tm, hipStream_t st) {
+    return tracers<float>(L, sub, phase, tm, st);
+}
 }  // namespace nhdc

@@ -54,6 +54,13 @@ hipError_t run_step(const Launcher &L, const double *dt, int nsub, Timing *tm, h
     for (int i = 0; i < L.n; ++i) sub.dt[i] = dt[i] / nsub;
     for (int i = L.n; i < MAX_INST; ++i) sub.dt[i] = 0.0;
     sub.nsub = nsub;
+    Sub whole = sub;  // the step's dt per instance (diffusion, tracers)
+    for (int i = 0; i < L.n; ++i) whole.dt[i] = dt[i];
+    if (L.tracers) {
+        hipError_t e = L.precision == NHDC_MIXED ? launch_tracers_mixed(L, whole, 0, tm, st)
+                                                 : launch_tracers_fp64(L, whole, 0, tm, st);
+        if (e != hipSuccess) return e;
+    }
     for (int s = 0; s < nsub; ++s) {
         sub.first = s == 0;
         sub.last = s == nsub - 1;
@@ -62,10 +69,13 @@ hipError_t run_step(const Launcher &L, const double *dt, int nsub, Timing *tm, h
         if (e != hipSuccess) return e;
     }
     if (L.smag) {  // the diffusion of vn over the whole step
-        Sub sd = sub;
-        for (int i = 0; i < L.n; ++i) sd.dt[i] = dt[i];
-        hipError_t e = L.precision == NHDC_MIXED ? launch_diffusion_mixed(L, sd, tm, st)
-                                                 : launch_diffusion_fp64(L, sd, tm, st);
+        hipError_t e = L.precision == NHDC_MIXED ? launch_diffusion_mixed(L, whole, tm, st)
+                                                 : launch_diffusion_fp64(L, whole, tm, st);
+        if (e != hipSuccess) return e;
+    }
+    if (L.tracers) {  // tracer transport with the step's averaged mass fluxes
+        hipError_t e = L.precision == NHDC_MIXED ? launch_tracers_mixed(L, whole, 1, tm, st)
+                                                 : launch_tracers_fp64(L, whole, 1, tm, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -86,6 +96,7 @@ static Inst<RT> make_inst(const nhdc_ctx *c, const Work<RT> &w) {
     I.s = c->s;
     I.w = w;
     I.p = c->p;
+    I.tr = c->tr;
     return I;
 }
 
@@ -114,8 +125,9 @@ int upload_insts(Launcher &L, const std::vector<nhdc_ctx *> &ctxs, std::string &
     if (e != hipSuccess) return hip_fail(err, e, "instance descriptors: hipMemcpy");
     L.precision = prec;
     L.n = n;
-    L.upwind = L.div4 = L.smag = L.sponge = false;
+    L.upwind = L.div4 = L.smag = L.sponge = L.tracers = false;
     for (auto *c : ctxs) {
+        L.tracers = L.tracers || c->tr.nt > 0;
         L.sponge = L.sponge || c->g.w_damp != nullptr;
         L.upwind = L.upwind || c->p.upwind != 0;
         L.div4 = L.div4 || c->p.div_damp4 != 0.0;
@@ -130,6 +142,7 @@ static void state_arrays(nhdc_ctx *c, std::vector<std::pair<double *, size_t>> &
                  NE = size_t(c->g.N) * c->g.ne;
     out = {{c->s.vn, NE}, {c->s.w, NC1}, {c->s.rho, NC}, {c->s.pi, NC}, {c->s.thv, NC},
            {c->s.pi_prev, NC}, {c->s.facc, NE}, {c->s.wacc, NC1}, {c->s.px, NC}};
+    if (c->tr.nt) out.push_back({c->tr.q, size_t(c->tr.nt) * NC});
 }
 
 static int snapshot(const std::vector<nhdc_ctx *> &ctxs, std::vector<void *> &buf, bool restore,
@@ -489,13 +502,12 @@ int nhdc_upload_grid(nhdc_ctx *ctx, const nhdc_grid *g, const nhdc_vertical *v,
         return set_err(ctx, NHDC_EINVAL, "upload_grid: bad parameters");
     if (prm->smag > 0.0 && !g->edge_normal)
         return set_err(ctx, NHDC_EINVAL, "upload_grid: the diffusion option needs edge_normal");
-    if (prm->upwind) {
-        if (!g->edge_normal || !g->dual_frac)
-            return set_err(ctx, NHDC_EINVAL, "upload_grid: the upwind option needs edge_normal and dual_frac");
+    if (prm->upwind && (!g->edge_normal || !g->dual_frac))
+        return set_err(ctx, NHDC_EINVAL, "upload_grid: the upwind option needs edge_normal and dual_frac");
+    if (g->dual_frac)
         for (int64_t e = 0; e < g->n_edges; ++e)
             if (!(g->dual_frac[e] > 0.0 && g->dual_frac[e] < 1.0))
                 return set_err(ctx, NHDC_EGRID, "grid: dual_frac outside (0, 1)");
-    }
     int rc = validate(ctx, g, v);
     if (rc) return rc;
     if (v->w_damp)
@@ -573,6 +585,19 @@ int nhdc_upload_grid(nhdc_ctx *ctx, const nhdc_grid *g, const nhdc_vertical *v,
     if ((rc = upload(ctx, &G.c_e, g->cell_edges, 3 * nc))) return rc;
     if ((rc = upload(ctx, &G.c_n, c_n.data(), 3 * nc))) return rc;
     if ((rc = upload(ctx, &G.c_v, c_v.data(), 3 * nc))) return rc;
+    {
+        // the slot of each shared edge in the neighbour across it
+        std::vector<int32_t> c_ns(3 * nc);
+        for (int64_t c = 0; c < nc; ++c)
+            for (int j = 0; j < 3; ++j) {
+                const int64_t e = g->cell_edges[j * nc + c], nb = c_n[j * nc + c];
+                int s = 0;
+                while (s < 3 && g->cell_edges[s * nc + nb] != e) ++s;
+                if (s == 3) return set_err(ctx, NHDC_EGRID, "grid: a neighbour does not share the edge");
+                c_ns[j * nc + c] = s;
+            }
+        if ((rc = upload(ctx, &G.c_ns, c_ns.data(), 3 * nc))) return rc;
+    }
     if ((rc = upload(ctx, &G.e_c, g->edge_cells, 2 * ne))) return rc;
     if ((rc = upload(ctx, &G.e_v, g->edge_verts, 2 * ne))) return rc;
     if ((rc = upload(ctx, &G.v_e, v_e.data(), 6 * nv))) return rc;
@@ -608,12 +633,15 @@ int nhdc_upload_grid(nhdc_ctx *ctx, const nhdc_grid *g, const nhdc_vertical *v,
                 d2[x * ne + e] = a * (g->edge_x[x * ne + e] - g->cell_x[x * nc + c2]);
             }
         }
-        if ((rc = upload(ctx, &G.e_frac, g->dual_frac, ne))) return rc;
         if ((rc = upload(ctx, &G.e_d1, d1.data(), 3 * ne))) return rc;
         if ((rc = upload(ctx, &G.e_d2, d2.data(), 3 * ne))) return rc;
     }
-    if (prm->upwind || prm->smag > 0.0)
+    // normals and arc fractions whenever the grid has them (the upwind,
+    // diffusion and tracer options read them)
+    if (g->edge_normal)
         if ((rc = upload(ctx, &G.e_n, g->edge_normal, 3 * ne))) return rc;
+    if (g->dual_frac)
+        if ((rc = upload(ctx, &G.e_frac, g->dual_frac, ne))) return rc;
     if (v->w_damp)
         if ((rc = upload(ctx, &G.w_damp, v->w_damp, int64_t(N) + 1))) return rc;
     HIP_TRY(ctx, launch_metrics(G, nullptr));
@@ -815,12 +843,64 @@ int nhdc_kernel_stats(const nhdc_ctx *ctx, int index, const char **name, double 
 
 const char *nhdc_last_error(const nhdc_ctx *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
 
+int nhdc_set_tracers(nhdc_ctx *ctx, int n_tracers, const double *q, int on_device, void *stream) {
+    if (!ctx) return NHDC_EINVAL;
+    if (!ctx->grid_ready) return set_err(ctx, NHDC_ESTATE, "set_tracers: no grid uploaded");
+    if (n_tracers < 0 || n_tracers > NHDC_MAX_TRACERS)
+        return set_err(ctx, NHDC_EINVAL, "set_tracers: n_tracers out of range");
+    if (n_tracers > 0 && !q) return set_err(ctx, NHDC_EINVAL, "set_tracers: NULL tracers");
+    if (ctx->in_batches > 0)
+        return set_err(ctx, NHDC_ESTATE, "set_tracers: the context is part of a live batch");
+    if (n_tracers > 0 && (!ctx->g.e_n || !ctx->g.e_frac))
+        return set_err(ctx, NHDC_EINVAL, "set_tracers: the grid was uploaded without edge_normal and dual_frac");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    HIP_TRY(ctx, hipDeviceSynchronize());
+    for (void *p : ctx->tr_allocs) (void)hipFree(p);
+    ctx->tr_allocs.clear();
+    ctx->tr = Tracers{};
+    if (n_tracers > 0) {
+        const int64_t NC = int64_t(ctx->g.N) * ctx->g.nc;
+        double **arr[] = {&ctx->tr.q, &ctx->tr.rec, &ctx->tr.qs, &ctx->tr.rs, &ctx->tr.rho0};
+        const int64_t len[] = {n_tracers * NC, 3 * n_tracers * NC, n_tracers * NC, NC, NC};
+        for (int i = 0; i < 5; ++i) {
+            int rc = dalloc(ctx, arr[i], len[i]);
+            if (rc) return rc;
+            ctx->allocs.pop_back();  // owned by the tracer list, freed on replacement
+            ctx->tr_allocs.push_back(*arr[i]);
+        }
+        ctx->tr.nt = n_tracers;
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->tr.q, q, sizeof(double) * n_tracers * NC,
+                                    on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+        HIP_TRY(ctx, hipStreamSynchronize(s));
+    }
+    std::vector<nhdc_ctx *> one{ctx};
+    return upload_insts(ctx->L, one, ctx->err);
+}
+
+int nhdc_get_tracers(nhdc_ctx *ctx, double *q, int on_device, void *stream) {
+    if (!ctx) return NHDC_EINVAL;
+    if (!q) return set_err(ctx, NHDC_EINVAL, "get_tracers: NULL buffer");
+    if (ctx->tr.nt == 0) return NHDC_OK;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t bytes = sizeof(double) * ctx->tr.nt * size_t(ctx->g.N) * ctx->g.nc;
+    HIP_TRY(ctx, hipMemcpyAsync(q, ctx->tr.q, bytes,
+                                on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+    if (!on_device) HIP_TRY(ctx, hipStreamSynchronize(s));
+    return NHDC_OK;
+}
+
+int nhdc_n_tracers(const nhdc_ctx *ctx) { return ctx ? ctx->tr.nt : NHDC_EINVAL; }
+
 void nhdc_destroy(nhdc_ctx *ctx) {
     if (!ctx) return;
     if (hipSetDevice(ctx->device) == hipSuccess) {
         for (hipEvent_t e : ctx->tm.ev) (void)hipEventDestroy(e);
         if (ctx->L.d_insts) (void)hipFree(ctx->L.d_insts);
         for (void *q : ctx->allocs) (void)hipFree(q);
+        for (void *q : ctx->tr_allocs) (void)hipFree(q);
     }
     delete ctx;
 }

@@ -156,7 +156,8 @@ hipError_t launch_finite(const Grid &g, const State &s, int *flag, hipStream_t s
 const char *const kKernelNames[K_NUM] = {"vt_edge",   "vertex",      "cell_vt",
                                          "edge_pred", "column_pred", "edge_corr",
                                          "column_corr", "cell_grad", "div4",
-                                         "smag_cell",   "smag_edge"};
+                                         "smag_cell",   "smag_edge",   "tr_save",
+                                         "tr_recon",    "tr_horiz",    "tr_vert"};
 
 void build_map(Map &m, int64_t &nblocks, Kind kind, const Grid *const *grids, int n,
                const Tune &t) {

@@ -22,7 +22,8 @@ EXPORTS = ("nhdc_create", "nhdc_upload_grid", "nhdc_init_state", "nhdc_step", "n
            "nhdc_set_tiles", "nhdc_autotune", "nhdc_set_timing", "nhdc_kernel_count",
            "nhdc_kernel_stats", "nhdc_last_error", "nhdc_destroy", "nhdc_batch_create",
            "nhdc_batch_step", "nhdc_batch_set_tiles", "nhdc_batch_autotune",
-           "nhdc_batch_last_error", "nhdc_batch_destroy")
+           "nhdc_batch_last_error", "nhdc_batch_destroy", "nhdc_set_tracers", "nhdc_get_tracers",
+           "nhdc_n_tracers")
 
 
 class NhdcError(RuntimeError):
@@ -82,6 +83,9 @@ def lib():
         L.nhdc_step.argtypes = [vp, d, i, vp]
         L.nhdc_get_state.argtypes = [vp, vp, vp]
         L.nhdc_get_mass_flux.argtypes = [vp, vp, vp, i, vp]
+        L.nhdc_set_tracers.argtypes = [vp, i, vp, i, vp]
+        L.nhdc_get_tracers.argtypes = [vp, vp, i, vp]
+        L.nhdc_n_tracers.argtypes = [vp]
         L.nhdc_diag.argtypes = [vp, vp, vp, vp]
         L.nhdc_check_finite.argtypes = [vp, vp]
         L.nhdc_sizes.argtypes = [vp] + [vp] * 4
@@ -166,6 +170,8 @@ class Dycore:
         self._check(self.L.nhdc_upload_grid(self.h, C.byref(gs), C.byref(vs), C.byref(ps)))
         if init:
             self.init_state(case.vn, case.w, case.rho, case.pi, case.theta_v)
+        if getattr(case, "tracers", None) is not None:
+            self.set_tracers(case.tracers)
 
     # -- helpers ------------------------------------------------------------
     def _check(self, rc):
@@ -238,6 +244,22 @@ class Dycore:
         self._check(self.L.nhdc_get_mass_flux(self.h, _np_ptr(facc), _np_ptr(wacc), 0,
                                               _stream_ptr(None)))
         return facc, wacc
+
+    def set_tracers(self, q):
+        """Tracer mixing ratios [n, N, n_cells] (numpy, FP64); n = 0 removes them."""
+        q = np.ascontiguousarray(q, dtype=np.float64)
+        n = q.shape[0] if q.size else 0
+        if n:
+            assert q.shape[1:] == (self.N, self.grid.n_cells)
+        self._check(self.L.nhdc_set_tracers(self.h, int(n), _np_ptr(q) if n else None, 0,
+                                            _stream_ptr(None)))
+
+    def get_tracers(self):
+        n = self.L.nhdc_n_tracers(self.h)
+        out = np.empty((n, self.N, self.grid.n_cells))
+        if n:
+            self._check(self.L.nhdc_get_tracers(self.h, _np_ptr(out), 0, _stream_ptr(None)))
+        return out
 
     def diag(self):
         m, r = C.c_double(), C.c_double()
