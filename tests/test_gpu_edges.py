@@ -115,3 +115,24 @@ def test_full_size_r2b7_mixed_properties():
     d.close()
     print(f"R2B7x90 mixed: mass {m1 / m0 - 1:.2e}  rho*theta_v {r1 / r0 - 1:.2e}", flush=True)
     assert abs(m1 / m0 - 1) <= 1e-13 and abs(r1 / r0 - 1) <= 1e-13
+
+
+def test_full_size_r2b6_all_options_one_step_bitwise():
+    """The R2B6x90 benchmark workload with every option on (upwind edge
+    values, fourth-order divergence damping, the w sponge, the diffusion of
+    vn, four tracers), one step in the benchmark's launch configuration,
+    against the oracle entry by entry."""
+    c = CS.with_tracers(CS.with_params(CS.with_damping(CS.config_case(2)), upwind=1))
+    d = _nhdc().Dycore(c)
+    d.step(c.dt, c.nsub)
+    gs, gq, gf = d.get_state(), d.get_tracers(), d.mass_flux()
+    d.close()
+    m = oracle.Model(c)
+    m.step(c.dt, c.nsub)
+    _same(gs, m.state(), "R2B6x90 all options")
+    bad_q = int(np.count_nonzero(gq != m.tracers()))
+    print("tracers differing entries", bad_q, flush=True)
+    assert bad_q == 0
+    of = m.flux()
+    assert np.array_equal(gf[0], of[0]) and np.array_equal(gf[1], of[1])
+    assert np.all(gq[0] == 1.0)
