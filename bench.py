@@ -165,10 +165,45 @@ def cpu_baseline(case):
     m.step(case.dt, case.nsub)
     el = time.perf_counter() - t0
     units = case.grid.n_cells * case.n_lev * case.nsub
-    return {"value": units / el, "unit": "cell-level updates/s", "cores": threads,
-            "kind": "oracle", "seconds": round(el, 2),
-            "sample": f"1 step ({case.nsub} substeps) of the same R2B{case.grid.k}x{case.n_lev} "
-                      f"case from its initial state"}
+    out = {"value": units / el, "unit": "cell-level updates/s", "cores": threads,
+           "kind": "oracle", "seconds": round(el, 2),
+           "sample": f"1 step ({case.nsub} substeps) of the same R2B{case.grid.k}x{case.n_lev} "
+                     f"case from its initial state"}
+    out["host_cpu"] = host_cpu_model()
+    out["logical_cpus"] = os.cpu_count()
+    # thread scaling of the oracle on the small flat case (R2B4x20, one step),
+    # in child processes with their own OpenMP thread counts
+    out["small_case"] = {n: oracle_small_case_rate(n) for n in (1, threads)}
+    return out
+
+
+def host_cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_small_case_rate(threads):
+    """Cell-level updates/s of the oracle on one step of R2B4x20 (flat, dt
+    300 s) with `threads` OpenMP threads, timed in a child process."""
+    import subprocess
+    code = ("import time, oracle\n"
+            "from paper_2511_02021_amd.inputs import case as CS\n"
+            "c = CS.config_case(1)\n"
+            "m = oracle.Model(c)\n"
+            "t = time.perf_counter(); m.step(c.dt, c.nsub); el = time.perf_counter() - t\n"
+            "print(c.grid.n_cells * c.n_lev * c.nsub / el, el)\n")
+    env = dict(os.environ, OMP_NUM_THREADS=str(threads))
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True,
+                       text=True, timeout=300)
+    if r.returncode != 0:
+        return {"error": r.stderr.strip()[-200:]}
+    v, el = (float(x) for x in r.stdout.split())
+    return {"threads": threads, "value": v, "seconds": round(el, 3)}
 
 
 def timed_steps(torch, stepper, steps, warmup, stream):

@@ -207,3 +207,18 @@ def test_mixed_batch_equals_mixed_alone():
     b.close()
     for d in ds:
         d.close()
+
+
+@pytest.mark.parametrize("option", ["upwind", "damped"])
+def test_mixed_form_error_with_options(option):
+    """The mixed form's per-field deviation from FP64 stays below the
+    FP32-rounding floor with the upwind edge values and with the damping and
+    diffusion options on."""
+    c = CS.config_case(3, k=4, n_lev=30)
+    c = CS.with_params(c, upwind=1) if option == "upwind" else CS.with_damping(c)
+    table, _ = mixed_error_table(c, 10)
+    for f, r in table.items():
+        print(f"mixed {option} {f}: E={r['E']:.2e} S={r['S']:.2e} E/signal={r['E_signal']:.2e}",
+              flush=True)
+        assert r["E"] <= r["S"], (f, r)
+        assert r["E_signal"] < 1e-5, (f, r)
