@@ -392,14 +392,7 @@ def bench_default(args, torch, nhdc, CS):
         forms["mixed"]["roofline"]["step_hbm_GBs"] = round(gbs, 1)
         forms["mixed"]["roofline"]["step_hbm_frac"] = round(gbs / HBM_PEAK_GBS, 4)
     if args.copy_calibration:
-        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
-        b = torch.empty_like(a)
-        a.fill_(1.0)
-        torch.cuda.synchronize()
-        b.copy_(a)
-        torch.cuda.synchronize()
-        log("copy calibration: 1 GiB read + 1 GiB written")
-        del a, b
+        calibration_copy(torch)
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -432,6 +425,29 @@ def bench_default(args, torch, nhdc, CS):
     }
 
 
+def calibration_copy(torch):
+    """One 1 GiB device-to-device copy: a plain copy kernel of known size whose
+    counter readings scale the hardware byte counters."""
+    a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    log("copy calibration: 1 GiB read + 1 GiB written")
+    del a, b
+
+
+def counters_line(args, ms, steps, units, workload):
+    """The JSON line of a counter run: how many steps ran in all (warm-up and
+    timed), for the per-step byte count."""
+    return {"metric": METRIC, "value": units / (ms / 1e3), "unit": "cell-level updates/s",
+            "n_gpus": 1, "steps": steps, "warmup": args.warmup, "ms_per_step": ms / steps,
+            "steps_run": steps + args.warmup, "counters_run": True, "config": {"workload": workload},
+            "tiles_arg": "" if args.tiles == [0, 0, 0] else " --tiles " + ",".join(map(str, args.tiles)),
+            "kernel_source_sha256_16": kernel_source_hash()}
+
+
 def bench_single(args, torch, nhdc, CS, cfg):
     """R2B7x90 (config 3) or R2B8x90 (config 5), FP32-mixed."""
     stream = torch.cuda.current_stream()
@@ -444,6 +460,10 @@ def bench_single(args, torch, nhdc, CS, cfg):
     ms = timed_steps(torch, lambda: d.step(case.dt, case.nsub, stream), steps, args.warmup, stream)
     d.check_finite()
     units = g.n_cells * case.n_lev * case.nsub * steps
+    if args.counters:  # only the warm-up and timed steps ran: counted bytes / steps_run
+        d.close()
+        calibration_copy(torch)
+        return counters_line(args, ms, steps, units, f"R2B{g.k}x{case.n_lev} FP32-mixed")
     kern = kernel_table(d, case, args.timing_steps, stream, "mixed")
     d.close()
     dom = max(kern, key=lambda k: kern[k]["share"])
@@ -477,6 +497,18 @@ def bench_batch(args, torch, nhdc, CS):
     steps = args.steps if args.steps != 98 else 10
     units = sum(c.grid.n_cells * c.n_lev * c.nsub for c in cases) * steps
     res = {}
+    if args.counters:  # the batch alone at given tiles: counted bytes / steps_run
+        ds = [nhdc.Dycore(c, precision="mixed") for c in cases]
+        b = nhdc.Batch(ds)
+        b.set_tiles(*args.tiles)
+        dts = [c.dt for c in cases]
+        ms = timed_steps(torch, lambda: b.step(dts, 5, 1, stream), steps, args.warmup, stream)
+        b.close()
+        for d in ds:
+            d.close()
+        calibration_copy(torch)
+        return counters_line(args, ms, steps, units, "batch of 16, FP32-mixed, tiles "
+                             + ",".join(map(str, args.tiles)))
     for prec in ("fp64", "mixed"):
         total = 0.0
         for c in cases:  # sequential, one instance at a time
@@ -529,6 +561,16 @@ for _k in list(PROFILE_CMDS):  # the damping options' kernels in runs of their o
     PROFILE_CMDS[_k] = PROFILE_CMDS[_k].replace("--no-cpu-baseline", "--no-cpu-baseline --forms upwind")
     PROFILE_CMDS["d" + _k] = (PROFILE_CMDS[_k].replace("--forms upwind", "--forms damped,tracers")
                               .replace(f"prof_{_k}", f"prof_d{_k}").replace(f"-o {_k}", f"-o d{_k}"))
+# whole-step HBM bytes of the other workloads: unprofiled runs give the time
+# per step, FETCH_SIZE / WRITE_SIZE passes over only the warm-up and timed
+# steps give the bytes (config 4 at the tiles its unprofiled run chose)
+CONFIG_CMDS = {
+    cfg: {"run": f"python3 -u bench.py --config {cfg} --no-cpu-baseline > gpurun_out/bench_c{cfg}.json",
+          **{kind: f"rocprofv3 --pmc {ctr} --output-format csv -d gpurun_out/prof_c{cfg}{kind} "
+                   f"-o c{cfg}{kind} -- python3 -u bench.py --config {cfg} --steps 3 --warmup 1 "
+                   f"--counters --no-cpu-baseline{{tiles}} > gpurun_out/prof_c{cfg}{kind}.json"
+             for kind, ctr in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE"))}}
+    for cfg in (3, 4, 5)}
 CS_TRACERS = ("one", "h2o", "o3", "co2")  # the tracer set the tracer form carries
 OPTION_KERNELS = ("div4", "smag_cell", "smag_edge", "column_pred_sponge", "column_corr_sponge",
                   "tr_save", "tr_recon", "tr_horiz", "tr_vert")
@@ -669,7 +711,64 @@ def profile_summary(src, dst):
             f.write("\n".join(lines) + "\n")
     if all(k in runs for k in ("dtrace", "dfetch", "dwrite")):
         damped_summary(src, dst, runs, src_hash, wl, nc, ne, nv, N, rows, counter)
+    config_summary(src, dst)
     print(f"wrote summaries for kernel sources {src_hash} to {dst}")
+
+
+def config_summary(src, dst):
+    """profiles/dycore_config{3,4,5}_hbm.txt: whole-step HBM bytes of each
+    workload from its counter passes (every dispatch of a step kernel, summed,
+    over the steps that ran), against its unprofiled time per step."""
+    import csv
+    from collections import defaultdict
+    for cfg, cmds in CONFIG_CMDS.items():
+        paths = {k: os.path.join(src, f"prof_c{cfg}{k}.json") for k in ("fetch", "write")}
+        run = os.path.join(src, f"bench_c{cfg}.json")
+        if not all(os.path.exists(p) for p in list(paths.values()) + [run]):
+            continue
+        meta = {k: json.loads(open(p).read().strip().splitlines()[-1]) for k, p in paths.items()}
+        timed = json.loads(open(run).read().strip().splitlines()[-1])
+        tot, per, cal = {}, {}, {}
+        for kind, ctr in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE")):
+            f = os.path.join(src, f"prof_c{cfg}{kind}", f"c{cfg}{kind}_counter_collection.csv")
+            rows_ = sorted(csv.DictReader(open(f)), key=lambda r: int(r["Dispatch_Id"]))
+            acc = defaultdict(float)
+            copies = []
+            for r in rows_:
+                if r["Counter_Name"] != ctr:
+                    continue
+                if "copyBuffer" in r["Kernel_Name"]:
+                    copies.append(float(r["Counter_Value"]))
+                    continue
+                k, _ = _kernel_id(r["Kernel_Name"])
+                if k:
+                    acc[k] += float(r["Counter_Value"])
+            cal[kind] = (1 << 30) / (copies[-1] * 1024)
+            per[kind] = {k: v * 1024 * cal[kind] / meta[kind]["steps_run"] for k, v in acc.items()}
+            tot[kind] = sum(per[kind].values())
+        step_bytes = tot["fetch"] + tot["write"]
+        ms = timed["ms_per_step"]
+        gbs = step_bytes / (ms / 1e3) / 1e9
+        lines = [f"# rocprofv3 HBM counters, whole step: {timed['config']['workload']}",
+                 f"kernel_source_sha256_16: {meta['fetch']['kernel_source_sha256_16']}",
+                 f"command (time per step, unprofiled): {cmds['run']}",
+                 f"command (FETCH_SIZE pass): {cmds['fetch'].format(tiles=meta['fetch']['tiles_arg'])}",
+                 f"command (WRITE_SIZE pass): {cmds['write'].format(tiles=meta['write']['tiles_arg'])}",
+                 f"summarised by: python3 bench.py --profile-summary gpurun_out",
+                 f"calibration: FETCH_SIZE x {cal['fetch']:.3f}, WRITE_SIZE x {cal['write']:.3f} "
+                 "(the 1 GiB device copy at the end of each pass)",
+                 f"counter passes: {meta['fetch']['steps_run']} steps each (warm-up + timed)", "",
+                 f"HBM bytes per step: {step_bytes:.4e}",
+                 f"time per step (unprofiled): {ms:.3f} ms",
+                 f"HBM rate: {gbs:.1f} GB/s = {100 * gbs / HBM_PEAK_GBS:.1f} % of {HBM_PEAK_GBS:.0f} GB/s",
+                 "", f"{'kernel':20s} {'bytes_per_step':>15s} {'share':>7s}"]
+        allk = set(per["fetch"]) | set(per["write"])
+        for k in sorted(allk, key=lambda x: -(per["fetch"].get(x, 0) + per["write"].get(x, 0))):
+            b = per["fetch"].get(k, 0) + per["write"].get(k, 0)
+            lines.append(f"{k:20s} {b:15.4e} {b / step_bytes:7.3f}")
+        with open(os.path.join(dst, f"dycore_config{cfg}_hbm.txt"), "w") as fo:
+            fo.write("\n".join(lines) + "\n")
+        print(f"config {cfg}: {gbs:.1f} GB/s ({100 * gbs / HBM_PEAK_GBS:.1f} % of peak)")
 
 
 def damped_summary(src, dst, runs, src_hash, wl, nc, ne, nv, N, rows, counter):
@@ -735,6 +834,11 @@ def main():
     ap.add_argument("--timing-steps", type=int, default=4)
     ap.add_argument("--error-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--counters", action="store_true",
+                    help="configs 3-5: run only the warm-up and timed steps (no kernel table, "
+                         "error table, sequential runs or autotuning), for a hardware-counter pass")
+    ap.add_argument("--tiles", type=lambda x: [int(v) for v in x.split(",")], default=[0, 0, 0],
+                    help="config 4 with --counters: level tiles lt_edge,lt_cell,lt_vert")
     ap.add_argument("--forms", default="upwind,damped,tracers",
                     help="options timed next to the FP64 and mixed forms: upwind, damped, tracers")
     ap.add_argument("--profile-summary", metavar="DIR",
