@@ -136,3 +136,29 @@ def test_full_size_r2b6_all_options_one_step_bitwise():
     of = m.flux()
     assert np.array_equal(gf[0], of[0]) and np.array_equal(gf[1], of[1])
     assert np.all(gq[0] == 1.0)
+
+
+def test_config2_recipe_ninety_levels_ten_steps_bitwise():
+    """The benchmark's vertical grid (90 levels stretched to 75 km, terrain)
+    on R2B4, ten steps against the oracle entry by entry."""
+    c = CS.config_case(2, k=4)
+    gs, gf = _gpu(c, 10)
+    os_, of = _oracle(c, 10)
+    _same(gs, os_, "R2B4x90 10 steps")
+    assert np.array_equal(gf[0], of[0]) and np.array_equal(gf[1], of[1])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_full_size_hundred_steps_conserve(precision):
+    """R2B6x90, the benchmark's 100 steps: dry mass and sum rho theta_v
+    conserved to 1e-13 relative (fixed-order device sums), state finite."""
+    c = CS.config_case(2)
+    d = _nhdc().Dycore(c, precision=precision)
+    m0, r0 = d.diag()
+    for _ in range(100):
+        d.step(c.dt, c.nsub)
+    d.check_finite()
+    m1, r1 = d.diag()
+    d.close()
+    print(f"{precision} 100 steps: mass {m1 / m0 - 1:.2e}  rho*theta_v {r1 / r0 - 1:.2e}", flush=True)
+    assert abs(m1 / m0 - 1) <= 1e-13 and abs(r1 / r0 - 1) <= 1e-13
