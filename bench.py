@@ -124,16 +124,24 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, src_hash, precision):
+def _summary_matches(txt, src_hash, numbering):
+    """A counter summary describes this run if it was taken on the current
+    kernel sources and the same numbering of the grid."""
+    m = re.search(r"kernel_source_sha256_16:\s*(\w+)", txt)
+    n = re.search(r"^numbering:\s*(\w+)", txt, re.M)
+    return bool(m and n and m.group(1) == src_hash and n.group(1) == numbering)
+
+
+def measured_traffic(kernel, src_hash, precision, numbering="curve"):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel sources; else None."""
+    summary, if it was taken on the current kernel sources and numbering;
+    else None."""
     path = os.path.join(ROOT, "profiles", f"dycore_{precision}_r2b6x90_hbm_counters.txt")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
-    m = re.search(r"kernel_source_sha256_16:\s*(\w+)", txt)
     b = re.search(rf"^{kernel}\s+.*?hbm_bytes_per_launch=([0-9.eE+]+)", txt, re.M)
-    if not m or not b or m.group(1) != src_hash:
+    if not b or not _summary_matches(txt, src_hash, numbering):
         return None
     return float(b.group(1))
 
@@ -142,7 +150,7 @@ LAUNCHES_PER_STEP = {"vt_edge": 2, "vertex": 2, "cell_vt": 2, "edge_pred": 1, "c
                      "edge_corr": 1, "column_corr": 1}  # per substep
 
 
-def step_traffic(src_hash, precision, nsub):
+def step_traffic(src_hash, precision, nsub, numbering="curve"):
     """HBM bytes of one whole step from the committed counter summary (every
     kernel's counted bytes per launch x its launches), if it was taken on the
     current kernel sources; else None."""
@@ -150,8 +158,7 @@ def step_traffic(src_hash, precision, nsub):
     if not os.path.exists(path):
         return None
     txt = open(path).read()
-    m = re.search(r"kernel_source_sha256_16:\s*(\w+)", txt)
-    if not m or m.group(1) != src_hash:
+    if not _summary_matches(txt, src_hash, numbering):
         return None
     total = 0.0
     for k, n in LAUNCHES_PER_STEP.items():
@@ -307,7 +314,7 @@ def error_table(nhdc, case, steps):
 def bench_default(args, torch, nhdc, CS):
     stream = torch.cuda.current_stream()
     t0 = time.time()
-    case = CS.config_case(2)
+    case = CS.config_case(2, order=args.order)
     g = case.grid
     units_per_step = g.n_cells * case.n_lev * case.nsub
     log(f"case R2B{g.k}x{case.n_lev}: {g.n_cells} cells, {g.n_edges} edges ({time.time() - t0:.1f}s)")
@@ -367,10 +374,10 @@ def bench_default(args, torch, nhdc, CS):
     achieved = kern[dom]["alg_GBs"]
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(dom, src_hash, "fp64"),
+                "traffic": measured_traffic(dom, src_hash, "fp64", args.order),
                 "alg_bytes_per_launch": int(kern[dom]["alg_bytes"]),
                 "avg_launch_ms": round(kern[dom]["avg_ms"], 5)}
-    step_bytes = step_traffic(src_hash, "fp64", case.nsub)
+    step_bytes = step_traffic(src_hash, "fp64", case.nsub, args.order)
     if step_bytes is not None:
         roofline["step_hbm_GBs"] = round(step_bytes / (forms["fp64"]["ms_per_step"] / 1e3) / 1e9, 1)
         roofline["step_hbm_frac"] = round(roofline["step_hbm_GBs"] / HBM_PEAK_GBS, 4)
@@ -385,8 +392,8 @@ def bench_default(args, torch, nhdc, CS):
                                      "alg_GBs": round(v["alg_GBs"], 1)} for k, v in mk.items()}
     forms["mixed"]["roofline"] = {"kernel": mdom, "achieved": round(mk[mdom]["alg_GBs"], 1),
                                   "frac": round(mk[mdom]["alg_GBs"] / HBM_PEAK_GBS, 4),
-                                  "traffic": measured_traffic(mdom, src_hash, "mixed")}
-    mstep = step_traffic(src_hash, "mixed", case.nsub)
+                                  "traffic": measured_traffic(mdom, src_hash, "mixed", args.order)}
+    mstep = step_traffic(src_hash, "mixed", case.nsub, args.order)
     if mstep is not None:
         gbs = mstep / (forms["mixed"]["ms_per_step"] / 1e3) / 1e9
         forms["mixed"]["roofline"]["step_hbm_GBs"] = round(gbs, 1)
@@ -415,7 +422,7 @@ def bench_default(args, torch, nhdc, CS):
         "config": {"workload": f"R2B{g.k} ({g.n_cells} cells) x {case.n_lev} levels to 75 km, "
                                f"terrain, dt={case.dt:g}s, {case.nsub} substeps, FP64 plain",
                    "cells": g.n_cells, "levels": case.n_lev, "substeps": case.nsub,
-                   "parallelism": "single GPU"},
+                   "numbering": args.order, "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "forms": forms,
@@ -571,6 +578,17 @@ CONFIG_CMDS = {
                    f"--counters --no-cpu-baseline{{tiles}} > gpurun_out/prof_c{cfg}{kind}.json"
              for kind, ctr in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE"))}}
     for cfg in (3, 4, 5)}
+# the same workload in a 3-D Hilbert numbering, the bisection's own and a
+# random one, against the bisection-curve numbering of the main runs
+ORDER_CMDS = {
+    o: {"run": f"python3 -u bench.py --order {o} --forms none --error-steps 0 --no-cpu-baseline "
+               f"--steps 20 > gpurun_out/bench_o{o}.json",
+        **{kind: f"rocprofv3 --pmc {ctr} --output-format csv -d gpurun_out/prof_o{o}{kind} "
+                 f"-o o{o}{kind} -- python3 -u bench.py --order {o} --forms none --steps 2 "
+                 f"--warmup 1 --timing-steps 1 --error-steps 0 --no-cpu-baseline --copy-calibration "
+                 f"> gpurun_out/prof_o{o}{kind}.json"
+           for kind, ctr in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE"))}}
+    for o in ("sfc", "canonical", "random")}
 CS_TRACERS = ("one", "h2o", "o3", "co2")  # the tracer set the tracer form carries
 OPTION_KERNELS = ("div4", "smag_cell", "smag_edge", "column_pred_sponge", "column_corr_sponge",
                   "tr_save", "tr_recon", "tr_horiz", "tr_vert")
@@ -623,8 +641,10 @@ def profile_summary(src, dst):
     wl = f"R2B6x90 ({nc} cells x {N} levels, dt 90 s, 5 substeps)"
     # ---- kernel trace ----
     stats = rows(os.path.join(src, "prof_trace", "trace_kernel_stats.csv"))
+    numbering = cfg.get("numbering", "sfc")
     lines = [f"# rocprofv3 kernel trace: dycore substep kernels, {wl}",
              f"kernel_source_sha256_16: {src_hash}",
+             f"numbering: {numbering}",
              f"command: {PROFILE_CMDS['trace']}",
              f"summarised by: python3 bench.py --profile-summary gpurun_out",
              "", "## per instantiation (rocprofv3 --stats)",
@@ -687,6 +707,7 @@ def profile_summary(src, dst):
                 per[var][1] += write.get(kname, [])
         lines = [f"# rocprofv3 HBM counters: dycore substep kernels, {prec} form, {wl}",
                  f"kernel_source_sha256_16: {src_hash}",
+                 f"numbering: {numbering}",
                  f"command (FETCH_SIZE pass): {PROFILE_CMDS['fetch']}",
                  f"command (WRITE_SIZE pass): {PROFILE_CMDS['write']}",
                  f"summarised by: python3 bench.py --profile-summary gpurun_out",
@@ -712,7 +733,72 @@ def profile_summary(src, dst):
     if all(k in runs for k in ("dtrace", "dfetch", "dwrite")):
         damped_summary(src, dst, runs, src_hash, wl, nc, ne, nv, N, rows, counter)
     config_summary(src, dst)
+    order_summary(src, dst)
     print(f"wrote summaries for kernel sources {src_hash} to {dst}")
+
+
+def order_summary(src, dst):
+    """profiles/dycore_numbering_r2b6x90.txt: per-kernel time (HIP events)
+    and counted HBM bytes of the FP64 step in the space-filling-curve, the
+    bisection's and a random numbering."""
+    import csv
+    from collections import defaultdict
+
+    def bytes_per_launch(tag):
+        out = {}
+        cal = {}
+        acc = {}
+        for kind, ctr in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE")):
+            f = os.path.join(src, f"prof_{tag}{kind}", f"{tag}{kind}_counter_collection.csv")
+            vals, copies = defaultdict(list), []
+            for r in sorted(csv.DictReader(open(f)), key=lambda r: int(r["Dispatch_Id"])):
+                if r["Counter_Name"] != ctr:
+                    continue
+                if "copyBuffer" in r["Kernel_Name"]:
+                    copies.append(float(r["Counter_Value"]))
+                    continue
+                k, p = _kernel_id(r["Kernel_Name"])
+                if k and p == "fp64":
+                    vals[k].append(float(r["Counter_Value"]))
+            cal[kind] = (1 << 30) / (copies[-1] * 1024)
+            acc[kind] = {k: sum(v) / len(v) * 1024 * cal[kind] for k, v in vals.items()}
+        for k in acc["fetch"]:
+            out[k] = acc["fetch"][k] + acc["write"].get(k, 0.0)
+        return out
+
+    runs = {"curve": ("", os.path.join(src, "bench.json"))}
+    for o in ORDER_CMDS:
+        runs[o] = (f"o{o}", os.path.join(src, f"bench_o{o}.json"))
+    if not all(os.path.exists(p) for _, p in runs.values()) or not all(
+            os.path.exists(os.path.join(src, f"prof_o{o}fetch.json")) for o in ORDER_CMDS):
+        return
+    res = {}
+    for o, (tag, path) in runs.items():
+        d = json.loads(open(path).read().strip().splitlines()[-1])
+        res[o] = {"ms": d["ms_per_step"], "kern": d["kernels"], "bytes": bytes_per_launch(tag)}
+    kernels = [k for k in res["curve"]["kern"] if k in res["random"]["kern"]]
+    lines = ["# the FP64 R2B6x90 step in four numberings of cells, edges and vertices: the "
+             "continuous curve over the bisection tree (the default), a 3-D Hilbert curve "
+             "through the cell centres, the bisection's own order, random",
+             f"kernel_source_sha256_16: {kernel_source_hash()}",
+             "commands (bisection curve): python3 -u bench.py > gpurun_out/bench.json; "
+             + PROFILE_CMDS["fetch"] + "; " + PROFILE_CMDS["write"]]
+    for o in ORDER_CMDS:
+        lines.append(f"commands ({o}): " + "; ".join(ORDER_CMDS[o][k] for k in ("run", "fetch", "write")))
+    lines += ["summarised by: python3 bench.py --profile-summary gpurun_out",
+              "per kernel: avg ms per launch (HIP events) / counted HBM bytes per cell-level per launch",
+              "", "ms per step: " + ", ".join(f"{o} {r['ms']:.2f}" for o, r in res.items()), "",
+              f"{'kernel':12s} " + " ".join(f"{o + ' ms':>14s} {o + ' B/cl':>14s}" for o in res)]
+    ncl = 327680 * 90
+    for k in kernels:
+        row = f"{k:12s} "
+        for o, r in res.items():
+            b = r["bytes"].get(k)
+            row += f"{r['kern'][k]['avg_ms']:14.4f} {(b / ncl if b else float('nan')):14.1f} "
+        lines.append(row.rstrip())
+    with open(os.path.join(dst, "dycore_numbering_r2b6x90.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("numbering: " + ", ".join(f"{o} {r['ms']:.2f} ms" for o, r in res.items()))
 
 
 def config_summary(src, dst):
@@ -834,6 +920,10 @@ def main():
     ap.add_argument("--timing-steps", type=int, default=4)
     ap.add_argument("--error-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--order", default="curve", choices=["curve", "sfc", "canonical", "random"],
+                    help="numbering of cells, edges and vertices of the default workload: the "
+                         "continuous curve over the bisection tree (default), a 3-D Hilbert "
+                         "curve through the cell centres, the bisection's own order, or random")
     ap.add_argument("--counters", action="store_true",
                     help="configs 3-5: run only the warm-up and timed steps (no kernel table, "
                          "error table, sequential runs or autotuning), for a hardware-counter pass")

@@ -52,7 +52,8 @@ extern "C" {
 #endif
 
 enum { NHGRID_OK = 0, NHGRID_EINVAL = -1, NHGRID_ENOMEM = -2, NHGRID_EINTERNAL = -3 };
-enum { NHGRID_ORDER_CANONICAL = 0, NHGRID_ORDER_SFC = 1, NHGRID_ORDER_RANDOM = 2 };
+enum { NHGRID_ORDER_CANONICAL = 0, NHGRID_ORDER_SFC = 1, NHGRID_ORDER_RANDOM = 2,
+       NHGRID_ORDER_CURVE = 3 };
 
 typedef struct nhgrid nhgrid;
 
@@ -99,6 +100,11 @@ int nhgrid_build(int k, double radius, nhgrid **out);
 /* Renumber in place.  order: NHGRID_ORDER_CANONICAL restores canonical ids;
  * NHGRID_ORDER_SFC sorts cells along a 3-D Hilbert curve through the cell
  * centres and numbers edges and vertices by first touch in that cell order;
+ * NHGRID_ORDER_CURVE orders cells along a vertex-continuous curve over the
+ * bisection tree (each triangle entered at one corner and left at another, its
+ * children visited entry corner, centre, third corner, exit corner; the 20
+ * root faces chained at shared vertices) and numbers edges and vertices by
+ * first touch in that cell order;
  * NHGRID_ORDER_RANDOM applies independent seeded random permutations to cells,
  * edges and vertices (a locality worst case used for invariance tests). */
 int nhgrid_reorder(nhgrid *g, int order, uint64_t seed);

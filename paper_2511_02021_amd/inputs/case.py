@@ -180,7 +180,7 @@ def legendre(l, x):
 
 
 def make_case(k, n_lev, z_top=30000.0, stretch=1.0, terrain_seed=None, noise_seed=None,
-              sigma=1.0, dt=300.0, nsub=5, order="sfc", balanced=True, gravity_wave=None,
+              sigma=1.0, dt=300.0, nsub=5, order="curve", balanced=True, gravity_wave=None,
               params=Params(), grids=None, meta=None):
     """Build one case.  ``terrain_seed`` is a seed of the random terrain, a
     callable mapping the canonical grid to surface heights, or None (flat).
@@ -235,7 +235,7 @@ CONFIGS = {
 BATCH_DT = {4: 300.0, 5: 150.0, 6: 90.0}
 
 
-def config_case(cfg, inst=0, order="sfc", k=None, n_lev=None, **kw):
+def config_case(cfg, inst=0, order="curve", k=None, n_lev=None, **kw):
     """Case of a named workload; ``k``/``n_lev`` override the grid size
     (smaller stand-ins of the same recipe for tests)."""
     c = CONFIGS[cfg]
@@ -254,7 +254,7 @@ def batch_shapes(n=16, seed=(2, 4, 0)):
     return [(int(a), int(b)) for a, b in zip(ks, ns)]
 
 
-def batch_cases(n=16, order="sfc"):
+def batch_cases(n=16, order="curve"):
     out = []
     for i, (k, nl) in enumerate(batch_shapes(n)):
         out.append(make_case(k, nl, z_top=75000.0, stretch=1.6, terrain_seed=[1, 4, i],

@@ -10,6 +10,7 @@
 #include "nhgrid.h"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -459,6 +460,54 @@ void apply(nhgrid *g, const std::vector<int32_t> &pc, const std::vector<int32_t>
     remap_values(g->vert_cells, ic);
 }
 
+// Canonical cell ids in the order of a continuous curve over the bisection
+// tree.  The canonical id of a cell is its root face followed by one base-4
+// digit per bisection level (0..2: the child at the parent's vertex slot j,
+// 3: the centre child).  A triangle entered at vertex slot a and left at slot
+// b visits its children as: the child at a, the centre, the child at the
+// third slot c, the child at b; consecutive children share a vertex, and every
+// child is left at its own slot b (the child at a is entered at a, the centre
+// and the child at b at c, the child at c at a).
+void bisection_curve(int64_t base, int64_t quarter, int a, int b, std::vector<int32_t> &out) {
+    if (quarter == 0) {
+        out.push_back(int32_t(base));
+        return;
+    }
+    const int c = 3 - a - b;
+    const int64_t q = quarter / 4;
+    bisection_curve(base + a * quarter, q, a, b, out);
+    bisection_curve(base + 3 * quarter, q, c, b, out);
+    bisection_curve(base + c * quarter, q, a, b, out);
+    bisection_curve(base + b * quarter, q, c, b, out);
+}
+
+// An order of the root faces, each with entry and exit vertex slots, in which
+// every face is entered at the vertex the previous one was left at (depth-
+// first search over faces sharing that vertex; the first face is face 0).
+bool chain_faces(const std::vector<std::array<int32_t, 3>> &corner, std::vector<int> &face,
+                 std::vector<int> &entry, std::vector<int> &exit_, std::vector<char> &used,
+                 int depth) {
+    const int nf = int(corner.size());
+    if (depth == nf) return true;
+    const int prev = depth > 0 ? face[depth - 1] : -1;
+    for (int f = 0; f < (prev < 0 ? 1 : nf); ++f) {
+        if (used[f]) continue;
+        for (int a = 0; a < 3; ++a) {
+            if (prev >= 0 && corner[f][a] != corner[prev][exit_[depth - 1]]) continue;
+            for (int b = 0; b < 3; ++b) {
+                if (b == a) continue;
+                used[f] = 1;
+                face[depth] = f;
+                entry[depth] = a;
+                exit_[depth] = b;
+                if (chain_faces(corner, face, entry, exit_, used, depth + 1)) return true;
+                used[f] = 0;
+            }
+        }
+    }
+    return false;
+}
+
 }  // namespace
 
 extern "C" int nhgrid_reorder(nhgrid *g, int order, uint64_t seed) {
@@ -484,11 +533,49 @@ extern "C" int nhgrid_reorder(nhgrid *g, int order, uint64_t seed) {
                 }
                 key[c] = {hilbert3(q[0], q[1], q[2], bits), g->canon_cell[c]};
             }
-            std::vector<int32_t> idx(nc);
-            std::iota(idx.begin(), idx.end(), 0);
-            std::sort(idx.begin(), idx.end(),
-                      [&](int32_t x, int32_t y) { return key[x] < key[y]; });
-            pc = idx;
+            std::iota(pc.begin(), pc.end(), 0);
+            std::sort(pc.begin(), pc.end(), [&](int32_t x, int32_t y) { return key[x] < key[y]; });
+        } else if (order == NHGRID_ORDER_CURVE) {
+            // current id of each canonical cell
+            std::vector<int32_t> cur(nc);
+            for (int64_t i = 0; i < nc; ++i) cur[g->canon_cell[i]] = int32_t(i);
+            const int64_t per_face = nc / 20;  // 4^(bisection levels)
+            // the root faces' corner vertices: the child at slot j on every
+            // level carries the root's vertex j
+            std::vector<std::array<int32_t, 3>> corner(20);
+            for (int f = 0; f < 20; ++f)
+                for (int j = 0; j < 3; ++j) {
+                    const int64_t id = int64_t(f) * per_face + j * ((per_face - 1) / 3);
+                    corner[f][j] = g->cell_verts[j * nc + cur[id]];
+                }
+            std::vector<int> face(20), entry(20), exit_(20);
+            std::vector<char> used(20, 0);
+            if (!chain_faces(corner, face, entry, exit_, used, 0))
+                return fail(NHGRID_EINTERNAL, "nhgrid_reorder: no vertex chain over the root faces");
+            std::vector<int32_t> canon_order;
+            canon_order.reserve(nc);
+            for (int i = 0; i < 20; ++i)
+                bisection_curve(int64_t(face[i]) * per_face, per_face / 4, entry[i], exit_[i],
+                                canon_order);
+            if (int64_t(canon_order.size()) != nc)
+                return fail(NHGRID_EINTERNAL, "nhgrid_reorder: curve length mismatch");
+            for (int64_t i = 0; i < nc; ++i) pc[i] = cur[canon_order[i]];
+        } else if (order == NHGRID_ORDER_RANDOM) {
+            std::mt19937_64 rng(seed);
+            auto shuffle = [&](std::vector<int32_t> &p) {
+                std::iota(p.begin(), p.end(), 0);
+                for (int64_t i = int64_t(p.size()) - 1; i > 0; --i) {
+                    int64_t j = int64_t(rng() % uint64_t(i + 1));
+                    std::swap(p[i], p[j]);
+                }
+            };
+            shuffle(pc);
+            shuffle(pe);
+            shuffle(pv);
+        } else {
+            return fail(NHGRID_EINVAL, "nhgrid_reorder: unknown order");
+        }
+        if (order == NHGRID_ORDER_SFC || order == NHGRID_ORDER_CURVE) {
             // edges and vertices by first touch in the new cell order
             std::vector<char> seen_e(ne, 0), seen_v(nv, 0);
             int64_t ke = 0, kv = 0;
@@ -505,20 +592,6 @@ extern "C" int nhgrid_reorder(nhgrid *g, int order, uint64_t seed) {
             }
             if (ke != ne || kv != nv)
                 return fail(NHGRID_EINTERNAL, "nhgrid_reorder: first-touch count mismatch");
-        } else if (order == NHGRID_ORDER_RANDOM) {
-            std::mt19937_64 rng(seed);
-            auto shuffle = [&](std::vector<int32_t> &p) {
-                std::iota(p.begin(), p.end(), 0);
-                for (int64_t i = int64_t(p.size()) - 1; i > 0; --i) {
-                    int64_t j = int64_t(rng() % uint64_t(i + 1));
-                    std::swap(p[i], p[j]);
-                }
-            };
-            shuffle(pc);
-            shuffle(pe);
-            shuffle(pv);
-        } else {
-            return fail(NHGRID_EINVAL, "nhgrid_reorder: unknown order");
         }
         apply(g, pc, pe, pv);
         g->order = order;

@@ -11,7 +11,7 @@ import numpy as np
 
 from .. import _build
 
-ORDERS = {"canonical": 0, "sfc": 1, "random": 2}
+ORDERS = {"canonical": 0, "sfc": 1, "random": 2, "curve": 3}
 EARTH_RADIUS = 6371229.0
 
 
@@ -100,7 +100,7 @@ def _snapshot(h):
     nc, ne, nv = v.n_cells, v.n_edges, v.n_verts
     i32, i8, f64 = C.c_int32, C.c_int8, C.c_double
     return Grid(
-        k=v.k, order={0: "canonical", 1: "sfc", 2: "random"}[v.order], radius=v.radius,
+        k=v.k, order={v_: k_ for k_, v_ in ORDERS.items()}[v.order], radius=v.radius,
         n_cells=nc, n_edges=ne, n_verts=nv,
         cell_edges=_copy(v.cell_edges, i32, (3, nc)), cell_verts=_copy(v.cell_verts, i32, (3, nc)),
         cell_cells=_copy(v.cell_cells, i32, (3, nc)), cell_sign=_copy(v.cell_sign, i8, (3, nc)),

@@ -131,7 +131,7 @@ def _mapped_back(gr, canon):
     return out
 
 
-@pytest.mark.parametrize("order", ["sfc", "random"])
+@pytest.mark.parametrize("order", ["sfc", "random", "curve"])
 def test_renumbering_is_a_relabelling(order):
     canon, gr = G.build_grid(4, order=order, seed=7, with_canonical=True)
     for m in (gr.canon_cell, gr.canon_edge, gr.canon_vert):
@@ -151,3 +151,20 @@ def test_sfc_locality_beats_random():
     # edges numbered by first touch: a cell's three edge ids are close together
     spread = lambda gr: np.median(gr.cell_edges.max(0) - gr.cell_edges.min(0))
     assert spread(sfc) < 16 and spread(rnd) > 10000
+
+
+@pytest.mark.parametrize("k", [0, 1, 3, 5])
+def test_bisection_curve_is_vertex_continuous(k):
+    """Along the curve order every cell shares at least a vertex with the
+    next one (root faces included), and most share an edge; the edges and
+    vertices follow by first touch."""
+    g = G.build_grid(k, order="curve")
+    cv = g.cell_verts
+    cnt = np.zeros(g.n_cells - 1, dtype=int)
+    for a in range(3):
+        for b in range(3):
+            cnt += cv[a, :-1] == cv[b, 1:]
+    assert cnt.min() >= 1
+    assert (cnt >= 2).mean() > 0.6
+    spread = np.median(g.cell_edges.max(0) - g.cell_edges.min(0))
+    assert spread < 16

@@ -449,7 +449,7 @@ def test_substep_splitting_is_exact():
 
 def test_numbering_invariance():
     ref = None
-    for order, seed in (("canonical", 0), ("sfc", 0), ("random", 5)):
+    for order, seed in (("canonical", 0), ("sfc", 0), ("random", 5), ("curve", 0)):
         canon, gr = G.build_grid(3, order=order, seed=seed, with_canonical=True)
         c = CS.config_case(2, k=3, n_lev=20, grids=(canon, gr))
         s = _run(c, 2).state()
