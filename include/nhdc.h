@@ -23,6 +23,13 @@
  * state with interface values averaged between old and predicted; FP64
  * accumulation of the mass fluxes.
  *
+ * Options (nhdc_params, nhdc_vertical, nhdc_set_tracers; all off by default):
+ * second-order upwind edge values of rho and theta_v in the fluxes; fourth-
+ * order divergence damping; a Rayleigh sponge on w in the column solves;
+ * Smagorinsky diffusion of vn once per step; and tracers carried by the
+ * step's averaged mass fluxes (Sec. 1 counts water vapour, carbon dioxide and
+ * ozone among the atmosphere's prognostic quantities; Table 2).
+ *
  * Conventions
  *  - Return values: NHDC_OK (0) or a negative NHDC_E* code; nothing throws or
  *    aborts across the ABI.  nhdc_last_error(ctx) gives the message of the
@@ -151,7 +158,11 @@ int nhdc_upload_grid(nhdc_ctx *ctx, const nhdc_grid *grid, const nhdc_vertical *
 int nhdc_init_state(nhdc_ctx *ctx, const nhdc_state_view *state, void *stream);
 
 /* Enqueue nsubsteps substeps of dt/nsubsteps.  The mass-flux accumulators are
- * restarted at entry and hold the average over these substeps afterwards. */
+ * restarted at entry and hold the average over these substeps afterwards.
+ * With the options set, the step also runs the diffusion of vn over dt after
+ * the substeps, and then the tracer transport with the averaged fluxes.
+ * Errors: EINVAL for dt <= 0 or not finite and nsubsteps < 1, ESTATE before
+ * a state is initialised, EHIP when a launch fails. */
 int nhdc_step(nhdc_ctx *ctx, double dt, int nsubsteps, void *stream);
 
 /* Copy the state into caller buffers (host or device per dst->on_device;
