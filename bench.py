@@ -253,6 +253,29 @@ def copy_bandwidth(torch, gib=4, reps=10):
     return 2 * (gib << 30) / (best / 1e3) / 1e9
 
 
+def stream_rates(torch, gib=4, reps=10):
+    """Read-only (a sum) and write-only (a fill) streaming over `gib` GiB, the
+    best of `reps` each, in GB/s: with the copy, the rates plain streaming
+    kernels reach on this GPU."""
+    n = (gib << 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    out = {}
+    for name, op in (("read", lambda: a.sum()), ("write", lambda: a.fill_(1.0))):
+        best = float("inf")
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            op()
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        out[name] = (gib << 30) / (best / 1e3) / 1e9
+    del a
+    torch.cuda.empty_cache()
+    return out
+
+
 def kernel_table(d, case, steps, stream, precision):
     g = case.grid
     d.set_timing(True)
@@ -385,7 +408,11 @@ def bench_default(args, torch, nhdc, CS):
         copy_gbs = copy_bandwidth(torch)
         roofline["copy_GBs"] = round(copy_gbs, 1)
         roofline["frac_of_copy"] = round(achieved / copy_gbs, 4)
-        log(f"4 GiB device copy: {copy_gbs:.1f} GB/s")
+        rates = stream_rates(torch)
+        roofline["read_GBs"] = round(rates["read"], 1)
+        roofline["write_GBs"] = round(rates["write"], 1)
+        log(f"4 GiB device copy: {copy_gbs:.1f} GB/s; read-only {rates['read']:.1f}, "
+            f"write-only {rates['write']:.1f} GB/s")
     mk = tables["mixed"]
     mdom = max(mk, key=lambda k: mk[k]["share"])
     forms["mixed"]["kernels"] = {k: {"avg_ms": round(v["avg_ms"], 5), "share": round(v["share"], 4),
