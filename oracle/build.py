@@ -7,10 +7,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SO = os.path.join(HERE, "liboracle.so")
 
 
+def command(src, out):
+    """The compiler command of the oracle library."""
+    return ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
+            "-shared", "-I", HERE, src, "-lm", "-o", out]
+
+
 def build():
     tmp = SO + ".tmp"
-    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
-           "-shared", os.path.join(HERE, "nhdc_oracle.c"), "-lm", "-o", tmp]
+    cmd = command(os.path.join(HERE, "nhdc_oracle.c"), tmp)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("oracle build failed:\n" + " ".join(cmd) + "\n" + r.stderr)

@@ -5,6 +5,7 @@ tridiagonal solve, a dense solve of the un-substituted implicit column
 equations, the resting atmosphere, conservation of mass and rho*theta_v, the
 linear gravity-wave dispersion relation, and algebraic invariances
 (numbering, substep splitting, save/resume)."""
+import dataclasses
 import types
 
 import numpy as np
@@ -165,6 +166,121 @@ def test_solid_body_rotation_convergence():
         assert np.all(e[1:] < e[:-1]), (name, e)
         assert rates[-1] > 0.9, (name, e, rates)
     assert errs["vt"][-1] < 2e-3 and errs["zeta"][-1] < 2e-2 and errs["ke"][-1] < 2e-2
+
+
+def _sheared_solid_body(k, N=12, U0=15.0, S=1e-3, W0=0.0, params=None):
+    """vn of u = (U0 + S z) cos(lat) eastward on a flat R2Bk, w = W0 at the
+    interior half levels; returns the case, vn, w and the edge projections of
+    cos(lat) e_lambda and cos(lat) e_phi."""
+    c = CS.make_case(k, N, z_top=12000.0, sigma=0.0, params=params or CS.Params())
+    g = c.grid
+    z = 0.5 * (c.zh[:-1] + c.zh[1:])[:, 0]
+    east = (np.cross(np.array([0.0, 0.0, 1.0])[:, None], g.edge_x, axis=0) * g.edge_normal).sum(0)
+    north = ((np.array([0.0, 0.0, 1.0])[:, None] - g.edge_x[2] * g.edge_x) * g.edge_normal).sum(0)
+    u0 = U0 + S * z
+    vn = u0[:, None] * east[None, :]
+    w = np.zeros((N + 1, g.n_cells))
+    w[1:N] = W0
+    return c, u0, vn, w, east, north
+
+
+def test_vn_tendency_of_sheared_solid_body_rotation():
+    """For u = u0(z) cos(lat) eastward the horizontal tendency is
+    -(u0/a + 2 Omega) u0 sin(lat) cos(lat) northward (within 1.5 % at R2B4-5;
+    the vector-invariant form on triangles keeps a ~1 % error here rather than
+    converging); the rotation term alone is 2 Omega sin(lat) times the
+    tangential velocity; a uniform ascent W0 adds exactly -W0 du0/dz eastward
+    at the levels whose two half levels are interior."""
+    Om = CS.Params().omega
+    for k in (4, 5):
+        c, u0, vn, w, east, north = _sheared_solid_body(k)
+        sinp = c.grid.edge_x[2]
+        t_rot, _, _, _ = oracle.Model(c).vt(vn, w)
+        exact = -(u0[:, None] / A + 2 * Om) * u0[:, None] * sinp[None, :] * north[None, :]
+        ks = slice(1, c.n_lev - 1)
+        assert np.abs(t_rot[ks] - exact[ks]).max() <= 0.015 * np.abs(exact[ks]).max(), k
+        c0 = CS.make_case(k, c.n_lev, z_top=12000.0, sigma=0.0, params=CS.Params(omega=0.0))
+        t0, _, _, _ = oracle.Model(c0).vt(vn, w)
+        cor = -2 * Om * u0[:, None] * sinp[None, :] * north[None, :]
+        assert np.abs((t_rot - t0)[ks] - cor[ks]).max() <= 0.01 * np.abs(cor[ks]).max(), k
+    S, W0 = 1e-3, 0.5
+    c, u0, vn, w, east, north = _sheared_solid_body(4, S=S, W0=W0)
+    t_up, _, _, _ = oracle.Model(c).vt(vn, w)
+    t_no, _, _, _ = oracle.Model(c).vt(vn, np.zeros_like(w))
+    vert = -W0 * S * east
+    ks = slice(1, c.n_lev - 1)
+    assert np.abs((t_up - t_no)[ks] - vert[None, :]).max() <= 1e-9 * np.abs(vert).max()
+
+
+def test_w_tendency_of_advected_ascent():
+    """w = W1 x (x the first Cartesian coordinate of the unit position) carried
+    by the solid-body flow u = U0 cos(lat) eastward turns with the flow:
+    dw/dt = (U0/a) W1 y (within 5 % at R2B4-5: the tangential derivative of w
+    across the edge, taken between vertex interpolations of the cell values,
+    keeps an error of ~8 % of its own on the irregular grid rather than
+    converging; the normal derivative and the cell average converge).  At rest, w = a0 + b z
+    gives dw/dt = -(a0 + b z) b exactly at the half levels whose neighbours
+    are interior."""
+    U0, W1 = 15.0, 0.3
+    for k in (4, 5):
+        c, _, vn, w, _, _ = _sheared_solid_body(k, U0=U0, S=0.0)
+        g = c.grid
+        w[1:c.n_lev] = W1 * g.cell_x[0]
+        _, tw, _, _ = oracle.Model(c).vt(vn, w)
+        exact = (U0 / A) * W1 * g.cell_x[1]
+        ii = slice(2, c.n_lev - 1)
+        assert np.abs(tw[ii] - exact[None, :]).max() <= 0.05 * np.abs(exact).max(), k
+    a0, b = 0.2, 3e-5
+    c, _, vn, w, _, _ = _sheared_solid_body(3, U0=0.0, S=0.0)
+    zh = c.zh[:, 0]
+    w[1:c.n_lev] = (a0 + b * zh[1:c.n_lev])[:, None]
+    _, tw, _, _ = oracle.Model(c).vt(np.zeros_like(vn), w)
+    ii = slice(2, c.n_lev - 1)
+    exact = -(a0 + b * zh[ii]) * b
+    assert np.abs(tw[ii] - exact[:, None]).max() <= 1e-12 * np.abs(exact).max()
+
+
+def test_smagorinsky_coefficient_scales_with_cell_area():
+    """The diffusion's one-step change of vn, for a smooth zonal flow with
+    shear (u = U0 cos^2(lat) eastward), scales as (c_s Delta)^2 with Delta^2
+    the cell area: doubling c_s quadruples it (4.000), and going from R2B3 to
+    R2B4 quarters it (3.88: the deformation and the Laplacian of the smooth
+    flow are near their limits there; on finer grids the grid-scale error of
+    the tangential velocity adds deformation of its own and the ratio drops,
+    3.4 from R2B4 to R2B5).  The change stays below the stability cap."""
+    U0 = 20.0
+
+    def change(k, smag):
+        c, _, _, w, east, _ = _sheared_solid_body(k, N=3, S=0.0)
+        g = c.grid
+        vn = U0 * np.sqrt(1.0 - g.edge_x[2] ** 2) * east
+        out = []
+        for s in (0.0, smag):
+            m = oracle.Model(c, params=dataclasses.replace(c.params, smag=s))
+            m.set_state(np.tile(vn, (c.n_lev, 1)), w, c.rho, c.pi, c.theta_v)
+            m.step(c.dt, c.nsub)
+            out.append(m.state()["vn"])
+        return float(np.sqrt(np.mean((out[1] - out[0]) ** 2)))
+
+    d3, d3x2, d4 = change(3, 0.15), change(3, 0.3), change(4, 0.15)
+    assert 3.9 <= d3x2 / d3 <= 4.1
+    assert 3.5 <= d3 / d4 <= 4.5
+
+
+def test_divergence_damping_removes_divergence():
+    """The corrector's second-order divergence damping lowers the divergence
+    variance against the same run without it."""
+    base = CS.config_case(1, k=3)
+    g = base.grid
+
+    def dvar(div_damp):
+        m = oracle.Model(base, params=CS.Params(div_damp=div_damp))
+        for _ in range(5):
+            m.step(base.dt, base.nsub)
+        vn = m.state()["vn"]
+        return sum(float(np.sum(g.cell_area * oracle.div(g, vn[k]) ** 2)) for k in range(base.n_lev))
+
+    assert dvar(0.01) < 0.9 * dvar(0.0)
 
 
 # ---------------------------------------------------------------------------
@@ -842,14 +958,17 @@ def test_ppm_interfaces_exact_for_cubic_means_on_stretched_levels():
     assert a[0] == q[0] and a[N] == q[N - 1]
 
 
+@pytest.mark.parametrize("levels", ["uniform", "uneven"])
 @pytest.mark.parametrize("w", [0.37, -0.52])
-def test_ppm_column_exact_for_quadratic_under_uniform_advection(w):
-    """Uniform levels, density 1 and mass flux w (m/s) in the interior: cells
-    whose parabolas and upwind neighbours are all interior take the exact
-    means of the profile shifted by w dt."""
+def test_ppm_column_exact_for_quadratic_under_uniform_advection(w, levels):
+    """Density 1 and mass flux w (m/s) in the interior, on uniform levels and
+    on uneven ones (each thicker than w dt): cells whose parabolas and upwind
+    neighbours are all interior take the exact means of the profile shifted
+    by w dt.  On uneven levels the parabolas' curvature terms differ from
+    cell to cell, so they do not cancel in the flux differences."""
     N, dzv, dt = 30, 200.0, 250.0
-    dz = np.full(N, dzv)
-    zh = dzv * np.arange(N, -1, -1, dtype=float)
+    dz = np.full(N, dzv) if levels == "uniform" else np.random.default_rng(11).uniform(150.0, 400.0, N)
+    zh = np.concatenate([np.cumsum(dz[::-1])[::-1], [0.0]])
     coef = [1.0, 3e-4, -2e-8]
     q = _cubic_means(zh[:-1], zh[1:], coef)
     W = np.full(N + 1, w)
@@ -919,3 +1038,26 @@ def test_tracer_at_rest_stays_put():
     q = m.tracers()
     for t in range(q.shape[0]):
         assert np.abs(q[t] - c.tracers[t]).max() <= 1e-12 * np.abs(c.tracers[t]).max(), t
+
+
+def test_tracer_transport_does_not_grow_noise():
+    """A grid-scale random tracer carried by the flow of a terrain case: its
+    mass-weighted variance does not grow (upwind-biased fluxes damp the grid
+    scale; downwind ones would amplify it)."""
+    c = CS.config_case(2, k=3, n_lev=20)
+    rng = np.random.default_rng(31)
+    q = 1.0 + 0.1 * rng.standard_normal((1, c.n_lev, c.grid.n_cells))
+    c = dataclasses.replace(c, tracers=np.ascontiguousarray(q))
+    vol = c.grid.cell_area[None, :] * (c.zh[:-1] - c.zh[1:])
+
+    def var(m, qt):
+        rho = m.state()["rho"]
+        w = vol * rho
+        mean = np.sum(w * qt) / np.sum(w)
+        return np.sum(w * (qt - mean) ** 2)
+
+    m = oracle.Model(c)
+    v0 = var(m, m.tracers()[0])
+    for _ in range(10):
+        m.step(c.dt, c.nsub)
+    assert var(m, m.tracers()[0]) < v0

@@ -1,0 +1,101 @@
+"""The pins catch plausible mistakes.  Each case plants one mistake in a copy
+of the oracle's source (a flipped sign, a dropped term, a swapped index or
+operand), builds it, and runs the named pins against that build in a child
+process: at least one of them must fail.  CPU only; the oracle in the
+repository is not touched."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+from oracle import build as OB
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "nhdc_oracle.c")
+T = "tests/test_oracle.py::"
+
+# (what, original text, mistaken text, pins that must catch it)
+MUTANTS = [
+    ("Coriolis term with the wrong sign",
+     "(zeta_e + m->fe[e])", "(zeta_e - m->fe[e])",
+     [T + "test_vn_tendency_of_sheared_solid_body_rotation"]),
+    ("vertical advection of vn dropped",
+     " - obar * dvdz;", ";",
+     [T + "test_vn_tendency_of_sheared_solid_body_rotation"]),
+    ("normal gradient from c2 to c1",
+     "(p[g->edge_cells[ne + e]] - p[g->edge_cells[e]])",
+     "(p[g->edge_cells[e]] - p[g->edge_cells[ne + e]])",
+     [T + "test_divergence_of_gradient_exact_for_quadratic_on_regular_lattice"]),
+    ("kinetic-energy gradient from c2 to c1",
+     "(AT(m->kc, k, nc, c2) - AT(m->kc, k, nc, c1))", "(AT(m->kc, k, nc, c1) - AT(m->kc, k, nc, c2))",
+     [T + "test_vn_tendency_of_sheared_solid_body_rotation"]),
+    ("horizontal advection of w with the wrong sign",
+     "= -hadv - AT(m->omega", "= hadv - AT(m->omega",
+     [T + "test_w_tendency_of_advected_ascent"]),
+    ("divergence damping with the wrong sign",
+     "+ p->div_damp * abar * gdiv;", "- p->div_damp * abar * gdiv;",
+     [T + "test_divergence_damping_removes_divergence"]),
+    ("reference profile interpolated from the wrong levels",
+     "gw[i] * theta_ref[i] + (1.0 - gw[i]) * theta_ref[i - 1]",
+     "gw[i] * theta_ref[i - 1] + (1.0 - gw[i]) * theta_ref[i]",
+     [T + "test_column_matches_dense_solve_of_implicit_equations[20-3]"]),
+    ("explicit weight 1 + beta instead of 1 - beta",
+     "double pterm = (1.0 - beta)", "double pterm = (1.0 + beta)",
+     [T + "test_column_matches_dense_solve_of_implicit_equations[20-3]"]),
+    ("tridiagonal diagonal with the wrong sign",
+     "tb[i - 1] = 1.0 + ga[i]", "tb[i - 1] = 1.0 - ga[i]",
+     [T + "test_column_matches_dense_solve_of_implicit_equations[20-3]"]),
+    ("theta flux carried with rho instead of theta",
+     "AT(m->hfl, k, ne, e) = AT(the, k, ne, e) * f;", "AT(m->hfl, k, ne, e) = AT(rhoe, k, ne, e) * f;",
+     [T + "test_gravity_wave_frequency_r2b3"]),
+    ("mass flux without the layer depth",
+     "AT(vnx, k, ne, e) * AT(m->dz_e, k, ne, e);", "AT(vnx, k, ne, e);",
+     [T + "test_gravity_wave_frequency_r2b3"]),
+    ("upwind value from the downwind cell",
+     "int64_t up = u[e] >= 0.0 ?", "int64_t up = u[e] < 0.0 ?",
+     [T + "test_upwind_takes_the_upwind_cell"]),
+    ("upwind displacement reversed",
+     "d[x] = a * (g->edge_x[x * ne + e] - g->cell_x[x * nc + up])",
+     "d[x] = a * (g->cell_x[x * nc + up] - g->edge_x[x * ne + e])",
+     [T + "test_upwind_edge_value_exact_for_linear_field_on_a_plane"]),
+    ("sponge multiplies instead of divides",
+     "wp[i] * (1.0 / (1.0 + dt * p->w_damp[i]))", "wp[i] * (1.0 + dt * p->w_damp[i])",
+     [T + "test_column_sponge_damps_the_solved_w[20-3]"]),
+    ("deformation with the trace added",
+     "double d2 = 2.0 * s2 - tr * tr;", "double d2 = 2.0 * s2 + tr * tr;",
+     [T + "test_deformation_exact_for_linear_field_on_a_plane"]),
+    ("diffusion with the wrong sign",
+     "u[e] = u[e] + dt * ke * lap[e];", "u[e] = u[e] - dt * ke * lap[e];",
+     [T + "test_each_damping_option_removes_energy_where_it_acts"]),
+    ("Smagorinsky coefficient without the cell area",
+     "kh[c] = cs2 * g->cell_area[c] * kh[c];", "kh[c] = cs2 * kh[c];",
+     [T + "test_smagorinsky_coefficient_scales_with_cell_area"]),
+    ("tracer flux from the downwind cell",
+     "const int64_t up = F[e] >= 0.0 ?", "const int64_t up = F[e] < 0.0 ?",
+     [T + "test_tracer_transport_does_not_grow_noise"]),
+    ("tracer gradient without the arc weight",
+     "double dq = wgt * (q[nb] - q[c]);", "double dq = (q[nb] - q[c]);",
+     [T + "test_tracer_gradient_exact_for_linear_and_zero_for_constant"]),
+    ("PPM upward mean with the wrong curvature sign",
+     "aT + 0.5 * c * (da + a6", "aT + 0.5 * c * (da - a6",
+     [T + "test_ppm_column_exact_for_quadratic_under_uniform_advection[0.37-uneven]"]),
+    ("PPM upwind cell swapped",
+     "const int up = W[i] > 0.0 ? i : i - 1;", "const int up = W[i] > 0.0 ? i - 1 : i;",
+     [T + "test_ppm_column_exact_for_quadratic_under_uniform_advection[0.37-uneven]"]),
+]
+
+
+@pytest.mark.parametrize("what,old,new,pins", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_planted_mistake_is_caught(tmp_path, what, old, new, pins):
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"the text to change is not unique in the oracle: {old!r}"
+    mutant = tmp_path / "nhdc_oracle.c"
+    mutant.write_text(src.replace(old, new))
+    so = str(tmp_path / "liboracle_mutant.so")
+    r = subprocess.run(OB.command(str(mutant), so), capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    env = dict(os.environ, ORACLE_SO=so, OMP_NUM_THREADS=os.environ.get("OMP_NUM_THREADS", "8"))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", *pins],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 1 and "failed" in r.stdout, (what, r.stdout[-2000:])
