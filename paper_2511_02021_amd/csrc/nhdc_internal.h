@@ -94,13 +94,12 @@ struct Work {
     RT *wcc1 = nullptr, *tw1 = nullptr;  // [N+1][nc] of the predicted state
     RT *tvn0 = nullptr;   // [N][ne] vn tendency of state n
     double *vns = nullptr;    // [N][ne] predicted vn
-    double *flx = nullptr;    // [N][ne] corrector edge mass flux
-    double *hfl = nullptr;    // [N][ne] corrector edge rho*theta_v flux
+    double *fh = nullptr;     // [N][ne][2] edge mass flux and rho*theta_v flux, paired
     double *ws = nullptr;     // [N+1][nc] predicted w
     double *rhos = nullptr;   // [N][nc] predicted rho
     double *thvs = nullptr;   // [N][nc] predicted theta_v
-    double *cp = nullptr, *dp = nullptr;  // [N+1][nc] Thomas factors
-    double *rh = nullptr, *ph = nullptr;  // [N][nc] explicit rho and Exner parts
+    double *cd = nullptr;     // [N+1][nc][2] Thomas factors c', d', paired
+    double *rp = nullptr;     // [N][nc][2] explicit rho and Exner parts, paired
     double *gq = nullptr;  // [N][nc][6] cell gradients of rho, then theta_v (upwind)
     RT *dd4 = nullptr;     // [N][nc] D(G(D(vn*))) (fourth-order divergence damping)
     RT *kh = nullptr;      // [N][nc] Smagorinsky coefficient of the cell (diffusion)

@@ -431,15 +431,15 @@ int alloc_work(nhdc_ctx *ctx, Work<RT> &W) {
     if ((rc = dalloc(ctx, &W.zeta, NV))) return rc;
     if ((rc = dalloc(ctx, &W.wv, NV1))) return rc;
     HIP_TRY(ctx, hipMemset(W.wv, 0, sizeof(RT) * NV1));
-    double **d_c[] = {&W.rhos, &W.thvs, &W.rh, &W.ph};
-    double **d_c1[] = {&W.ws, &W.cp, &W.dp};
-    double **d_e[] = {&W.vns, &W.flx, &W.hfl};
+    double **d_c[] = {&W.rhos, &W.thvs};
     for (auto q : d_c)
         if ((rc = dalloc(ctx, q, NC))) return rc;
-    for (auto q : d_c1)
-        if ((rc = dalloc(ctx, q, NC1))) return rc;
-    for (auto q : d_e)
-        if ((rc = dalloc(ctx, q, NE))) return rc;
+    if ((rc = dalloc(ctx, &W.ws, NC1))) return rc;
+    if ((rc = dalloc(ctx, &W.vns, NE))) return rc;
+    // pairs of doubles read and written together
+    if ((rc = dalloc(ctx, &W.rp, 2 * NC))) return rc;
+    if ((rc = dalloc(ctx, &W.cd, 2 * NC1))) return rc;
+    if ((rc = dalloc(ctx, &W.fh, 2 * NE))) return rc;
     if (ctx->p.upwind) {
         if ((rc = dalloc(ctx, &W.gq, 6 * NC))) return rc;
     }
