@@ -56,6 +56,10 @@ struct Grid {
     // sponge option: Rayleigh damping rate of w per half level [N+1] (or null)
     double *w_damp = nullptr;
     double *zh = nullptr;         // [N+1][nc] half-level heights
+    // leading half levels (from the lid down) at which every cell's zh, and
+    // every vertex's zhv, has the same bits: there a neighbour's height is the
+    // level's first entry, read without a gather
+    int32_t flat_c = 0, flat_v = 0;
     double *zhv = nullptr;        // [N+1][nv] vertex average of zh
     double *pi_ref = nullptr;     // [N][nc]
     double *theta_ref = nullptr;  // [N][nc]
@@ -197,6 +201,9 @@ hipError_t launch_tracers_fp64(const Launcher &L, const Sub &sub, int phase, Tim
 hipError_t launch_tracers_mixed(const Launcher &L, const Sub &sub, int phase, Timing *tm, hipStream_t st);
 // set-up and diagnostics (nhdc_util.hip)
 hipError_t launch_metrics(const Grid &g, hipStream_t st);
+// out[i] |= 1 where row i of the [nlev][n] array a has an entry whose bits
+// differ from its first entry's
+hipError_t launch_level_nonflat(const double *a, int64_t n, int nlev, int32_t *out, hipStream_t st);
 hipError_t launch_to_float(const double *src, float *dst, int64_t n, hipStream_t st);
 hipError_t launch_diag(const Grid &g, const State &s, double *part, double *out2, hipStream_t st);
 hipError_t launch_finite(const Grid &g, const State &s, int *flag, hipStream_t st);

@@ -645,6 +645,20 @@ int nhdc_upload_grid(nhdc_ctx *ctx, const nhdc_grid *g, const nhdc_vertical *v,
     if (v->w_damp)
         if ((rc = upload(ctx, &G.w_damp, v->w_damp, int64_t(N) + 1))) return rc;
     HIP_TRY(ctx, launch_metrics(G, nullptr));
+    {
+        // the flat top of the height coordinate, level by level from the lid
+        int32_t *d_nf = nullptr;
+        if ((rc = dalloc(ctx, &d_nf, 2 * (int64_t(N) + 1)))) return rc;
+        HIP_TRY(ctx, hipMemset(d_nf, 0, sizeof(int32_t) * 2 * (size_t(N) + 1)));
+        HIP_TRY(ctx, launch_level_nonflat(G.zh, nc, N + 1, d_nf, nullptr));
+        HIP_TRY(ctx, launch_level_nonflat(G.zhv, nv, N + 1, d_nf + N + 1, nullptr));
+        std::vector<int32_t> nf(2 * (size_t(N) + 1));
+        HIP_TRY(ctx, hipMemcpy(nf.data(), d_nf, sizeof(int32_t) * nf.size(), hipMemcpyDeviceToHost));
+        G.flat_c = 0;
+        while (G.flat_c <= N && nf[G.flat_c] == 0) ++G.flat_c;
+        G.flat_v = 0;
+        while (G.flat_v <= N && nf[N + 1 + G.flat_v] == 0) ++G.flat_v;
+    }
     if (ctx->precision == NHDC_MIXED) {
         Geo<float> &F = G.gf;
         if ((rc = upload_f32(ctx, &F.c_sl, D.c_sl, 3 * nc))) return rc;

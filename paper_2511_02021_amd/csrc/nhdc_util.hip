@@ -29,6 +29,14 @@ __global__ void k_metrics_vert(int64_t nv, int64_t nc, int N, const int32_t *__r
     }
 }
 
+__global__ void k_level_nonflat(const double *__restrict__ a, int64_t n, int32_t *__restrict__ out) {
+    const int lvl = int(blockIdx.y);
+    const int64_t j = int64_t(blockIdx.x) * BLOCK + threadIdx.x;
+    const double *row = a + int64_t(lvl) * n;
+    const bool d = j < n && __double_as_longlong(row[j]) != __double_as_longlong(row[0]);
+    if (__ballot(d) != 0 && (threadIdx.x & 63u) == 0) atomicOr(out + lvl, 1);
+}
+
 __global__ void k_to_float(const double *__restrict__ src, float *__restrict__ dst, int64_t n) {
     int64_t i = lin();
     if (i < n) dst[i] = float(src[i]);
@@ -114,6 +122,11 @@ __global__ void k_finite(int64_t n, const double *__restrict__ x, int *__restric
 hipError_t launch_metrics(const Grid &g, hipStream_t st) {
     hipLaunchKernelGGL(k_metrics_vert, dim3(nb(g.nv)), dim3(BLOCK), 0, st, g.nv, g.nc, g.N, g.v_c,
                        g.gd.v_m, g.gd.v_ival, g.zh, g.zhv);
+    return hipGetLastError();
+}
+
+hipError_t launch_level_nonflat(const double *a, int64_t n, int nlev, int32_t *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_level_nonflat, dim3(nb(n), unsigned(nlev)), dim3(BLOCK), 0, st, a, n, out);
     return hipGetLastError();
 }
 

@@ -62,6 +62,23 @@ def test_small_ragged_and_deep_grids_bitwise(k, n_lev):
     assert np.array_equal(gf[0], of[0]) and np.array_equal(gf[1], of[1])
 
 
+@pytest.mark.parametrize("terrain,z_top", [(None, 30000.0), ([5, 1], 30000.0), ([5, 2], 12000.0),
+                                           ([5, 3], 16500.0)])
+def test_flat_top_regimes_bitwise(terrain, z_top):
+    """The kernels read a neighbour's height without a gather at the leading
+    half levels where every column has the same height.  Flat terrain (every
+    level flat), terrain below a flat top, terrain reaching the lid (no flat
+    level) and a lid just above the top of the terrain-following layer: each
+    bitwise equal to the oracle, upwind and damping options included."""
+    c = CS.make_case(3, 20, z_top=z_top, terrain_seed=terrain, noise_seed=[8, 3, 20, int(z_top)],
+                     dt=100.0)
+    c = CS.with_damping(CS.with_params(c, upwind=1))
+    gs, gf = _gpu(c, 3)
+    os_, of = _oracle(c, 3)
+    _same(gs, os_, f"terrain={terrain} z_top={z_top}")
+    assert np.array_equal(gf[0], of[0]) and np.array_equal(gf[1], of[1])
+
+
 @pytest.mark.parametrize("nsub", [1, 2, 3, 7])
 def test_substep_counts_bitwise(nsub):
     c = _case(2, 10, tag=nsub)
