@@ -60,6 +60,7 @@ struct Grid {
     // every vertex's zhv, has the same bits: there a neighbour's height is the
     // level's first entry, read without a gather
     int32_t flat_c = 0, flat_v = 0;
+    int32_t flat_r = 0;           // the same for pi_ref and theta_ref (full levels)
     double *zhv = nullptr;        // [N+1][nv] vertex average of zh
     double *pi_ref = nullptr;     // [N][nc]
     double *theta_ref = nullptr;  // [N][nc]

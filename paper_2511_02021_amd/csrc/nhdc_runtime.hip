@@ -647,17 +647,25 @@ int nhdc_upload_grid(nhdc_ctx *ctx, const nhdc_grid *g, const nhdc_vertical *v,
     HIP_TRY(ctx, launch_metrics(G, nullptr));
     {
         // the flat top of the height coordinate, level by level from the lid
+        // (rows: zh, zhv at N+1 half levels; pi_ref, theta_ref at N levels)
+        const int64_t n_rows = 2 * (int64_t(N) + 1) + 2 * int64_t(N);
         int32_t *d_nf = nullptr;
-        if ((rc = dalloc(ctx, &d_nf, 2 * (int64_t(N) + 1)))) return rc;
-        HIP_TRY(ctx, hipMemset(d_nf, 0, sizeof(int32_t) * 2 * (size_t(N) + 1)));
-        HIP_TRY(ctx, launch_level_nonflat(G.zh, nc, N + 1, d_nf, nullptr));
-        HIP_TRY(ctx, launch_level_nonflat(G.zhv, nv, N + 1, d_nf + N + 1, nullptr));
-        std::vector<int32_t> nf(2 * (size_t(N) + 1));
+        if ((rc = dalloc(ctx, &d_nf, n_rows))) return rc;
+        HIP_TRY(ctx, hipMemset(d_nf, 0, sizeof(int32_t) * size_t(n_rows)));
+        int32_t *nf_zh = d_nf, *nf_zhv = d_nf + N + 1, *nf_pr = d_nf + 2 * (N + 1), *nf_tr = nf_pr + N;
+        HIP_TRY(ctx, launch_level_nonflat(G.zh, nc, N + 1, nf_zh, nullptr));
+        HIP_TRY(ctx, launch_level_nonflat(G.zhv, nv, N + 1, nf_zhv, nullptr));
+        HIP_TRY(ctx, launch_level_nonflat(G.pi_ref, nc, N, nf_pr, nullptr));
+        HIP_TRY(ctx, launch_level_nonflat(G.theta_ref, nc, N, nf_tr, nullptr));
+        std::vector<int32_t> nf(static_cast<size_t>(n_rows));
         HIP_TRY(ctx, hipMemcpy(nf.data(), d_nf, sizeof(int32_t) * nf.size(), hipMemcpyDeviceToHost));
+        const int32_t *h_zh = nf.data(), *h_zhv = h_zh + N + 1, *h_pr = h_zhv + N + 1, *h_tr = h_pr + N;
         G.flat_c = 0;
-        while (G.flat_c <= N && nf[G.flat_c] == 0) ++G.flat_c;
+        while (G.flat_c <= N && h_zh[G.flat_c] == 0) ++G.flat_c;
         G.flat_v = 0;
-        while (G.flat_v <= N && nf[N + 1 + G.flat_v] == 0) ++G.flat_v;
+        while (G.flat_v <= N && h_zhv[G.flat_v] == 0) ++G.flat_v;
+        G.flat_r = 0;
+        while (G.flat_r < N && h_pr[G.flat_r] == 0 && h_tr[G.flat_r] == 0) ++G.flat_r;
     }
     if (ctx->precision == NHDC_MIXED) {
         Geo<float> &F = G.gf;
