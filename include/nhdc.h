@@ -150,7 +150,11 @@ int nhdc_create(nhdc_ctx **out, int precision, int device);
 
 /* Copy and validate the grid (index ranges, edge-cell consistency, signs,
  * positive lengths and areas) and the vertical coordinate; derive device
- * metrics and stencil coefficients.  May be called once per context. */
+ * metrics and stencil coefficients.  It also records how many half levels
+ * from the lid carry the same height bits in every column (the flat top of a
+ * terrain-following coordinate), and how many full levels the same reference
+ * profile; the kernels read those levels from one entry, with unchanged
+ * results.  May be called once per context. */
 int nhdc_upload_grid(nhdc_ctx *ctx, const nhdc_grid *grid, const nhdc_vertical *vert,
                      const nhdc_params *params);
 
