@@ -46,6 +46,12 @@ struct Grid {
     int32_t *v_e = nullptr;       // [6][nv] vertex ring edges (pad -> slot 0)
     int32_t *v_c = nullptr;       // [6][nv] vertex ring cells (pad -> slot 0)
     int32_t *c_ns = nullptr;      // [3][nc] slot of the shared edge in the neighbour across slot j
+    // cells shared by a block of BLOCK consecutive edges: the block's distinct
+    // cells in ascending order (padded with its first), their count, and each
+    // edge's c1 and c2 as positions in its block's list
+    int32_t *eb_cells = nullptr;  // [ceil(ne / BLOCK)][2 BLOCK]
+    int32_t *eb_n = nullptr;      // [ceil(ne / BLOCK)]
+    int32_t *e_loc = nullptr;     // [2][ne]
     Geo<double> gd;
     Geo<float> gf;
     // second-order upwind option (FP64; allocated only with the option)

@@ -3,6 +3,7 @@
 // autotuning and per-kernel timing.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -599,6 +600,34 @@ int nhdc_upload_grid(nhdc_ctx *ctx, const nhdc_grid *g, const nhdc_vertical *v,
         if ((rc = upload(ctx, &G.c_ns, c_ns.data(), 3 * nc))) return rc;
     }
     if ((rc = upload(ctx, &G.e_c, g->edge_cells, 2 * ne))) return rc;
+    {
+        // each block of BLOCK consecutive edges: its distinct cells, ascending
+        const int64_t nblk = (ne + BLOCK - 1) / BLOCK;
+        std::vector<int32_t> cells(static_cast<size_t>(nblk) * 2 * BLOCK);
+        std::vector<int32_t> cnt(static_cast<size_t>(nblk)), loc(static_cast<size_t>(2 * ne));
+        std::vector<int32_t> u;
+        u.reserve(2 * BLOCK);
+        for (int64_t b = 0; b < nblk; ++b) {
+            const int64_t e0 = b * BLOCK, e1 = std::min<int64_t>(ne, e0 + BLOCK);
+            u.clear();
+            for (int64_t e = e0; e < e1; ++e) {
+                u.push_back(g->edge_cells[e]);
+                u.push_back(g->edge_cells[ne + e]);
+            }
+            std::sort(u.begin(), u.end());
+            u.erase(std::unique(u.begin(), u.end()), u.end());
+            cnt[size_t(b)] = int32_t(u.size());
+            for (int j = 0; j < 2 * BLOCK; ++j)
+                cells[size_t(b) * 2 * BLOCK + size_t(j)] = j < int(u.size()) ? u[size_t(j)] : u[0];
+            for (int64_t e = e0; e < e1; ++e)
+                for (int s = 0; s < 2; ++s)
+                    loc[size_t(s * ne + e)] = int32_t(
+                        std::lower_bound(u.begin(), u.end(), g->edge_cells[s * ne + e]) - u.begin());
+        }
+        if ((rc = upload(ctx, &G.eb_cells, cells.data(), nblk * 2 * BLOCK))) return rc;
+        if ((rc = upload(ctx, &G.eb_n, cnt.data(), nblk))) return rc;
+        if ((rc = upload(ctx, &G.e_loc, loc.data(), 2 * ne))) return rc;
+    }
     if ((rc = upload(ctx, &G.e_v, g->edge_verts, 2 * ne))) return rc;
     if ((rc = upload(ctx, &G.v_e, v_e.data(), 6 * nv))) return rc;
     if ((rc = upload(ctx, &G.v_c, v_c.data(), 6 * nv))) return rc;
