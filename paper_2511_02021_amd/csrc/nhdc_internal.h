@@ -52,6 +52,7 @@ struct Grid {
     int32_t *eb_cells = nullptr;  // [ceil(ne / BLOCK)][2 BLOCK]
     int32_t *eb_n = nullptr;      // [ceil(ne / BLOCK)]
     int32_t *e_loc = nullptr;     // [2][ne]
+    int32_t eb_max = 0;           // the most distinct cells of any block
     Geo<double> gd;
     Geo<float> gf;
     // second-order upwind option (FP64; allocated only with the option)
@@ -192,6 +193,7 @@ struct Launcher {
     bool smag = false;             // some instance uses the Smagorinsky diffusion
     bool sponge = false;           // some instance has a Rayleigh sponge on w
     bool tracers = false;          // some instance carries tracers
+    bool vt_two = false;           // some edge block has more distinct cells than lanes
     Map maps[KIND_NUM];
     int64_t nblocks[KIND_NUM] = {0};
 };

@@ -126,8 +126,9 @@ int upload_insts(Launcher &L, const std::vector<nhdc_ctx *> &ctxs, std::string &
     if (e != hipSuccess) return hip_fail(err, e, "instance descriptors: hipMemcpy");
     L.precision = prec;
     L.n = n;
-    L.upwind = L.div4 = L.smag = L.sponge = L.tracers = false;
+    L.upwind = L.div4 = L.smag = L.sponge = L.tracers = L.vt_two = false;
     for (auto *c : ctxs) {
+        L.vt_two = L.vt_two || c->g.eb_max > BLOCK;
         L.tracers = L.tracers || c->tr.nt > 0;
         L.sponge = L.sponge || c->g.w_damp != nullptr;
         L.upwind = L.upwind || c->p.upwind != 0;
@@ -624,6 +625,7 @@ int nhdc_upload_grid(nhdc_ctx *ctx, const nhdc_grid *g, const nhdc_vertical *v,
                     loc[size_t(s * ne + e)] = int32_t(
                         std::lower_bound(u.begin(), u.end(), g->edge_cells[s * ne + e]) - u.begin());
         }
+        G.eb_max = *std::max_element(cnt.begin(), cnt.end());
         if ((rc = upload(ctx, &G.eb_cells, cells.data(), nblk * 2 * BLOCK))) return rc;
         if ((rc = upload(ctx, &G.eb_n, cnt.data(), nblk))) return rc;
         if ((rc = upload(ctx, &G.e_loc, loc.data(), 2 * ne))) return rc;
