@@ -616,6 +616,18 @@ ORDER_CMDS = {
                  f"> gpurun_out/prof_o{o}{kind}.json"
            for kind, ctr in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE"))}}
     for o in ("sfc", "canonical", "random")}
+# instruction issue and texture-addresser activity of the step kernels (FP64
+# and mixed R2B6x90 steps): two counter passes over the same short run
+ISSUE_CMDS = {
+    "issue1": "rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR SQ_INSTS_SALU "
+              "GRBM_GUI_ACTIVE --output-format csv -d gpurun_out/prof_issue1 -o issue1 -- python3 -u "
+              "bench.py --forms none --steps 2 --warmup 1 --timing-steps 1 --error-steps 0 "
+              "--no-cpu-baseline > gpurun_out/prof_issue1.json",
+    "issue2": "rocprofv3 --pmc TA_BUSY_avr SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_MUL_F64 "
+              "SQ_INSTS_VALU_FMA_F64 GRBM_GUI_ACTIVE --output-format csv -d gpurun_out/prof_issue2 "
+              "-o issue2 -- python3 -u bench.py --forms none --steps 2 --warmup 1 --timing-steps 1 "
+              "--error-steps 0 --no-cpu-baseline > gpurun_out/prof_issue2.json",
+}
 CS_TRACERS = ("one", "h2o", "o3", "co2")  # the tracer set the tracer form carries
 OPTION_KERNELS = ("div4", "smag_cell", "smag_edge", "column_pred_sponge", "column_corr_sponge",
                   "tr_save", "tr_recon", "tr_horiz", "tr_vert")
@@ -761,7 +773,60 @@ def profile_summary(src, dst):
         damped_summary(src, dst, runs, src_hash, wl, nc, ne, nv, N, rows, counter)
     config_summary(src, dst)
     order_summary(src, dst)
+    if all(os.path.exists(os.path.join(src, f"prof_{k}.json")) for k in ISSUE_CMDS):
+        issue_summary(src, dst)
     print(f"wrote summaries for kernel sources {src_hash} to {dst}")
+
+
+def issue_summary(src, dst):
+    """profiles/dycore_r2b6x90_issue_counters.txt: per step kernel, the share
+    of its cycles in which the texture addresser (the unit every vector memory
+    instruction passes) is busy, vector instructions issued per CU-cycle, and
+    the FP64 operations, from the two ISSUE_CMDS passes.  A kernel's cycles are
+    GRBM_GUI_ACTIVE over the 8 XCDs, whose counts it sums; the chip has 256
+    CUs, each issuing at most one wave-wide vector instruction per cycle."""
+    import csv
+    from collections import defaultdict
+    acc = defaultdict(lambda: defaultdict(list))
+    meta = {}
+    for k in ISSUE_CMDS:
+        meta[k] = json.loads(open(os.path.join(src, f"prof_{k}.json")).read().strip().splitlines()[-1])
+        f = os.path.join(src, f"prof_{k}", f"{k}_counter_collection.csv")
+        for r in csv.DictReader(open(f)):
+            kid, prec = _kernel_id(r["Kernel_Name"])
+            if kid is None:
+                continue
+            acc[(kid, prec)][r["Counter_Name"] + "@" + k].append(float(r["Counter_Value"]))
+    src_hash = meta["issue1"].get("kernel_source_sha256_16")
+    wl = meta["issue1"]["config"]["workload"]
+    lines = [f"# rocprofv3 issue counters: dycore substep kernels, {wl}",
+             f"kernel_source_sha256_16: {src_hash}",
+             f"numbering: {meta['issue1']['config'].get('numbering')}"]
+    lines += [f"command ({k}): {ISSUE_CMDS[k]}" for k in ISSUE_CMDS]
+    lines += ["summarised by: python3 bench.py --profile-summary gpurun_out",
+              "cycles = GRBM_GUI_ACTIVE / 8 (the counter sums the 8 XCDs); TA busy = TA_BUSY_avr / "
+              "cycles; VALU/CU-cycle = SQ_INSTS_VALU / (256 x cycles); VMEM/CU-cycle likewise for "
+              "SQ_INSTS_VMEM_RD + SQ_INSTS_VMEM_WR; counts are per dispatch", "",
+              f"{'kernel':20s} {'form':5s} {'n':>3s} {'cycles':>9s} {'TA_busy':>8s} {'VALU/CUc':>9s} "
+              f"{'VMEM/CUc':>9s} {'VMEM_RD':>10s} {'VMEM_WR':>10s} {'F64_ADD':>10s} {'F64_MUL':>10s} "
+              f"{'F64_FMA':>10s}"]
+    def avg(d, name):
+        v = d.get(name)
+        return sum(v) / len(v) if v else float("nan")
+    for (kid, prec) in sorted(acc, key=lambda x: (x[1], x[0])):
+        d = acc[(kid, prec)]
+        cyc1 = avg(d, "GRBM_GUI_ACTIVE@issue1") / 8.0
+        cyc2 = avg(d, "GRBM_GUI_ACTIVE@issue2") / 8.0
+        n = len(d.get("GRBM_GUI_ACTIVE@issue1", []))
+        ta = avg(d, "TA_BUSY_avr@issue2") / cyc2
+        valu = avg(d, "SQ_INSTS_VALU@issue1") / (256.0 * cyc1)
+        vmem = (avg(d, "SQ_INSTS_VMEM_RD@issue1") + avg(d, "SQ_INSTS_VMEM_WR@issue1")) / (256.0 * cyc1)
+        lines.append(f"{kid:20s} {prec:5s} {n:3d} {cyc1:9.0f} {100 * ta:7.1f}% {100 * valu:8.1f}% "
+                     f"{100 * vmem:8.2f}% {avg(d, 'SQ_INSTS_VMEM_RD@issue1'):10.3e} "
+                     f"{avg(d, 'SQ_INSTS_VMEM_WR@issue1'):10.3e} {avg(d, 'SQ_INSTS_VALU_ADD_F64@issue2'):10.3e} "
+                     f"{avg(d, 'SQ_INSTS_VALU_MUL_F64@issue2'):10.3e} {avg(d, 'SQ_INSTS_VALU_FMA_F64@issue2'):10.3e}")
+    with open(os.path.join(dst, "dycore_r2b6x90_issue_counters.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
 
 
 def order_summary(src, dst):
