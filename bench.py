@@ -627,6 +627,10 @@ ISSUE_CMDS = {
               "SQ_INSTS_VALU_FMA_F64 GRBM_GUI_ACTIVE --output-format csv -d gpurun_out/prof_issue2 "
               "-o issue2 -- python3 -u bench.py --forms none --steps 2 --warmup 1 --timing-steps 1 "
               "--error-steps 0 --no-cpu-baseline > gpurun_out/prof_issue2.json",
+    # L2 read requests to the fabric, and those of less than a full line
+    "issue3": "rocprofv3 --pmc TCC_EA0_RDREQ_sum TCC_EA0_RDREQ_32B_sum TCC_BUBBLE_sum --output-format csv "
+              "-d gpurun_out/prof_issue3 -o issue3 -- python3 -u bench.py --forms none --steps 2 "
+              "--warmup 1 --timing-steps 1 --error-steps 0 --no-cpu-baseline > gpurun_out/prof_issue3.json",
 }
 CS_TRACERS = ("one", "h2o", "o3", "co2")  # the tracer set the tracer form carries
 OPTION_KERNELS = ("div4", "smag_cell", "smag_edge", "column_pred_sponge", "column_corr_sponge",
@@ -806,10 +810,11 @@ def issue_summary(src, dst):
     lines += ["summarised by: python3 bench.py --profile-summary gpurun_out",
               "cycles = GRBM_GUI_ACTIVE / 8 (the counter sums the 8 XCDs); TA busy = TA_BUSY_avr / "
               "cycles; VALU/CU-cycle = SQ_INSTS_VALU / (256 x cycles); VMEM/CU-cycle likewise for "
-              "SQ_INSTS_VMEM_RD + SQ_INSTS_VMEM_WR; counts are per dispatch", "",
+              "SQ_INSTS_VMEM_RD + SQ_INSTS_VMEM_WR; L2_RDREQ = TCC_EA0_RDREQ_sum, of which RDREQ_32B "
+              "(32-byte requests) and BUBBLE (TCC_BUBBLE_sum); counts are per dispatch", "",
               f"{'kernel':20s} {'form':5s} {'n':>3s} {'cycles':>9s} {'TA_busy':>8s} {'VALU/CUc':>9s} "
               f"{'VMEM/CUc':>9s} {'VMEM_RD':>10s} {'VMEM_WR':>10s} {'F64_ADD':>10s} {'F64_MUL':>10s} "
-              f"{'F64_FMA':>10s}"]
+              f"{'F64_FMA':>10s} {'L2_RDREQ':>10s} {'RDREQ_32B':>10s} {'BUBBLE':>8s}"]
     def avg(d, name):
         v = d.get(name)
         return sum(v) / len(v) if v else float("nan")
@@ -824,7 +829,9 @@ def issue_summary(src, dst):
         lines.append(f"{kid:20s} {prec:5s} {n:3d} {cyc1:9.0f} {100 * ta:7.1f}% {100 * valu:8.1f}% "
                      f"{100 * vmem:8.2f}% {avg(d, 'SQ_INSTS_VMEM_RD@issue1'):10.3e} "
                      f"{avg(d, 'SQ_INSTS_VMEM_WR@issue1'):10.3e} {avg(d, 'SQ_INSTS_VALU_ADD_F64@issue2'):10.3e} "
-                     f"{avg(d, 'SQ_INSTS_VALU_MUL_F64@issue2'):10.3e} {avg(d, 'SQ_INSTS_VALU_FMA_F64@issue2'):10.3e}")
+                     f"{avg(d, 'SQ_INSTS_VALU_MUL_F64@issue2'):10.3e} {avg(d, 'SQ_INSTS_VALU_FMA_F64@issue2'):10.3e} "
+                     f"{avg(d, 'TCC_EA0_RDREQ_sum@issue3'):10.3e} {avg(d, 'TCC_EA0_RDREQ_32B_sum@issue3'):10.3e} "
+                     f"{avg(d, 'TCC_BUBBLE_sum@issue3'):8.0f}")
     with open(os.path.join(dst, "dycore_r2b6x90_issue_counters.txt"), "w") as f:
         f.write("\n".join(lines) + "\n")
 
