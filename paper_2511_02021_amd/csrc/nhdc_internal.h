@@ -10,7 +10,11 @@
 
 namespace nhdc {
 
-constexpr int BLOCK = 256;      // lanes per workgroup (4 wavefronts)
+constexpr int BLOCK = 256;
+// cell_vt's per-block tables: at most this many distinct edges, vertices and
+// outside neighbours per block of BLOCK cells (a block of the bisection-curve
+// numbering is one subtree of 256 triangles: 408, 153 and 48)
+constexpr int CVT_E = 416, CVT_V = 160, CVT_X = 64;      // lanes per workgroup (4 wavefronts)
 constexpr int MAX_INST = NHDC_MAX_INST;  // instances of one batched launch
 
 // Stencil coefficients in one precision.  The FP64 form reads the double
@@ -53,6 +57,15 @@ struct Grid {
     int32_t *eb_n = nullptr;      // [ceil(ne / BLOCK)]
     int32_t *e_loc = nullptr;     // [2][ne]
     int32_t eb_max = 0;           // the most distinct cells of any block
+    // the same for blocks of BLOCK consecutive cells (cell_vt), when every
+    // block fits the CVT_* sizes (cvt_ok): distinct edges, vertices and
+    // neighbours outside the block (ascending, padded with the first), their
+    // three counts per block [3][nblk], and each cell's slots as positions:
+    // edges and vertices in the block's lists, neighbours as the cell's
+    // position in the block or BLOCK + position in the outside list
+    int32_t cvt_ok = 0;
+    int32_t *cb_e = nullptr, *cb_v = nullptr, *cb_x = nullptr, *cb_n = nullptr;
+    int32_t *c_el = nullptr, *c_vl = nullptr, *c_nl = nullptr;  // [3][nc]
     Geo<double> gd;
     Geo<float> gf;
     // second-order upwind option (FP64; allocated only with the option)
@@ -194,6 +207,7 @@ struct Launcher {
     bool sponge = false;           // some instance has a Rayleigh sponge on w
     bool tracers = false;          // some instance carries tracers
     bool vt_two = false;           // some edge block has more distinct cells than lanes
+    bool cvt_lds = false;          // every instance has cell_vt's block tables
     Map maps[KIND_NUM];
     int64_t nblocks[KIND_NUM] = {0};
 };

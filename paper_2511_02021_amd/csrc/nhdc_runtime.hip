@@ -127,7 +127,9 @@ int upload_insts(Launcher &L, const std::vector<nhdc_ctx *> &ctxs, std::string &
     L.precision = prec;
     L.n = n;
     L.upwind = L.div4 = L.smag = L.sponge = L.tracers = L.vt_two = false;
+    L.cvt_lds = true;
     for (auto *c : ctxs) {
+        L.cvt_lds = L.cvt_lds && c->g.cvt_ok != 0;
         L.vt_two = L.vt_two || c->g.eb_max > BLOCK;
         L.tracers = L.tracers || c->tr.nt > 0;
         L.sponge = L.sponge || c->g.w_damp != nullptr;
@@ -587,6 +589,65 @@ int nhdc_upload_grid(nhdc_ctx *ctx, const nhdc_grid *g, const nhdc_vertical *v,
     if ((rc = upload(ctx, &G.c_e, g->cell_edges, 3 * nc))) return rc;
     if ((rc = upload(ctx, &G.c_n, c_n.data(), 3 * nc))) return rc;
     if ((rc = upload(ctx, &G.c_v, c_v.data(), 3 * nc))) return rc;
+    {
+        // each block of BLOCK consecutive cells: its distinct edges and
+        // vertices and the neighbours outside it, ascending, if they fit
+        const int64_t nblk = (nc + BLOCK - 1) / BLOCK;
+        std::vector<int32_t> be(static_cast<size_t>(nblk) * CVT_E), bv(static_cast<size_t>(nblk) * CVT_V);
+        std::vector<int32_t> bx(static_cast<size_t>(nblk) * CVT_X), bn(static_cast<size_t>(3 * nblk));
+        std::vector<int32_t> el(static_cast<size_t>(3 * nc)), vl(static_cast<size_t>(3 * nc));
+        std::vector<int32_t> nl(static_cast<size_t>(3 * nc));
+        std::vector<int32_t> ue, uv, ux;
+        bool fits = true;
+        for (int64_t b = 0; b < nblk && fits; ++b) {
+            const int64_t c0 = b * BLOCK, c1 = std::min<int64_t>(nc, c0 + BLOCK);
+            ue.clear();
+            uv.clear();
+            ux.clear();
+            for (int64_t c = c0; c < c1; ++c)
+                for (int j = 0; j < 3; ++j) {
+                    ue.push_back(g->cell_edges[j * nc + c]);
+                    uv.push_back(c_v[size_t(j * nc + c)]);
+                    const int32_t x = c_n[size_t(j * nc + c)];
+                    if (x < c0 || x >= c1) ux.push_back(x);
+                }
+            for (auto *u : {&ue, &uv, &ux}) {
+                std::sort(u->begin(), u->end());
+                u->erase(std::unique(u->begin(), u->end()), u->end());
+            }
+            if (ue.size() > size_t(CVT_E) || uv.size() > size_t(CVT_V) || ux.size() > size_t(CVT_X)) {
+                fits = false;
+                break;
+            }
+            bn[size_t(b)] = int32_t(ue.size());
+            bn[size_t(nblk + b)] = int32_t(uv.size());
+            bn[size_t(2 * nblk + b)] = int32_t(ux.size());
+            for (int j = 0; j < CVT_E; ++j) be[size_t(b * CVT_E + j)] = j < int(ue.size()) ? ue[size_t(j)] : ue[0];
+            for (int j = 0; j < CVT_V; ++j) bv[size_t(b * CVT_V + j)] = j < int(uv.size()) ? uv[size_t(j)] : uv[0];
+            for (int j = 0; j < CVT_X; ++j)
+                bx[size_t(b * CVT_X + j)] = j < int(ux.size()) ? ux[size_t(j)] : (ux.empty() ? int32_t(c0) : ux[0]);
+            for (int64_t c = c0; c < c1; ++c)
+                for (int j = 0; j < 3; ++j) {
+                    const size_t s = size_t(j * nc + c);
+                    el[s] = int32_t(std::lower_bound(ue.begin(), ue.end(), g->cell_edges[s]) - ue.begin());
+                    vl[s] = int32_t(std::lower_bound(uv.begin(), uv.end(), c_v[s]) - uv.begin());
+                    const int32_t x = c_n[s];
+                    nl[s] = (x >= c0 && x < c1)
+                                ? int32_t(x - c0)
+                                : int32_t(BLOCK + (std::lower_bound(ux.begin(), ux.end(), x) - ux.begin()));
+                }
+        }
+        G.cvt_ok = fits ? 1 : 0;
+        if (fits) {
+            if ((rc = upload(ctx, &G.cb_e, be.data(), nblk * CVT_E))) return rc;
+            if ((rc = upload(ctx, &G.cb_v, bv.data(), nblk * CVT_V))) return rc;
+            if ((rc = upload(ctx, &G.cb_x, bx.data(), nblk * CVT_X))) return rc;
+            if ((rc = upload(ctx, &G.cb_n, bn.data(), 3 * nblk))) return rc;
+            if ((rc = upload(ctx, &G.c_el, el.data(), 3 * nc))) return rc;
+            if ((rc = upload(ctx, &G.c_vl, vl.data(), 3 * nc))) return rc;
+            if ((rc = upload(ctx, &G.c_nl, nl.data(), 3 * nc))) return rc;
+        }
+    }
     {
         // the slot of each shared edge in the neighbour across it
         std::vector<int32_t> c_ns(3 * nc);
