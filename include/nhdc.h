@@ -154,7 +154,9 @@ int nhdc_create(nhdc_ctx **out, int precision, int device);
  * from the lid carry the same height bits in every column (the flat top of a
  * terrain-following coordinate), and how many full levels the same reference
  * profile; the kernels read those levels from one entry, with unchanged
- * results.  May be called once per context. */
+ * results.  It lists, per block of 256 edges and per block of 256 cells, the
+ * distinct cells (edges, vertices, outside neighbours) the block's lanes share
+ * through LDS.  May be called once per context. */
 int nhdc_upload_grid(nhdc_ctx *ctx, const nhdc_grid *grid, const nhdc_vertical *vert,
                      const nhdc_params *params);
 
