@@ -63,7 +63,8 @@ enum {
     NHDC_EHIP = -3,      /* a HIP runtime call failed (message has hipGetErrorString) */
     NHDC_EGRID = -4,     /* grid or vertical coordinate failed validation */
     NHDC_ESTATE = -5,    /* call out of order (e.g. step before init) */
-    NHDC_EUNSTABLE = -6  /* non-finite value found by nhdc_check_finite */
+    NHDC_EUNSTABLE = -6, /* non-finite value found by nhdc_check_finite */
+    NHDC_ETOOBIG = -7    /* input larger than a fixed maximum (nhdc_diag_noalloc) */
 };
 
 enum { NHDC_FP64 = 0, NHDC_MIXED = 1 };
@@ -276,6 +277,34 @@ int nhdc_kernel_count(void);
 int nhdc_kernel_stats(const nhdc_ctx *ctx, int index, const char **name, double *total_ms,
                       int64_t *launches);
 
+/* ---- allocation-free entry point ------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * global sums as nhdc_diag (dry mass sum A_c dz rho and sum A_c dz rho theta_v,
+ * with the same fixed-order two-level reduction, so bitwise equal to it), over
+ * caller-held device arrays, with no context and no allocation:
+ *   cell_area [n_cells], zh [n_lev+1][n_cells] (half-level heights),
+ *   rho, theta_v [n_lev][n_cells]: device memory, read only;
+ *   out [2]: device memory, receives {mass, rho_theta}.
+ * Asynchronous: the work is enqueued on `stream` (of the current device) and
+ * out holds the sums once the stream reaches it; no synchronisation, host
+ * copy, memset or allocation happens, so the call can be captured in a graph.
+ * The per-block partials live in a fixed device array of the library
+ * (2 doubles per 256 cells, NHDC_NOALLOC_MAX_CELLS cells at most: 1 MiB),
+ * one per GPU, held until the process ends and shared by every call on that
+ * GPU: calls that overlap on one GPU (different streams or threads) race;
+ * calls ordered on one stream do not.  Every partial is written by the call
+ * before it is read, so nothing carries over between calls.
+ * Errors: NHDC_EINVAL for a NULL array, n_cells < 1 or n_lev outside
+ * 1..NHDC_MAX_LEV; NHDC_ETOOBIG for n_cells > NHDC_NOALLOC_MAX_CELLS; NHDC_EHIP
+ * when the launch fails.  nhdc_last_error(NULL) gives the calling thread's
+ * message of the last failed call. */
+#define NHDC_NOALLOC_MAX_CELLS (65536LL * 256)
+int nhdc_diag_noalloc(int64_t n_cells, int32_t n_lev, const double *cell_area, const double *zh,
+                      const double *rho, const double *theta_v, double *out, void *stream);
+
+/* Message of the context's last failure; with ctx NULL, the calling thread's
+ * last failure of a context-free call (nhdc_diag_noalloc). */
 const char *nhdc_last_error(const nhdc_ctx *ctx);
 void nhdc_destroy(nhdc_ctx *ctx);
 

@@ -230,6 +230,8 @@ hipError_t launch_level_nonflat(const double *a, int64_t n, int nlev, int32_t *o
 hipError_t launch_to_float(const double *src, float *dst, int64_t n, hipStream_t st);
 hipError_t launch_diag(const Grid &g, const State &s, double *part, double *out2, hipStream_t st);
 hipError_t launch_finite(const Grid &g, const State &s, int *flag, hipStream_t st);
+// message of the calling thread's last failed context-free call
+const char *context_free_error();
 hipError_t launch_init_prev(const Grid &g, const State &s, hipStream_t st);
 hipError_t launch_exner_x(const Grid &g, const State &s, double eps, hipStream_t st);
 // timing helpers (nhdc_runtime.hip); no-ops when tm is null or off

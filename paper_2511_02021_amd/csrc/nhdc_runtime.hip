@@ -955,7 +955,7 @@ int nhdc_kernel_stats(const nhdc_ctx *ctx, int index, const char **name, double 
     return NHDC_OK;
 }
 
-const char *nhdc_last_error(const nhdc_ctx *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+const char *nhdc_last_error(const nhdc_ctx *ctx) { return ctx ? ctx->err.c_str() : context_free_error(); }
 
 int nhdc_set_tracers(nhdc_ctx *ctx, int n_tracers, const double *q, int on_device, void *stream) {
     if (!ctx) return NHDC_EINVAL;

@@ -5,6 +5,9 @@
 // definitions.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+#include <string>
+
 #include "nhdc_internal.h"
 
 #pragma clang fp contract(off)
@@ -166,6 +169,37 @@ hipError_t launch_finite(const Grid &g, const State &s, int *flag, hipStream_t s
     return hipGetLastError();
 }
 
+// ---- the allocation-free mass sums (nhdc_diag_noalloc) ----
+// The per-block partials live in a fixed device array of this file, one copy
+// per GPU for the life of the process.  Host code never passes the array's
+// name to a kernel: it looks up the array's device address once per device
+// and passes that.
+constexpr int64_t NOALLOC_PARTS = (NHDC_NOALLOC_MAX_CELLS + BLOCK - 1) / BLOCK;
+static __device__ __align__(256) double scratch[2 * NOALLOC_PARTS];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+double *scratch_ptr[MAX_DEVICES] = {};
+thread_local std::string free_err;  // message of the last failed context-free call
+}  // namespace
+
+const char *context_free_error() { return free_err.empty() ? "no context" : free_err.c_str(); }
+
+// The device address of this device's scratch array, looked up on the first
+// call on each device (with that device current).
+static hipError_t device_scratch(int dev, double **out) {
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *out = scratch_ptr[dev];
+    return hipSuccess;
+}
+
 const char *const kKernelNames[K_NUM] = {"vt_edge",   "vertex",      "cell_vt",
                                          "edge_pred", "column_pred", "edge_corr",
                                          "column_corr", "cell_grad", "div4",
@@ -192,3 +226,44 @@ void build_map(Map &m, int64_t &nblocks, Kind kind, const Grid *const *grids, in
 }
 
 }  // namespace nhdc
+
+extern "C" int nhdc_diag_noalloc(int64_t n_cells, int32_t n_lev, const double *cell_area,
+                                 const double *zh, const double *rho, const double *theta_v,
+                                 double *out, void *stream) {
+    using namespace nhdc;
+    if (!cell_area || !zh || !rho || !theta_v || !out) {
+        free_err = "diag_noalloc: NULL array";
+        return NHDC_EINVAL;
+    }
+    if (n_cells < 1 || n_lev < 1 || n_lev > NHDC_MAX_LEV) {
+        free_err = "diag_noalloc: n_cells must be >= 1 and n_lev in 1.." + std::to_string(NHDC_MAX_LEV);
+        return NHDC_EINVAL;
+    }
+    if (n_cells > NHDC_NOALLOC_MAX_CELLS) {
+        free_err = "diag_noalloc: " + std::to_string(n_cells) + " cells exceed the static scratch of " +
+                   std::to_string(int64_t(NHDC_NOALLOC_MAX_CELLS)) + " cells";
+        return NHDC_ETOOBIG;
+    }
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess && (dev < 0 || dev >= MAX_DEVICES)) e = hipErrorInvalidDevice;
+    double *part = nullptr;
+    if (e == hipSuccess) e = device_scratch(dev, &part);
+    if (e != hipSuccess) {
+        free_err = std::string("diag_noalloc: scratch address: ") + hipGetErrorString(e);
+        return NHDC_EHIP;
+    }
+    // every partial the final pass reads is written first by this call, so
+    // nothing needs clearing; the kernels are those of nhdc_diag
+    const unsigned n = nb(n_cells);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_diag_partial, dim3(n), dim3(BLOCK), 0, st, int64_t(n_cells), int(n_lev),
+                       cell_area, zh, rho, theta_v, part);
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(BLOCK), 0, st, int(n), part, out);
+    e = hipGetLastError();
+    if (e != hipSuccess) {
+        free_err = std::string("diag_noalloc: launch: ") + hipGetErrorString(e);
+        return NHDC_EHIP;
+    }
+    return NHDC_OK;
+}

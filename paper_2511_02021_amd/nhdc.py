@@ -15,7 +15,9 @@ from . import _build
 NHDC_FP64, NHDC_MIXED = 0, 1
 MAX_INST = 64  # NHDC_MAX_INST: instances of one batch
 PRECISIONS = {"fp64": NHDC_FP64, "mixed": NHDC_MIXED}
-ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EGRID", -5: "ESTATE", -6: "EUNSTABLE"}
+ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EGRID", -5: "ESTATE", -6: "EUNSTABLE",
+          -7: "ETOOBIG"}
+NOALLOC_MAX_CELLS = 65536 * 256  # NHDC_NOALLOC_MAX_CELLS
 
 EXPORTS = ("nhdc_create", "nhdc_upload_grid", "nhdc_init_state", "nhdc_step", "nhdc_get_state",
            "nhdc_get_mass_flux", "nhdc_diag", "nhdc_check_finite", "nhdc_sizes",
@@ -23,7 +25,7 @@ EXPORTS = ("nhdc_create", "nhdc_upload_grid", "nhdc_init_state", "nhdc_step", "n
            "nhdc_kernel_stats", "nhdc_last_error", "nhdc_destroy", "nhdc_batch_create",
            "nhdc_batch_step", "nhdc_batch_set_tiles", "nhdc_batch_autotune",
            "nhdc_batch_last_error", "nhdc_batch_destroy", "nhdc_set_tracers", "nhdc_get_tracers",
-           "nhdc_n_tracers")
+           "nhdc_n_tracers", "nhdc_diag_noalloc")
 
 
 class NhdcError(RuntimeError):
@@ -103,6 +105,7 @@ def lib():
         L.nhdc_kernel_count.argtypes = []
         L.nhdc_kernel_stats.argtypes = [vp, i, C.POINTER(C.c_char_p), C.POINTER(d),
                                         C.POINTER(C.c_int64)]
+        L.nhdc_diag_noalloc.argtypes = [C.c_int64, C.c_int32] + [vp] * 6
         L.nhdc_last_error.argtypes = [vp]
         L.nhdc_last_error.restype = C.c_char_p
         L.nhdc_destroy.argtypes = [vp]
@@ -293,6 +296,24 @@ class Dycore:
             self._check(self.L.nhdc_kernel_stats(self.h, k, C.byref(name), C.byref(ms), C.byref(n)))
             out[name.value.decode()] = (ms.value, n.value)
         return out
+
+
+def diag_noalloc(cell_area, zh, rho, theta_v, out, stream=None):
+    """nhdc_diag_noalloc: the global sums (mass, rho*theta_v) of caller-held
+    device tensors (float64, contiguous; zh [N+1][nc], rho and theta_v
+    [N][nc]) into the device tensor out[2], enqueued on the stream; the
+    library allocates nothing."""
+    L = lib()
+    nc = int(cell_area.numel())
+    n_lev = int(rho.shape[0]) if rho.dim() == 2 else 0
+    for t in (cell_area, zh, rho, theta_v, out):
+        assert t.is_cuda and t.dtype.is_floating_point and t.element_size() == 8 and t.is_contiguous()
+    assert tuple(zh.shape) == (n_lev + 1, nc) and tuple(theta_v.shape) == tuple(rho.shape)
+    assert tuple(rho.shape) == (n_lev, nc) and out.numel() >= 2
+    rc = L.nhdc_diag_noalloc(nc, n_lev, *[C.c_void_p(t.data_ptr()) for t in
+                                          (cell_area, zh, rho, theta_v, out)], _stream_ptr(stream))
+    if rc != 0:
+        raise NhdcError(rc, L.nhdc_last_error(None).decode())
 
 
 class Batch:

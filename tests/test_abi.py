@@ -64,3 +64,17 @@ def test_argument_errors_without_device():
     assert L.nhdc_create(C.byref(h), 7, 0) == -1
     assert L.nhdc_step(None, 1.0, 1, None) == -1
     assert L.nhdc_last_error(None) == b"no context"
+
+
+def test_noalloc_argument_errors_without_device():
+    """The allocation-free entry point refuses NULL arrays, bad sizes and
+    inputs beyond its fixed scratch before any device call."""
+    L = nhdc.lib()
+    fake = C.c_void_p(0x1000)  # never dereferenced: the checks come first
+    assert L.nhdc_diag_noalloc(10, 5, None, fake, fake, fake, fake, None) == -1
+    assert b"NULL" in L.nhdc_last_error(None)
+    assert L.nhdc_diag_noalloc(0, 5, fake, fake, fake, fake, fake, None) == -1
+    assert L.nhdc_diag_noalloc(10, 0, fake, fake, fake, fake, fake, None) == -1
+    assert L.nhdc_diag_noalloc(10, 257, fake, fake, fake, fake, fake, None) == -1
+    assert L.nhdc_diag_noalloc(nhdc.NOALLOC_MAX_CELLS + 1, 5, fake, fake, fake, fake, fake, None) == -7
+    assert b"exceed the static scratch" in L.nhdc_last_error(None)
