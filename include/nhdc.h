@@ -50,6 +50,7 @@
  */
 #ifndef NHDC_H
 #define NHDC_H
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -145,11 +146,36 @@ typedef struct nhdc_state_view {
 } nhdc_state_view;
 
 /* Create a context on HIP device `device` with precision NHDC_FP64 (every
- * operation in FP64) or NHDC_MIXED (horizontal stencils and tendencies in
- * FP32; vertical solve, reference-state perturbations and mass fluxes FP64). */
+ * operation in FP64, the precision the paper's memory accounting assumes,
+ * Sec. 1) or NHDC_MIXED (horizontal stencils and tendencies in FP32; vertical
+ * solve, reference-state perturbations and mass fluxes FP64; the paper has no
+ * reduced-precision form).  No device memory is taken yet.
+ * Errors: EINVAL for out NULL or an unknown precision, EHIP for a device that
+ * does not exist, ENOMEM when the host context cannot be made. */
 int nhdc_create(nhdc_ctx **out, int precision, int device);
 
-/* Copy and validate the grid (index ranges, edge-cell consistency, signs,
+/* Device memory source of the context (the paper keeps the model's data
+ * resident on the GPU for the whole run, Sec. 3.1, so a caller that manages
+ * device memory itself, e.g. PyTorch's caching allocator, can own it).  Every
+ * device allocation the context makes from here on (grid, state, work
+ * arrays, tracers, its launch descriptors, autotuning snapshots; also the
+ * descriptors of a batch whose first instance it is) calls
+ * alloc(bytes, user), which returns device memory of the context's device
+ * (NULL on failure: the calling entry point then returns ENOMEM), and every
+ * release calls free_(ptr, user) after the device has finished all work.
+ * The callbacks and `user` must stay valid until nhdc_destroy has returned.
+ * Both NULL restores hipMalloc / hipFree (the default).  Must be called
+ * before nhdc_upload_grid (ESTATE afterwards); EINVAL if only one callback
+ * is given. */
+int nhdc_set_allocator(nhdc_ctx *ctx, void *(*alloc)(size_t bytes, void *user),
+                       void (*free_)(void *ptr, void *user), void *user);
+
+/* The grid upload of the problem statement: the icosahedral-triangular C
+ * grid with its dual (Sec. 2; triangles, their hexagon/pentagon dual and the
+ * integer index lookups between them, Sec. 3.2), the terrain-following
+ * height coordinate (Sec. 2) and the reference profile.  Host arrays, copied;
+ * the caller keeps ownership.
+ * Copy and validate the grid (index ranges, edge-cell consistency, signs,
  * positive lengths and areas) and the vertical coordinate; derive device
  * metrics and stencil coefficients.  It also records how many half levels
  * from the lid carry the same height bits in every column (the flat top of a
@@ -161,10 +187,18 @@ int nhdc_create(nhdc_ctx **out, int precision, int device);
 int nhdc_upload_grid(nhdc_ctx *ctx, const nhdc_grid *grid, const nhdc_vertical *vert,
                      const nhdc_params *params);
 
-/* Copy the initial state (host or device memory); zeroes the flux accumulators. */
+/* State initialisation (the paper starts from an interpolated initial
+ * state, Sec. 4.1; here any state the caller gives).  Copy the initial state
+ * (host or device memory per state->on_device; the caller keeps ownership);
+ * zeroes the flux accumulators.  The state then stays resident on the device
+ * between steps (Sec. 3.1).  Errors: EINVAL for a NULL field, ESTATE before
+ * nhdc_upload_grid, EHIP when a copy fails.  Host copies are complete when
+ * it returns; device copies are ordered on `stream`. */
 int nhdc_init_state(nhdc_ctx *ctx, const nhdc_state_view *state, void *stream);
 
-/* Enqueue nsubsteps substeps of dt/nsubsteps.  The mass-flux accumulators are
+/* step(dt, nsubsteps) of the problem statement: the nonhydrostatic
+ * dynamical core (Sec. 2) on the device, memory-bandwidth bound (Sec. 3.2).
+ * Enqueue nsubsteps substeps of dt/nsubsteps.  The mass-flux accumulators are
  * restarted at entry and hold the average over these substeps afterwards.
  * With the options set, the step also runs the diffusion of vn over dt after
  * the substeps, and then the tracer transport with the averaged fluxes.
@@ -173,7 +207,10 @@ int nhdc_init_state(nhdc_ctx *ctx, const nhdc_state_view *state, void *stream);
 int nhdc_step(nhdc_ctx *ctx, double dt, int nsubsteps, void *stream);
 
 /* Copy the state into caller buffers (host or device per dst->on_device;
- * NULL members are skipped).  Host copies are complete when this returns. */
+ * NULL members are skipped; the caller owns them).  Host copies are complete
+ * when this returns.  The layout is that of nhdc_state_view.  Errors: EINVAL
+ * for dst NULL, ESTATE before a state is initialised, EHIP when a copy
+ * fails. */
 int nhdc_get_state(nhdc_ctx *ctx, const nhdc_state_view *dst, void *stream);
 
 /* Tracers (option), up to NHDC_MAX_TRACERS mixing ratios q [n][N][n_cells]
@@ -203,14 +240,19 @@ int nhdc_get_tracers(nhdc_ctx *ctx, double *q, int on_device, void *stream);
 /* Number of tracers of the context. */
 int nhdc_n_tracers(const nhdc_ctx *ctx);
 
-/* Substep-averaged FP64 mass fluxes of the last step: edge fluxes
- * rho*vn*dz [N][n_edges] (kg/m/s per unit edge length and layer) and
- * vertical fluxes at half levels [N+1][n_cells] (kg/m^2/s). */
+/* Substep-averaged FP64 mass fluxes of the last step, which transport the
+ * atmosphere's tracers (water vapour, carbon dioxide and ozone, Sec. 1):
+ * edge fluxes rho*vn*dz [N][n_edges] (kg/m/s per unit edge length and layer)
+ * and vertical fluxes at half levels [N+1][n_cells] (kg/m^2/s), into caller
+ * buffers (host or device per on_device; NULL skips one).  Errors: ESTATE
+ * before a state is initialised, EHIP when a copy fails. */
 int nhdc_get_mass_flux(nhdc_ctx *ctx, double *facc, double *wacc, int on_device, void *stream);
 
 /* Global dry mass sum A_c dz rho and sum A_c dz rho theta_v, computed on the
  * device with a fixed-order two-level reduction (bitwise reproducible);
- * synchronous. */
+ * synchronous.  The flux form keeps both constant to round-off (the
+ * conservation invariants of the substep; the paper states none).  Either
+ * output may be NULL.  Errors: ESTATE before a state is initialised, EHIP. */
 int nhdc_diag(nhdc_ctx *ctx, double *mass, double *rho_theta, void *stream);
 
 /* NHDC_EUNSTABLE if any prognostic value is NaN or Inf, else NHDC_OK; synchronous. */

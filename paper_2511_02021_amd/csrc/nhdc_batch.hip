@@ -90,7 +90,8 @@ int nhdc_batch_create(nhdc_batch **out, nhdc_ctx *const *inst, int n) {
     *out = nullptr;
     if (!inst || n < 1 || n > MAX_INST) return NHDC_EINVAL;
     for (int i = 0; i < n; ++i) {
-        if (!inst[i] || !inst[i]->grid_ready || !inst[i]->state_ready) return NHDC_ESTATE;
+        if (!inst[i] || !inst[i]->grid_ready || !inst[i]->state_ready || inst[i]->destroy_pending)
+            return NHDC_ESTATE;
         if (inst[i]->device != inst[0]->device || inst[i]->precision != inst[0]->precision)
             return NHDC_EINVAL;
         for (int j = 0; j < i; ++j)
@@ -100,6 +101,7 @@ int nhdc_batch_create(nhdc_batch **out, nhdc_ctx *const *inst, int n) {
     if (!b) return NHDC_ENOMEM;
     b->device = inst[0]->device;
     b->ctxs.assign(inst, inst + n);
+    b->L.al = inst[0]->al;  // the batch's descriptors come from its first instance's allocator
     if (hipSetDevice(b->device) != hipSuccess ||
         hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
         delete b;
@@ -158,11 +160,15 @@ const char *nhdc_batch_last_error(const nhdc_batch *b) { return b ? b->err.c_str
 void nhdc_batch_destroy(nhdc_batch *b) {
     if (!b) return;
     if (hipSetDevice(b->device) == hipSuccess) {
+        (void)hipDeviceSynchronize();  // replays still in flight read the descriptors
         drop_graph(b);
-        if (b->L.d_insts) (void)hipFree(b->L.d_insts);
+        dev_free(b->L.al, b->L.d_insts);
         if (b->cap) (void)hipStreamDestroy(b->cap);
     }
-    for (auto *c : b->ctxs) --c->in_batches;
+    for (auto *c : b->ctxs) {
+        --c->in_batches;
+        if (c->in_batches == 0 && c->destroy_pending) free_context(c);
+    }
     delete b;
 }
 

@@ -196,8 +196,20 @@ struct Timing {
     int64_t launches[K_NUM] = {0};
 };
 
+// Device memory source of a context: the caller's callbacks
+// (nhdc_set_allocator), or hipMalloc / hipFree when none are set.
+struct Allocator {
+    void *(*alloc)(size_t bytes, void *user) = nullptr;
+    void (*free_)(void *ptr, void *user) = nullptr;
+    void *user = nullptr;
+};
+// bytes of device memory from `a` (nullptr on failure), and their release
+void *dev_alloc(const Allocator &a, size_t bytes);
+void dev_free(const Allocator &a, void *p);
+
 // One set of instances advanced together (a context is a batch of one).
 struct Launcher {
+    Allocator al;                  // where d_insts (and autotuning snapshots) come from
     int precision = NHDC_FP64;
     int n = 0;
     void *d_insts = nullptr;       // Inst<double>[n] or Inst<float>[n] in device memory
@@ -230,6 +242,9 @@ hipError_t launch_level_nonflat(const double *a, int64_t n, int nlev, int32_t *o
 hipError_t launch_to_float(const double *src, float *dst, int64_t n, hipStream_t st);
 hipError_t launch_diag(const Grid &g, const State &s, double *part, double *out2, hipStream_t st);
 hipError_t launch_finite(const Grid &g, const State &s, int *flag, hipStream_t st);
+// release a context's device memory and the context (nhdc_destroy, or the
+// last batch holding a context whose destroy was deferred)
+void free_context(nhdc_ctx *ctx);
 // message of the calling thread's last failed context-free call
 const char *context_free_error();
 hipError_t launch_init_prev(const Grid &g, const State &s, hipStream_t st);
@@ -255,6 +270,8 @@ struct nhdc_ctx {
     nhdc::Tracers tr;
     std::vector<void *> tr_allocs;  // tracer arrays (freed when the tracers are replaced)
     int in_batches = 0;             // live batches holding this context's descriptor
+    bool destroy_pending = false;   // nhdc_destroy came while batched: freed by the last batch
+    nhdc::Allocator al;             // device memory source (nhdc_set_allocator)
     nhdc::Tune tune;
     nhdc::Launcher L;
     nhdc::Timing tm;

@@ -32,6 +32,23 @@ int hip_fail(std::string &err, hipError_t e, const char *where) {
     return set_err(err, NHDC_EHIP, std::string(where) + ": " + hipGetErrorString(e));
 }
 
+void *dev_alloc(const Allocator &a, size_t bytes) {
+    void *p = nullptr;
+    if (a.alloc) {
+        p = a.alloc(bytes, a.user);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+    }
+    return p;
+}
+
+void dev_free(const Allocator &a, void *p) {
+    if (!p) return;
+    if (a.free_) a.free_(p, a.user);
+    else (void)hipFree(p);
+}
+
 hipError_t timing_begin(Timing *tm, int id, hipStream_t st) {
     if (!tm || !tm->on) return hipSuccess;
     size_t slot = tm->ids.size();
@@ -117,12 +134,14 @@ int upload_insts(Launcher &L, const std::vector<nhdc_ctx *> &ctxs, std::string &
         host.assign(b, b + v.size() * sizeof(Inst<double>));
     }
     if (L.d_insts) {
-        (void)hipFree(L.d_insts);
+        hipError_t e = hipDeviceSynchronize();  // no launch may still read the old descriptors
+        if (e != hipSuccess) return hip_fail(err, e, "instance descriptors: sync");
+        dev_free(L.al, L.d_insts);
         L.d_insts = nullptr;
     }
-    hipError_t e = hipMalloc(&L.d_insts, host.size());
-    if (e != hipSuccess) return set_err(err, NHDC_ENOMEM, "instance descriptors: hipMalloc failed");
-    e = hipMemcpy(L.d_insts, host.data(), host.size(), hipMemcpyHostToDevice);
+    L.d_insts = dev_alloc(L.al, host.size());
+    if (!L.d_insts) return set_err(err, NHDC_ENOMEM, "instance descriptors: allocation failed");
+    hipError_t e = hipMemcpy(L.d_insts, host.data(), host.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(err, e, "instance descriptors: hipMemcpy");
     L.precision = prec;
     L.n = n;
@@ -149,8 +168,8 @@ static void state_arrays(nhdc_ctx *c, std::vector<std::pair<double *, size_t>> &
     if (c->tr.nt) out.push_back({c->tr.q, size_t(c->tr.nt) * NC});
 }
 
-static int snapshot(const std::vector<nhdc_ctx *> &ctxs, std::vector<void *> &buf, bool restore,
-                    hipStream_t st, std::string &err) {
+static int snapshot(const Allocator &al, const std::vector<nhdc_ctx *> &ctxs,
+                    std::vector<void *> &buf, bool restore, hipStream_t st, std::string &err) {
     size_t q = 0;
     for (auto *c : ctxs) {
         std::vector<std::pair<double *, size_t>> arr;
@@ -158,10 +177,9 @@ static int snapshot(const std::vector<nhdc_ctx *> &ctxs, std::vector<void *> &bu
         for (auto &a : arr) {
             hipError_t e;
             if (!restore) {
-                void *b = nullptr;
-                if (hipMalloc(&b, a.second * 8) != hipSuccess) {
-                    (void)hipGetLastError();
-                    for (void *x : buf) (void)hipFree(x);
+                void *b = dev_alloc(al, a.second * 8);
+                if (!b) {
+                    for (void *x : buf) dev_free(al, x);
                     buf.clear();
                     return set_err(err, NHDC_ENOMEM, "autotune: no memory for the state snapshot");
                 }
@@ -176,7 +194,7 @@ static int snapshot(const std::vector<nhdc_ctx *> &ctxs, std::vector<void *> &bu
     hipError_t e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(err, e, "autotune: sync");
     if (restore) {
-        for (void *x : buf) (void)hipFree(x);
+        for (void *x : buf) dev_free(al, x);
         buf.clear();
     }
     return NHDC_OK;
@@ -246,11 +264,11 @@ int autotune(Launcher &L, Tune &tune, const std::vector<nhdc_ctx *> &ctxs, const
         return NHDC_OK;
     }
     std::vector<void *> snap;
-    int rc = snapshot(ctxs, snap, false, st, err);
+    int rc = snapshot(L.al, ctxs, snap, false, st, err);
     if (rc) return rc;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
-        snapshot(ctxs, snap, true, st, err);
+        snapshot(L.al, ctxs, snap, true, st, err);
         return set_err(err, NHDC_EHIP, "autotune: hipEventCreate failed");
     }
     auto measure = [&](const Tune &t, double &ms) -> int {
@@ -290,7 +308,7 @@ int autotune(Launcher &L, Tune &tune, const std::vector<nhdc_ctx *> &ctxs, const
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     std::string err2;
-    int rc2 = snapshot(ctxs, snap, true, st, err2);
+    int rc2 = snapshot(L.al, ctxs, snap, true, st, err2);
     if (rc) return rc;
     if (rc2) return set_err(err, rc2, err2);
     tune = bt;
@@ -303,6 +321,17 @@ int autotune(Launcher &L, Tune &tune, const std::vector<nhdc_ctx *> &ctxs, const
     if (best_out)
         for (int i = 0; i < 4; ++i) best_out[i] = best[i];
     return NHDC_OK;
+}
+
+void free_context(nhdc_ctx *ctx) {
+    if (hipSetDevice(ctx->device) == hipSuccess) {
+        (void)hipDeviceSynchronize();  // no pending work may touch the memory
+        for (hipEvent_t e : ctx->tm.ev) (void)hipEventDestroy(e);
+        dev_free(ctx->al, ctx->L.d_insts);
+        for (void *q : ctx->allocs) dev_free(ctx->al, q);
+        for (void *q : ctx->tr_allocs) dev_free(ctx->al, q);
+    }
+    delete ctx;
 }
 
 }  // namespace nhdc
@@ -322,14 +351,11 @@ int set_err(nhdc_ctx *ctx, int code, const std::string &msg) {
 
 template <class T>
 int dalloc(nhdc_ctx *ctx, T **p, int64_t n) {
-    void *q = nullptr;
     size_t bytes = size_t(n > 0 ? n : 1) * sizeof(T);
-    hipError_t e = hipMalloc(&q, bytes);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return set_err(ctx, NHDC_ENOMEM,
-                       "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
-    }
+    void *q = dev_alloc(ctx->al, bytes);
+    if (!q)
+        return set_err(ctx, NHDC_ENOMEM, "device allocation of " + std::to_string(bytes) +
+                                             " bytes failed" + (ctx->al.alloc ? " (caller's allocator)" : ""));
     ctx->allocs.push_back(q);
     *p = static_cast<T *>(q);
     return NHDC_OK;
@@ -484,6 +510,18 @@ int nhdc_create(nhdc_ctx **out, int precision, int device) {
     ctx->device = device;
     ctx->precision = precision;
     *out = ctx;
+    return NHDC_OK;
+}
+
+int nhdc_set_allocator(nhdc_ctx *ctx, void *(*alloc)(size_t bytes, void *user),
+                       void (*free_)(void *ptr, void *user), void *user) {
+    if (!ctx) return NHDC_EINVAL;
+    if ((alloc == nullptr) != (free_ == nullptr))
+        return set_err(ctx, NHDC_EINVAL, "set_allocator: give both callbacks or neither");
+    if (ctx->grid_ready || !ctx->allocs.empty())
+        return set_err(ctx, NHDC_ESTATE, "set_allocator: must come before nhdc_upload_grid");
+    ctx->al = Allocator{alloc, free_, alloc ? user : nullptr};
+    ctx->L.al = ctx->al;
     return NHDC_OK;
 }
 
@@ -971,7 +1009,7 @@ int nhdc_set_tracers(nhdc_ctx *ctx, int n_tracers, const double *q, int on_devic
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(ctx, hipStreamSynchronize(s));
     HIP_TRY(ctx, hipDeviceSynchronize());
-    for (void *p : ctx->tr_allocs) (void)hipFree(p);
+    for (void *p : ctx->tr_allocs) dev_free(ctx->al, p);
     ctx->tr_allocs.clear();
     ctx->tr = Tracers{};
     if (n_tracers > 0) {
@@ -1010,13 +1048,13 @@ int nhdc_n_tracers(const nhdc_ctx *ctx) { return ctx ? ctx->tr.nt : NHDC_EINVAL;
 
 void nhdc_destroy(nhdc_ctx *ctx) {
     if (!ctx) return;
-    if (hipSetDevice(ctx->device) == hipSuccess) {
-        for (hipEvent_t e : ctx->tm.ev) (void)hipEventDestroy(e);
-        if (ctx->L.d_insts) (void)hipFree(ctx->L.d_insts);
-        for (void *q : ctx->allocs) (void)hipFree(q);
-        for (void *q : ctx->tr_allocs) (void)hipFree(q);
+    if (ctx->in_batches > 0) {
+        // a live batch still holds the context's descriptor and device
+        // memory: the last nhdc_batch_destroy releases them
+        ctx->destroy_pending = true;
+        return;
     }
-    delete ctx;
+    free_context(ctx);
 }
 
 }  // extern "C"

@@ -25,7 +25,7 @@ EXPORTS = ("nhdc_create", "nhdc_upload_grid", "nhdc_init_state", "nhdc_step", "n
            "nhdc_kernel_stats", "nhdc_last_error", "nhdc_destroy", "nhdc_batch_create",
            "nhdc_batch_step", "nhdc_batch_set_tiles", "nhdc_batch_autotune",
            "nhdc_batch_last_error", "nhdc_batch_destroy", "nhdc_set_tracers", "nhdc_get_tracers",
-           "nhdc_n_tracers", "nhdc_diag_noalloc")
+           "nhdc_n_tracers", "nhdc_diag_noalloc", "nhdc_set_allocator")
 
 
 class NhdcError(RuntimeError):
@@ -60,6 +60,39 @@ class _State(C.Structure):
 
 
 _LIB = None
+
+# nhdc_set_allocator callbacks: alloc(bytes, user) -> device pointer; free_(ptr, user)
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class TorchAllocator:
+    """Device memory of a context from PyTorch's caching allocator
+    (nhdc_set_allocator): the library then allocates nothing of its own, and
+    torch.cuda.memory_allocated() counts the context's arrays."""
+
+    def __init__(self, device):
+        import torch
+        self.device = int(device)
+        self.live = 0
+
+        def alloc(nbytes, user):
+            try:
+                p = torch.cuda.caching_allocator_alloc(int(nbytes), device=self.device)
+            except Exception:  # out of memory: the library reports ENOMEM
+                return None
+            self.live += 1
+            return p
+
+        def free(ptr, user):
+            try:
+                torch.cuda.caching_allocator_delete(ptr)
+                self.live -= 1
+            except Exception:  # interpreter shutdown
+                pass
+
+        self.alloc = _ALLOC_FN(alloc)  # kept alive with the context
+        self.free = _FREE_FN(free)
 
 
 def library_path():
@@ -106,6 +139,7 @@ def lib():
         L.nhdc_kernel_stats.argtypes = [vp, i, C.POINTER(C.c_char_p), C.POINTER(d),
                                         C.POINTER(C.c_int64)]
         L.nhdc_diag_noalloc.argtypes = [C.c_int64, C.c_int32] + [vp] * 6
+        L.nhdc_set_allocator.argtypes = [vp, _ALLOC_FN, _FREE_FN, vp]
         L.nhdc_last_error.argtypes = [vp]
         L.nhdc_last_error.restype = C.c_char_p
         L.nhdc_destroy.argtypes = [vp]
@@ -134,7 +168,9 @@ def params_struct(p):
 class Dycore:
     """One dynamical-core instance resident on a GPU."""
 
-    def __init__(self, case, precision="fp64", device=0, init=True):
+    def __init__(self, case, precision="fp64", device=0, init=True, allocator=None):
+        """allocator: None (the library's hipMalloc) or "torch" (PyTorch's
+        caching allocator, through nhdc_set_allocator)."""
         self.L = lib()
         self.case = case
         self.grid = case.grid
@@ -146,6 +182,13 @@ class Dycore:
         if rc != 0:
             raise NhdcError(rc, "nhdc_create failed (no usable HIP device?)")
         self.h = h
+        self.allocator = None
+        if allocator == "torch":
+            self.allocator = TorchAllocator(device)
+            self._check(self.L.nhdc_set_allocator(self.h, self.allocator.alloc,
+                                                  self.allocator.free, None))
+        elif allocator is not None:
+            raise ValueError(f"unknown allocator {allocator!r}")
         g = case.grid
         keep = {}
 
@@ -319,7 +362,9 @@ def diag_noalloc(cell_area, zh, rho, theta_v, out, stream=None):
 class Batch:
     """Several Dycore instances (same device and precision, any sizes) advanced
     together: one launch per kernel over all of them, each step replayed from a
-    captured HIP graph.  The instances must outlive the batch."""
+    captured HIP graph.  The batch keeps its members alive; closing a member
+    while the batch lives defers the release of its device memory to the
+    batch's close."""
 
     def __init__(self, dycores):
         self.L = lib()
