@@ -6,19 +6,20 @@ column solve) over the whole grid; a cell-level update is one cell at one
 full level through one substep.  Inputs are synthetic (seeded recipe with the
 paper's grid and level counts) and resident in HBM before timing.
 
-Default workload (the value): R2B6 (327 680 cells), 90 stretched levels to
-75 km over seeded random-harmonic terrain, dt = 90 s, FP64 plain form, 2
-warm-up steps then 98 timed steps (steps 3..100 of the 100-step run).  The
+Default workload (the value): R2B8 (5 242 880 cells, the paper's 10 km grid),
+90 stretched levels to 75 km over seeded random-harmonic terrain, dt = 22.5 s,
+FP64 plain form, 2 warm-up steps then 48 timed steps (a 50-step run).  The
 same line carries the FP32-mixed form on the same workload (throughput,
 speedup, per-field error against FP64 next to the FP32-rounding floor), the
 roofline of the dominant kernel (algorithmic bytes / average duration from
-HIP events on the stream the kernels run on) and the CPU oracle timed on a
-bounded sample.
+HIP events on the stream the kernels run on) with the whole-substep
+accounting (bytes per cell-level-substep of the compulsory and the practical
+two-phase budgets, and counted bytes, times the rate), and, under forms, the
+other workloads: R2B6x90 in both forms with the options, R2B7x90 mixed with
+its per-field error after 100 steps, and the batch of 16 uneven instances
+against 16 sequential runs.  The CPU oracle is timed on a bounded sample.
 
-Other workloads (one JSON line each): --config 3 (R2B7x90 mixed, 100 steps,
-error vs FP64), --config 4 (batch of 16 uneven instances, mixed, one launch
-per kernel + graph replay + autotuned tiles, vs 16 sequential plain runs),
---config 5 (R2B8x90 mixed, 50-step sustained run).
+--config 3/4/5 runs one of those workloads alone (for its counter passes).
 """
 import argparse
 import hashlib
@@ -132,11 +133,11 @@ def _summary_matches(txt, src_hash, numbering):
     return bool(m and n and m.group(1) == src_hash and n.group(1) == numbering)
 
 
-def measured_traffic(kernel, src_hash, precision, numbering="curve"):
+def measured_traffic(kernel, src_hash, precision, numbering="curve", tag="r2b8x90"):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel sources and numbering;
-    else None."""
-    path = os.path.join(ROOT, "profiles", f"dycore_{precision}_r2b6x90_hbm_counters.txt")
+    summary of workload `tag`, if it was taken on the current kernel sources
+    and numbering; else None."""
+    path = os.path.join(ROOT, "profiles", f"dycore_{precision}_{tag}_hbm_counters.txt")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
@@ -150,11 +151,11 @@ LAUNCHES_PER_STEP = {"vt_edge": 2, "vertex": 2, "cell_vt": 2, "edge_pred": 1, "c
                      "edge_corr": 1, "column_corr": 1}  # per substep
 
 
-def step_traffic(src_hash, precision, nsub, numbering="curve"):
-    """HBM bytes of one whole step from the committed counter summary (every
-    kernel's counted bytes per launch x its launches), if it was taken on the
-    current kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", f"dycore_{precision}_r2b6x90_hbm_counters.txt")
+def step_traffic(src_hash, precision, nsub, numbering="curve", tag="r2b8x90"):
+    """HBM bytes of one whole step from the committed counter summary of
+    workload `tag` (every kernel's counted bytes per launch x its launches),
+    if it was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"dycore_{precision}_{tag}_hbm_counters.txt")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
@@ -169,8 +170,10 @@ def step_traffic(src_hash, precision, nsub, numbering="curve"):
     return total
 
 
-def cpu_baseline(case):
-    """The oracle, as it stands, on one step (5 substeps) of the same case."""
+def cpu_baseline(case, headline_tag=None):
+    """The oracle, as it stands, on one step (5 substeps) of `case` (the
+    R2B6x90 workload: the oracle cannot hold the larger grids in host memory,
+    and its rate per cell-level is about the same at any size)."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     m = oracle.Model(case)
@@ -180,8 +183,10 @@ def cpu_baseline(case):
     units = case.grid.n_cells * case.n_lev * case.nsub
     out = {"value": units / el, "unit": "cell-level updates/s", "cores": threads,
            "kind": "oracle", "seconds": round(el, 2),
-           "sample": f"1 step ({case.nsub} substeps) of the same R2B{case.grid.k}x{case.n_lev} "
-                     f"case from its initial state"}
+           "sample": f"1 step ({case.nsub} substeps) of the R2B{case.grid.k}x{case.n_lev} case of the "
+                     f"same recipe (terrain, 90 stretched levels) from its initial state"
+                     + (f", standing in for the {headline_tag} workload, which exceeds the oracle's "
+                        f"host memory" if headline_tag and headline_tag != "r2b6x90" else "")}
     out["host_cpu"] = host_cpu_model()
     out["logical_cpus"] = os.cpu_count()
     # thread scaling of the oracle on the small flat case (R2B4x20, one step),
@@ -334,103 +339,217 @@ def error_table(nhdc, case, steps):
     return out
 
 
-def bench_default(args, torch, nhdc, CS):
-    stream = torch.cuda.current_stream()
-    t0 = time.time()
-    case = CS.config_case(2, order=args.order)
+# bytes per cell-level-substep of the substep's budget (the design-independent
+# accounting): the compulsory traffic of an ideal single pass (state n read and
+# written, the Exner history, the FP64 flux accumulators read-modify-write, the
+# heights and reference profiles) and a practical two-phase design (plus the
+# predicted state, the state-n tendencies and the Exner gradient written and
+# read, and state n read again by the corrector); edge fields count 1.5 per
+# cell-level.  The mixed form's tendency arrays are FP32.
+STEP_BUDGET_B = {"fp64": {"compulsory": 152.0, "practical": 332.0},
+                 "mixed": {"compulsory": 152.0, "practical": 300.0}}
+
+
+def step_accounting(rate, precision, counted_b=None):
+    """Whole-substep bandwidth of a form running at `rate` cell-level
+    updates/s (= cell-level-substeps/s): each budget's bytes x rate, and the
+    counted bytes x rate when a counter summary of the same kernel sources
+    gives them; each against the 8 TB/s peak."""
+    out = {}
+    for basis, b in STEP_BUDGET_B[precision].items():
+        gbs = b * rate / 1e9
+        out[basis] = {"B_per_cell_level_substep": b, "GBs": round(gbs, 1),
+                      "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    if counted_b is not None:
+        gbs = counted_b * rate / 1e9
+        out["counted"] = {"B_per_cell_level_substep": round(counted_b, 1), "GBs": round(gbs, 1),
+                          "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    return out
+
+
+def time_form(args, torch, nhdc, case, prec, stream, steps=None, warmup=None, table=True):
+    """One form on one case: throughput over `steps` timed steps after
+    `warmup` untimed ones, then (optionally) the per-kernel table."""
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
     g = case.grid
-    units_per_step = g.n_cells * case.n_lev * case.nsub
-    log(f"case R2B{g.k}x{case.n_lev}: {g.n_cells} cells, {g.n_edges} edges ({time.time() - t0:.1f}s)")
-    forms = {}
-    tables = {}
-    for prec in ("fp64", "mixed"):
+    d = nhdc.Dycore(case, precision=prec)
+    ms = timed_steps(torch, lambda: d.step(case.dt, case.nsub, stream), steps, warmup, stream)
+    d.check_finite()
+    units = g.n_cells * case.n_lev * case.nsub
+    out = {"value": units * steps / (ms / 1e3), "ms_per_step": ms / steps}
+    if table:
+        out["_table"] = kernel_table(d, case, args.timing_steps, stream, prec)
+    d.close()
+    return out
+
+
+def error_table_device(torch, nhdc, case, steps):
+    """Per field: E = rel-L2(mixed - FP64), S = rel-L2 between two FP64 runs
+    whose initial states differ by seeded relative noise 2^-24 (the
+    FP32-rounding floor), after `steps` steps from the initial state.  The
+    norms are taken on the device, so grids of any size fit."""
+    dev = torch.device("cuda", 0)
+    init = {f: torch.from_numpy(getattr(case, f)).to(dev) for f in FIELDS}
+
+    def run(prec, state=None):
         d = nhdc.Dycore(case, precision=prec)
-        ms = timed_steps(torch, lambda: d.step(case.dt, case.nsub, stream), args.steps,
-                         args.warmup, stream)
-        d.check_finite()
-        forms[prec] = {"value": units_per_step * args.steps / (ms / 1e3),
-                       "ms_per_step": ms / args.steps}
-        log(f"{prec}: {ms / args.steps:.3f} ms/step, {forms[prec]['value']:.4e} cell-level updates/s")
-        tables[prec] = kernel_table(d, case, args.timing_steps, stream, prec)
+        if state is not None:
+            d.init_state(*[state[f] for f in FIELDS])
+        for _ in range(steps):
+            d.step(case.dt, case.nsub)
+        out = d.get_state_device()
+        torch.cuda.synchronize()
         d.close()
-    forms["mixed"]["speedup_vs_fp64"] = forms["fp64"]["ms_per_step"] / forms["mixed"]["ms_per_step"]
+        return {f: out[f] for f in FIELDS}
+
+    f64 = run("fp64")
+    mix = run("mixed")
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(7)
+    pert = {f: v * (1.0 + 2.0 ** -24 * torch.randn(v.shape, generator=gen, device=dev,
+                                                      dtype=torch.float64)) for f, v in init.items()}
+    f64p = run("fp64", pert)
+    del pert
+    out = {}
+    for f in FIELDS:
+        nref = float(torch.linalg.vector_norm(f64[f]))
+        sig = float(torch.linalg.vector_norm(f64[f] - init[f]))
+        e = float(torch.linalg.vector_norm(mix[f] - f64[f]))
+        sf = float(torch.linalg.vector_norm(f64p[f] - f64[f]))
+        out[f] = {"E": e / nref, "S": sf / nref, "E_over_signal": e / max(sig, 1e-300)}
+    del f64, mix, f64p, init
+    torch.cuda.empty_cache()
+    return out
+
+
+def options_forms(args, torch, nhdc, CS, case, stream, plain_ms):
+    """The FP64 step with each option set, on `case`, timed as the plain form."""
     import dataclasses
+    units = case.grid.n_cells * case.n_lev * case.nsub
+    out = {}
 
-    def option_form(label, ocase):
-        """The FP64 step with an option set, same workload and timing."""
-        d = nhdc.Dycore(ocase, precision="fp64")
-        ms = timed_steps(torch, lambda: d.step(ocase.dt, ocase.nsub, stream), args.steps,
-                         args.warmup, stream)
-        d.check_finite()
-        tab = kernel_table(d, ocase, args.timing_steps, stream, "fp64")
-        d.close()
-        out = {"value": units_per_step * args.steps / (ms / 1e3), "ms_per_step": ms / args.steps,
-               "cost_vs_plain": (ms / args.steps) / forms["fp64"]["ms_per_step"],
-               "kernels": {k: {"avg_ms": round(v["avg_ms"], 5), "alg_GBs": round(v["alg_GBs"], 1)}
-                           for k, v in tab.items()}}
-        log(f"fp64 {label}: {ms / args.steps:.3f} ms/step, {out['value']:.4e} cell-level updates/s")
-        return out
+    def one(label, ocase):
+        r = time_form(args, torch, nhdc, ocase, "fp64", stream)
+        tab = r.pop("_table")
+        r["cost_vs_plain"] = r["ms_per_step"] / plain_ms
+        r["kernels"] = {k: {"avg_ms": round(v["avg_ms"], 5), "alg_GBs": round(v["alg_GBs"], 1)}
+                        for k, v in tab.items()}
+        log(f"  fp64 {label}: {r['ms_per_step']:.3f} ms/step, {r['value']:.4e} cell-level updates/s")
+        return r
 
-    extra = [f for f in args.forms.split(",") if f]
+    extra = [f for f in args.options.split(",") if f]
     if "upwind" in extra:  # second-order upwind edge values of rho and theta_v
-        forms["fp64_upwind"] = option_form("upwind", dataclasses.replace(
+        out["fp64_upwind"] = one("upwind", dataclasses.replace(
             case, params=dataclasses.replace(case.params, upwind=1)))
     if "damped" in extra:  # fourth-order divergence damping, w sponge, Smagorinsky diffusion
         dc = CS.with_damping(case)
-        forms["fp64_damped"] = option_form("damped", dc)
-        forms["fp64_damped"]["options"] = {"div_damp4": dc.params.div_damp4, "smag": dc.params.smag,
-                                           "sponge_rate_at_lid": float(dc.w_damp[0]),
-                                           "sponge_base_m": CS.DAMPED["sponge_base"]}
+        out["fp64_damped"] = one("damped", dc)
+        out["fp64_damped"]["options"] = {"div_damp4": dc.params.div_damp4, "smag": dc.params.smag,
+                                         "sponge_rate_at_lid": float(dc.w_damp[0]),
+                                         "sponge_base_m": CS.DAMPED["sponge_base"]}
     if "tracers" in extra:  # four tracers carried by the step's averaged mass fluxes
-        tc = CS.with_tracers(case)
-        forms["fp64_tracers"] = option_form("tracers", tc)
-        forms["fp64_tracers"]["tracers"] = list(CS.TRACER_NAMES)
+        out["fp64_tracers"] = one("tracers", CS.with_tracers(case))
+        out["fp64_tracers"]["tracers"] = list(CS.TRACER_NAMES)
+    return out
+
+
+def short_table(tab):
+    return {k: {"avg_ms": round(v["avg_ms"], 5), "share": round(v["share"], 4),
+                "alg_GBs": round(v["alg_GBs"], 1)} for k, v in tab.items()}
+
+
+def kernel_roofline(tab, src_hash, prec, tag, numbering):
+    """The dominant kernel's algorithmic bytes per launch over its average
+    launch time (HIP events on the step's stream), against the 8 TB/s peak;
+    traffic = its counted bytes per launch when the counter summary of this
+    workload was taken on the current kernel sources."""
+    dom = max(tab, key=lambda k: tab[k]["share"])
+    achieved = tab[dom]["alg_GBs"]
+    return {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(dom, src_hash, prec, numbering, tag),
+            "alg_bytes_per_launch": int(tab[dom]["alg_bytes"]),
+            "avg_launch_ms": round(tab[dom]["avg_ms"], 5),
+            "basis": "dominant kernel: its algorithmic bytes per launch (every input and output "
+                     "array once) / its average launch time"}
+
+
+def bench_headline(args, torch, nhdc, CS):
+    """The headline workload in the FP64 and FP32-mixed forms, with the
+    other contract workloads as forms of the same line."""
+    stream = torch.cuda.current_stream()
+    cfg = args.headline
+    tag = f"r2b{CS.CONFIGS[cfg]['k']}x{CS.CONFIGS[cfg]['n_lev']}"
+    t0 = time.time()
+    case = CS.config_case(cfg, order=args.order)
+    g = case.grid
+    units_per_step = g.n_cells * case.n_lev * case.nsub
+    log(f"case R2B{g.k}x{case.n_lev}: {g.n_cells} cells, {g.n_edges} edges ({time.time() - t0:.1f}s)")
+    forms, tables = {}, {}
+    for prec in ("fp64", "mixed"):
+        forms[prec] = time_form(args, torch, nhdc, case, prec, stream)
+        tables[prec] = forms[prec].pop("_table")
+        log(f"{prec}: {forms[prec]['ms_per_step']:.3f} ms/step, "
+            f"{forms[prec]['value']:.4e} cell-level updates/s")
+    forms["mixed"]["speedup_vs_fp64"] = forms["fp64"]["ms_per_step"] / forms["mixed"]["ms_per_step"]
     if args.error_steps > 0:
-        log(f"per-field error, {args.error_steps} steps ...")
-        forms["mixed"]["per_field_error"] = error_table(nhdc, case, args.error_steps)
+        log(f"per-field error of the mixed form, {args.error_steps} steps ...")
+        forms["mixed"]["per_field_error"] = error_table_device(torch, nhdc, case, args.error_steps)
         forms["mixed"]["error_steps"] = args.error_steps
+    src_hash = kernel_source_hash()
     kern = tables["fp64"]
     for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["share"]):
         log(f"  fp64 {k:12s} {v['avg_ms']:8.4f} ms  share {v['share']:.3f}  {v['alg_GBs']:8.1f} GB/s")
-    dom = max(kern, key=lambda k: kern[k]["share"])
-    src_hash = kernel_source_hash()
-    achieved = kern[dom]["alg_GBs"]
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(dom, src_hash, "fp64", args.order),
-                "alg_bytes_per_launch": int(kern[dom]["alg_bytes"]),
-                "avg_launch_ms": round(kern[dom]["avg_ms"], 5)}
-    step_bytes = step_traffic(src_hash, "fp64", case.nsub, args.order)
-    if step_bytes is not None:
-        roofline["step_hbm_GBs"] = round(step_bytes / (forms["fp64"]["ms_per_step"] / 1e3) / 1e9, 1)
-        roofline["step_hbm_frac"] = round(roofline["step_hbm_GBs"] / HBM_PEAK_GBS, 4)
+    roofline = kernel_roofline(kern, src_hash, "fp64", tag, args.order)
+    counted = step_traffic(src_hash, "fp64", case.nsub, args.order, tag)
+    roofline["step"] = step_accounting(forms["fp64"]["value"], "fp64",
+                                       None if counted is None else counted / (units_per_step))
     if not args.copy_calibration:  # counter runs keep a single copy: the calibration one
         copy_gbs = copy_bandwidth(torch)
         roofline["copy_GBs"] = round(copy_gbs, 1)
-        roofline["frac_of_copy"] = round(achieved / copy_gbs, 4)
+        roofline["frac_of_copy"] = round(roofline["achieved"] / copy_gbs, 4)
         rates = stream_rates(torch)
         roofline["read_GBs"] = round(rates["read"], 1)
         roofline["write_GBs"] = round(rates["write"], 1)
         log(f"4 GiB device copy: {copy_gbs:.1f} GB/s; read-only {rates['read']:.1f}, "
             f"write-only {rates['write']:.1f} GB/s")
     mk = tables["mixed"]
-    mdom = max(mk, key=lambda k: mk[k]["share"])
-    forms["mixed"]["kernels"] = {k: {"avg_ms": round(v["avg_ms"], 5), "share": round(v["share"], 4),
-                                     "alg_GBs": round(v["alg_GBs"], 1)} for k, v in mk.items()}
-    forms["mixed"]["roofline"] = {"kernel": mdom, "achieved": round(mk[mdom]["alg_GBs"], 1),
-                                  "frac": round(mk[mdom]["alg_GBs"] / HBM_PEAK_GBS, 4),
-                                  "traffic": measured_traffic(mdom, src_hash, "mixed", args.order)}
-    mstep = step_traffic(src_hash, "mixed", case.nsub, args.order)
-    if mstep is not None:
-        gbs = mstep / (forms["mixed"]["ms_per_step"] / 1e3) / 1e9
-        forms["mixed"]["roofline"]["step_hbm_GBs"] = round(gbs, 1)
-        forms["mixed"]["roofline"]["step_hbm_frac"] = round(gbs / HBM_PEAK_GBS, 4)
+    forms["mixed"]["kernels"] = short_table(mk)
+    forms["mixed"]["roofline"] = kernel_roofline(mk, src_hash, "mixed", tag, args.order)
+    mcount = step_traffic(src_hash, "mixed", case.nsub, args.order, tag)
+    forms["mixed"]["roofline"]["step"] = step_accounting(
+        forms["mixed"]["value"], "mixed", None if mcount is None else mcount / units_per_step)
     if args.copy_calibration:
         calibration_copy(torch)
+    workload = (f"R2B{g.k} ({g.n_cells} cells) x {case.n_lev} levels to 75 km, terrain, "
+                f"dt={case.dt:g}s, {case.nsub} substeps, FP64 plain")
+    del case
+    want = [f for f in args.forms.split(",") if f]
+    if "r2b6" in want and cfg != 2:  # the R2B6x90 workload: both forms and the options
+        c2 = CS.config_case(2, order=args.order)
+        log("R2B6x90 ...")
+        r6 = {}
+        for prec in ("fp64", "mixed"):
+            r6[prec] = time_form(args, torch, nhdc, c2, prec, stream)
+            r6[prec]["kernels"] = short_table(r6[prec].pop("_table"))
+            log(f"  {prec}: {r6[prec]['ms_per_step']:.3f} ms/step, {r6[prec]['value']:.4e}")
+        r6.update(options_forms(args, torch, nhdc, CS, c2, stream, r6["fp64"]["ms_per_step"]))
+        forms["config2_r2b6x90"] = r6
+        del c2
+    elif cfg == 2:
+        forms.update(options_forms(args, torch, nhdc, CS, CS.config_case(2, order=args.order), stream,
+                                   forms["fp64"]["ms_per_step"]))
+    if "config3" in want:
+        log("R2B7x90 mixed ...")
+        forms["config3_r2b7x90_mixed"] = bench_config3(args, torch, nhdc, CS, stream)
+    if "config4" in want:
+        log("batch of 16 ...")
+        forms["config4_batch16"] = bench_batch_form(args, torch, nhdc, CS, stream)
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        cpu = cpu_baseline(case)
+        cpu = cpu_baseline(CS.config_case(2, order=args.order), headline_tag=tag)
         log(f"  oracle {cpu['value']:.4e} cell-level updates/s on {cpu['cores']} threads")
     return {
         "metric": METRIC,
@@ -440,23 +559,76 @@ def bench_default(args, torch, nhdc, CS):
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": forms["fp64"]["ms_per_step"],
-        "simulated_s_per_wall_s": case.dt / (forms["fp64"]["ms_per_step"] / 1e3),
+        "simulated_s_per_wall_s": CS.CONFIGS[cfg]["dt"] / (forms["fp64"]["ms_per_step"] / 1e3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"R2B{g.k} ({g.n_cells} cells) x {case.n_lev} levels to 75 km, "
-                               f"terrain, dt={case.dt:g}s, {case.nsub} substeps, FP64 plain",
-                   "cells": g.n_cells, "levels": case.n_lev, "substeps": case.nsub,
-                   "numbering": args.order, "parallelism": "single GPU"},
+        "config": {"workload": workload, "cells": g.n_cells, "levels": CS.CONFIGS[cfg]["n_lev"],
+                   "substeps": 5, "numbering": args.order, "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "forms": forms,
-        "kernels": {k: {"avg_ms": round(v["avg_ms"], 5), "share": round(v["share"], 4),
-                        "alg_GBs": round(v["alg_GBs"], 1)} for k, v in kern.items()},
+        "kernels": short_table(kern),
         "kernel_source_sha256_16": src_hash,
     }
+
+
+def bench_config3(args, torch, nhdc, CS, stream):
+    """R2B7x90 in the FP32-mixed form: throughput, and the per-field error
+    against FP64 after the workload's 100 steps."""
+    case = CS.config_case(3, order=args.order)
+    r = time_form(args, torch, nhdc, case, "mixed", stream, table=False)
+    f = time_form(args, torch, nhdc, case, "fp64", stream, table=False)
+    r["fp64_ms_per_step"] = f["ms_per_step"]
+    r["speedup_vs_fp64"] = f["ms_per_step"] / r["ms_per_step"]
+    r["workload"] = (f"R2B7 ({case.grid.n_cells} cells) x 90 levels, terrain, dt={case.dt:g}s, "
+                     "5 substeps, FP32-mixed")
+    log(f"  mixed {r['ms_per_step']:.3f} ms/step ({r['value']:.4e}), fp64 {f['ms_per_step']:.3f}")
+    if args.error_steps > 0:
+        n = CS.CONFIGS[3]["steps"]
+        log(f"  per-field error after {n} steps ...")
+        r["per_field_error"] = error_table_device(torch, nhdc, case, n)
+        r["error_steps"] = n
+    return r
+
+
+def bench_batch_form(args, torch, nhdc, CS, stream):
+    """16 uneven instances (R2B4-R2B6, 30-90 levels), FP32-mixed, one launch
+    per kernel over all instances, graph replay, autotuned level tiles; against
+    the 16 instances run one after another in the plain FP64 form and in the
+    mixed form, each instance for the same 10 steps."""
+    cases = CS.batch_cases(order=args.order)
+    steps = 10
+    units = sum(c.grid.n_cells * c.n_lev * c.nsub for c in cases) * steps
+    res = {}
+    for prec in ("fp64", "mixed"):
+        total = 0.0
+        for c in cases:  # sequential, one instance at a time
+            d = nhdc.Dycore(c, precision=prec)
+            total += timed_steps(torch, lambda: d.step(c.dt, c.nsub, stream), steps, 1, stream)
+            d.close()
+        res[f"sequential_{prec}_ms"] = total
+    ds = [nhdc.Dycore(c, precision="mixed") for c in cases]
+    b = nhdc.Batch(ds)
+    dts = [c.dt for c in cases]
+    best = b.autotune(dts, 5)
+    ms = timed_steps(torch, lambda: b.step(dts, 5, 1, stream), steps, 1, stream)
+    for d in ds:
+        d.check_finite()
+    b.close()
+    for d in ds:
+        d.close()
+    out = {"value": units / (ms / 1e3), "ms_per_step": ms / steps, "steps": steps,
+           "instances": [f"R2B{c.grid.k}x{c.n_lev}" for c in cases],
+           "tiles": {"lt_edge": best[0], "lt_cell": best[1], "lt_vert": best[2]},
+           "speedup_vs_sequential_fp64": res["sequential_fp64_ms"] / ms,
+           "speedup_vs_sequential_mixed": res["sequential_mixed_ms"] / ms,
+           "sequential_ms": res}
+    log(f"  batch {ms / steps:.3f} ms/step ({out['value']:.4e}); x{out['speedup_vs_sequential_fp64']:.2f} "
+        f"vs sequential fp64, x{out['speedup_vs_sequential_mixed']:.2f} vs sequential mixed")
+    return out
 
 
 def calibration_copy(torch):
@@ -489,7 +661,7 @@ def bench_single(args, torch, nhdc, CS, cfg):
     case = CS.config_case(cfg)
     g = case.grid
     log(f"case R2B{g.k}x{case.n_lev}: {g.n_cells} cells ({time.time() - t0:.1f}s)")
-    steps = args.steps if args.steps != 98 else CS.CONFIGS[cfg]["steps"] - 2
+    steps = args.steps if args.steps is not None else CS.CONFIGS[cfg]["steps"] - 2
     d = nhdc.Dycore(case, precision="mixed")
     ms = timed_steps(torch, lambda: d.step(case.dt, case.nsub, stream), steps, args.warmup, stream)
     d.check_finite()
@@ -528,7 +700,7 @@ def bench_batch(args, torch, nhdc, CS):
     t0 = time.time()
     cases = CS.batch_cases()
     log(f"16 cases ({time.time() - t0:.1f}s): " + ", ".join(f"R2B{c.grid.k}x{c.n_lev}" for c in cases))
-    steps = args.steps if args.steps != 98 else 10
+    steps = args.steps if args.steps is not None else 10
     units = sum(c.grid.n_cells * c.n_lev * c.nsub for c in cases) * steps
     res = {}
     if args.counters:  # the batch alone at given tiles: counted bytes / steps_run
@@ -580,24 +752,33 @@ def bench_batch(args, torch, nhdc, CS):
 # rocprofv3 summaries (profiles/): the commands that make the raw CSVs, and the
 # reduction of those CSVs to the short text files kept in the repository.
 
-PROFILE_CMDS = {
-    "trace": "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_trace -o trace "
-             "-- python3 -u bench.py --steps 10 --warmup 2 --timing-steps 4 --error-steps 0 "
-             "--no-cpu-baseline > gpurun_out/prof_trace.json",
-    "fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof_fetch -o fetch "
-             "-- python3 -u bench.py --steps 2 --warmup 1 --timing-steps 1 --error-steps 0 "
-             "--no-cpu-baseline --copy-calibration > gpurun_out/prof_fetch.json",
-    "write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof_write -o write "
-             "-- python3 -u bench.py --steps 2 --warmup 1 --timing-steps 1 --error-steps 0 "
-             "--no-cpu-baseline --copy-calibration > gpurun_out/prof_write.json",
+def _prof_cmds(tag, extra):
+    """rocprofv3 commands of one profiled workload: a kernel trace, then one
+    FETCH_SIZE and one WRITE_SIZE pass over a short run that ends with the
+    calibration copy."""
+    base = "python3 -u bench.py --forms none --error-steps 0 --no-cpu-baseline" + extra
+    return {
+        "trace": f"rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_{tag}trace "
+                 f"-o {tag}trace -- {base} --steps 10 --warmup 2 --timing-steps 4 "
+                 f"> gpurun_out/prof_{tag}trace.json",
+        "fetch": f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof_{tag}fetch "
+                 f"-o {tag}fetch -- {base} --steps 2 --warmup 1 --timing-steps 1 --copy-calibration "
+                 f"> gpurun_out/prof_{tag}fetch.json",
+        "write": f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof_{tag}write "
+                 f"-o {tag}write -- {base} --steps 2 --warmup 1 --timing-steps 1 --copy-calibration "
+                 f"> gpurun_out/prof_{tag}write.json",
+    }
+
+
+# the profiled workloads: the headline R2B8x90 step (FP64 and mixed); the
+# R2B6x90 step with the upwind option next to it; the R2B6x90 damped and
+# tracer forms (the kernels only the options run)
+PROFILE_SETS = {
+    "h": {"tag": "r2b8x90", "cmds": _prof_cmds("h", " --headline 5 --options none")},
+    "s": {"tag": "r2b6x90", "cmds": _prof_cmds("s", " --headline 2 --options upwind")},
+    "d": {"tag": "r2b6x90", "cmds": _prof_cmds("d", " --headline 2 --options damped,tracers")},
 }
-for _k in list(PROFILE_CMDS):  # the damping options' kernels in runs of their own
-    PROFILE_CMDS[_k] = PROFILE_CMDS[_k].replace("--no-cpu-baseline", "--no-cpu-baseline --forms upwind")
-    PROFILE_CMDS["d" + _k] = (PROFILE_CMDS[_k].replace("--forms upwind", "--forms damped,tracers")
-                              .replace(f"prof_{_k}", f"prof_d{_k}").replace(f"-o {_k}", f"-o d{_k}"))
-# whole-step HBM bytes of the other workloads: unprofiled runs give the time
-# per step, FETCH_SIZE / WRITE_SIZE passes over only the warm-up and timed
-# steps give the bytes (config 4 at the tiles its unprofiled run chose)
+PROFILE_CMDS = {k + kind: c for k, v in PROFILE_SETS.items() for kind, c in v["cmds"].items()}
 CONFIG_CMDS = {
     cfg: {"run": f"python3 -u bench.py --config {cfg} --no-cpu-baseline > gpurun_out/bench_c{cfg}.json",
           **{kind: f"rocprofv3 --pmc {ctr} --output-format csv -d gpurun_out/prof_c{cfg}{kind} "
@@ -608,28 +789,29 @@ CONFIG_CMDS = {
 # the same workload in a 3-D Hilbert numbering, the bisection's own and a
 # random one, against the bisection-curve numbering of the main runs
 ORDER_CMDS = {
-    o: {"run": f"python3 -u bench.py --order {o} --forms none --error-steps 0 --no-cpu-baseline "
-               f"--steps 20 > gpurun_out/bench_o{o}.json",
+    o: {"run": f"python3 -u bench.py --headline 2 --options none --order {o} --forms none "
+               f"--error-steps 0 --no-cpu-baseline --steps 20 > gpurun_out/bench_o{o}.json",
         **{kind: f"rocprofv3 --pmc {ctr} --output-format csv -d gpurun_out/prof_o{o}{kind} "
-                 f"-o o{o}{kind} -- python3 -u bench.py --order {o} --forms none --steps 2 "
+                 f"-o o{o}{kind} -- python3 -u bench.py --headline 2 --options none --order {o} "
+                 f"--forms none --steps 2 "
                  f"--warmup 1 --timing-steps 1 --error-steps 0 --no-cpu-baseline --copy-calibration "
                  f"> gpurun_out/prof_o{o}{kind}.json"
            for kind, ctr in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE"))}}
-    for o in ("sfc", "canonical", "random")}
+    for o in ("curve", "sfc", "canonical", "random")}
 # instruction issue and texture-addresser activity of the step kernels (FP64
 # and mixed R2B6x90 steps): two counter passes over the same short run
 ISSUE_CMDS = {
     "issue1": "rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR SQ_INSTS_SALU "
               "GRBM_GUI_ACTIVE --output-format csv -d gpurun_out/prof_issue1 -o issue1 -- python3 -u "
-              "bench.py --forms none --steps 2 --warmup 1 --timing-steps 1 --error-steps 0 "
+              "bench.py --headline 2 --options none --forms none --steps 2 --warmup 1 --timing-steps 1 --error-steps 0 "
               "--no-cpu-baseline > gpurun_out/prof_issue1.json",
     "issue2": "rocprofv3 --pmc TA_BUSY_avr SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_MUL_F64 "
               "SQ_INSTS_VALU_FMA_F64 GRBM_GUI_ACTIVE --output-format csv -d gpurun_out/prof_issue2 "
-              "-o issue2 -- python3 -u bench.py --forms none --steps 2 --warmup 1 --timing-steps 1 "
+              "-o issue2 -- python3 -u bench.py --headline 2 --options none --forms none --steps 2 --warmup 1 --timing-steps 1 "
               "--error-steps 0 --no-cpu-baseline > gpurun_out/prof_issue2.json",
     # L2 read requests to the fabric, and those of less than a full line
     "issue3": "rocprofv3 --pmc TCC_EA0_RDREQ_sum TCC_EA0_RDREQ_32B_sum TCC_BUBBLE_sum --output-format csv "
-              "-d gpurun_out/prof_issue3 -o issue3 -- python3 -u bench.py --forms none --steps 2 "
+              "-d gpurun_out/prof_issue3 -o issue3 -- python3 -u bench.py --headline 2 --options none --forms none --steps 2 "
               "--warmup 1 --timing-steps 1 --error-steps 0 --no-cpu-baseline > gpurun_out/prof_issue3.json",
 }
 CS_TRACERS = ("one", "h2o", "o3", "co2")  # the tracer set the tracer form carries
@@ -660,20 +842,61 @@ def _kernel_id(name):
     return k, ("fp64" if m.group(2) == "double" else "mixed")
 
 
-def profile_summary(src, dst):
-    """Reduce the rocprofv3 CSVs under `src` (made by PROFILE_CMDS) to the
-    text summaries under `dst`: per-kernel durations, and HBM bytes per launch
-    from FETCH_SIZE / WRITE_SIZE scaled by what the same counters read for the
-    1 GiB device copy of the calibration."""
+def _cell_vt_phase(name):
+    """k_cell_vt<RT, CORR, LDSM>: the corrector's build when CORR, the second
+    template argument, is true (the third selects the LDS-staged build)."""
+    m = re.search(r"k_cell_vt<(?:double|float), (true|false), (?:true|false)>", name)
+    return "corr" if m and m.group(1) == "true" else "pred"
+
+
+def _rows(path):
     import csv
+    with open(path) as f:
+        return list(csv.DictReader(f))
+
+
+def _counter(src, kind, name):
+    """Per kernel name, the values of counter `name` in dispatch order."""
     from collections import defaultdict
+    out = defaultdict(list)
+    for r in sorted(_rows(os.path.join(src, f"prof_{kind}", f"{kind}_counter_collection.csv")),
+                    key=lambda r: int(r["Dispatch_Id"])):
+        if r["Counter_Name"] == name:
+            out[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+    return out
 
-    def rows(path):
-        with open(path) as f:
-            return list(csv.DictReader(f))
 
-    runs = {k: json.load(open(os.path.join(src, f"prof_{k}.json"))) for k in PROFILE_CMDS
-            if not k.startswith("d") or os.path.exists(os.path.join(src, f"prof_{k}.json"))}
+def profile_summary(src, dst):
+    """Reduce the rocprofv3 CSVs under `src` (made by PROFILE_CMDS and the
+    other command tables) to the text summaries under `dst`."""
+    done = []
+    for key, ps in PROFILE_SETS.items():
+        if key != "d" and all(os.path.exists(os.path.join(src, f"prof_{key}{k}.json"))
+                              for k in ("trace", "fetch", "write")):
+            summarise_set(src, dst, key, ps["tag"])
+            done.append(key)
+    if all(os.path.exists(os.path.join(src, f"prof_d{k}.json")) for k in ("trace", "fetch", "write")):
+        runs = {f"d{k}": json.load(open(os.path.join(src, f"prof_d{k}.json")))
+                for k in ("trace", "fetch", "write")}
+        cfg = runs["dtrace"]["config"]
+        nc, N = cfg["cells"], cfg["levels"]
+        wl = f"R2B6x90 ({nc} cells x {N} levels, dt 90 s, 5 substeps)"
+        damped_summary(src, dst, runs, runs["dtrace"]["kernel_source_sha256_16"], wl, nc,
+                       nc * 3 // 2, nc // 2 + 2, N)
+    config_summary(src, dst)
+    order_summary(src, dst)
+    if all(os.path.exists(os.path.join(src, f"prof_{k}.json")) for k in ISSUE_CMDS):
+        issue_summary(src, dst)
+    print(f"wrote summaries of profile sets {done} to {dst}")
+
+
+def summarise_set(src, dst, key, tag):
+    """One profiled workload: per-kernel durations (kernel trace) and HBM
+    bytes per launch from FETCH_SIZE / WRITE_SIZE, scaled by what the same
+    counters read for the 1 GiB device copy of the calibration."""
+    from collections import defaultdict
+    cmds = PROFILE_SETS[key]["cmds"]
+    runs = {k: json.load(open(os.path.join(src, f"prof_{key}{k}.json"))) for k in cmds}
     hashes = {r["kernel_source_sha256_16"] for r in runs.values()}
     if len(hashes) != 1:
         raise SystemExit(f"profiled runs used different kernel sources: {hashes}")
@@ -681,14 +904,14 @@ def profile_summary(src, dst):
     cfg = runs["trace"]["config"]
     nc, N = cfg["cells"], cfg["levels"]
     ne, nv = nc * 3 // 2, nc // 2 + 2
-    wl = f"R2B6x90 ({nc} cells x {N} levels, dt 90 s, 5 substeps)"
+    wl = f"{tag.upper().replace('X', 'x')} ({nc} cells x {N} levels, {runs['trace']['config']['workload']})"
+    numbering = cfg.get("numbering", "curve")
     # ---- kernel trace ----
-    stats = rows(os.path.join(src, "prof_trace", "trace_kernel_stats.csv"))
-    numbering = cfg.get("numbering", "sfc")
+    stats = _rows(os.path.join(src, f"prof_{key}trace", f"{key}trace_kernel_stats.csv"))
     lines = [f"# rocprofv3 kernel trace: dycore substep kernels, {wl}",
              f"kernel_source_sha256_16: {src_hash}",
              f"numbering: {numbering}",
-             f"command: {PROFILE_CMDS['trace']}",
+             f"command: {cmds['trace']}",
              f"summarised by: python3 bench.py --profile-summary gpurun_out",
              "", "## per instantiation (rocprofv3 --stats)",
              f"{'kernel':24s} {'form':6s} {'calls':>6s} {'avg_us':>9s} {'min_us':>9s} {'max_us':>9s} {'share%':>7s}"]
@@ -697,9 +920,7 @@ def profile_summary(src, dst):
         k, prec = _kernel_id(r["Name"])
         if not k:
             continue
-        var = k
-        if k == "cell_vt":
-            var = "cell_vt(" + ("corr" if "true>" in r["Name"] else "pred") + ")"
+        var = f"cell_vt({_cell_vt_phase(r['Name'])})" if k == "cell_vt" else k
         lines.append(f"{var:24s} {prec:6s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:9.2f} "
                      f"{float(r['MinNs']) / 1e3:9.2f} {float(r['MaxNs']) / 1e3:9.2f} "
                      f"{float(r['Percentage']):7.2f}")
@@ -720,17 +941,10 @@ def profile_summary(src, dst):
         else:
             lines.append(f"{k:14s} {prec:6s} {a:15.2f} {e * 1e3:17.2f} {100 * (a / (e * 1e3) - 1):7.2f}")
     os.makedirs(dst, exist_ok=True)
-    with open(os.path.join(dst, "dycore_r2b6x90_kernel_trace.txt"), "w") as f:
+    with open(os.path.join(dst, f"dycore_{tag}_kernel_trace.txt"), "w") as f:
         f.write("\n".join(lines) + "\n")
     # ---- HBM counters ----
-    def counter(kind, name):
-        out = defaultdict(list)
-        for r in sorted(rows(os.path.join(src, f"prof_{kind}", f"{kind}_counter_collection.csv")),
-                        key=lambda r: int(r["Dispatch_Id"])):
-            if r["Counter_Name"] == name:
-                out[r["Kernel_Name"]].append(float(r["Counter_Value"]))
-        return out
-    fetch, write = counter("fetch", "FETCH_SIZE"), counter("write", "WRITE_SIZE")
+    fetch, write = _counter(src, f"{key}fetch", "FETCH_SIZE"), _counter(src, f"{key}write", "WRITE_SIZE")
     copy = [k for k in fetch if "copyBuffer" in k]
     # the calibration copy is the last device copy of the profiled run
     cf, cw = fetch[copy[0]][-1], write[copy[0]][-1]
@@ -745,14 +959,16 @@ def profile_summary(src, dst):
             per[k][0] += vals
             per[k][1] += write.get(kname, [])
             if k == "cell_vt":
-                var = "cell_vt_" + ("corr" if "true>" in kname else "pred")
+                var = "cell_vt_" + _cell_vt_phase(kname)
                 per[var][0] += vals
                 per[var][1] += write.get(kname, [])
+        if not per:
+            continue
         lines = [f"# rocprofv3 HBM counters: dycore substep kernels, {prec} form, {wl}",
                  f"kernel_source_sha256_16: {src_hash}",
                  f"numbering: {numbering}",
-                 f"command (FETCH_SIZE pass): {PROFILE_CMDS['fetch']}",
-                 f"command (WRITE_SIZE pass): {PROFILE_CMDS['write']}",
+                 f"command (FETCH_SIZE pass): {cmds['fetch']}",
+                 f"command (WRITE_SIZE pass): {cmds['write']}",
                  f"summarised by: python3 bench.py --profile-summary gpurun_out",
                  f"calibration: the 1 GiB device-to-device copy (__amd_rocclr_copyBuffer, 1 GiB read + "
                  f"1 GiB written) reads FETCH_SIZE {cf:.1f} KiB and WRITE_SIZE {cw:.1f} KiB per dispatch, "
@@ -761,6 +977,7 @@ def profile_summary(src, dst):
                  f"{'kernel':14s} {'n':>3s} {'fetch_KiB':>12s} {'write_KiB':>12s}  hbm_bytes_per_launch  "
                  f"alg_bytes_per_launch  hbm_B/cl  alg_B/cl  hbm/alg"]
         order = list(alg)
+        step_b = 0.0
         for k in sorted(per, key=lambda x: order.index(x) if x in order else order.index("cell_vt")):
             fv, wv = per[k]
             rd = sum(fv) / len(fv)
@@ -768,18 +985,15 @@ def profile_summary(src, dst):
             hbm = rd * 1024 * fs + wr * 1024 * ws
             base = k if k in alg else "cell_vt"
             a = alg[base]
+            if k in LAUNCHES_PER_STEP:
+                step_b += hbm * LAUNCHES_PER_STEP[k]
             lines.append(f"{k:14s} {len(fv):3d} {rd:12.1f} {wr:12.1f}  hbm_bytes_per_launch={hbm:.4e}  "
                          f"alg_bytes_per_launch={a:.4e}  {hbm / (nc * N):8.1f}  {a / (nc * N):8.1f}  "
                          f"{hbm / a:7.2f}")
-        with open(os.path.join(dst, f"dycore_{prec}_r2b6x90_hbm_counters.txt"), "w") as f:
+        lines += ["", f"substep total (every kernel x its launches per substep): {step_b:.4e} B = "
+                      f"{step_b / (nc * N):.1f} B per cell-level-substep"]
+        with open(os.path.join(dst, f"dycore_{prec}_{tag}_hbm_counters.txt"), "w") as f:
             f.write("\n".join(lines) + "\n")
-    if all(k in runs for k in ("dtrace", "dfetch", "dwrite")):
-        damped_summary(src, dst, runs, src_hash, wl, nc, ne, nv, N, rows, counter)
-    config_summary(src, dst)
-    order_summary(src, dst)
-    if all(os.path.exists(os.path.join(src, f"prof_{k}.json")) for k in ISSUE_CMDS):
-        issue_summary(src, dst)
-    print(f"wrote summaries for kernel sources {src_hash} to {dst}")
 
 
 def issue_summary(src, dst):
@@ -865,7 +1079,7 @@ def order_summary(src, dst):
             out[k] = acc["fetch"][k] + acc["write"].get(k, 0.0)
         return out
 
-    runs = {"curve": ("", os.path.join(src, "bench.json"))}
+    runs = {}
     for o in ORDER_CMDS:
         runs[o] = (f"o{o}", os.path.join(src, f"bench_o{o}.json"))
     if not all(os.path.exists(p) for _, p in runs.values()) or not all(
@@ -879,9 +1093,7 @@ def order_summary(src, dst):
     lines = ["# the FP64 R2B6x90 step in four numberings of cells, edges and vertices: the "
              "continuous curve over the bisection tree (the default), a 3-D Hilbert curve "
              "through the cell centres, the bisection's own order, random",
-             f"kernel_source_sha256_16: {kernel_source_hash()}",
-             "commands (bisection curve): python3 -u bench.py > gpurun_out/bench.json; "
-             + PROFILE_CMDS["fetch"] + "; " + PROFILE_CMDS["write"]]
+             f"kernel_source_sha256_16: {kernel_source_hash()}"]
     for o in ORDER_CMDS:
         lines.append(f"commands ({o}): " + "; ".join(ORDER_CMDS[o][k] for k in ("run", "fetch", "write")))
     lines += ["summarised by: python3 bench.py --profile-summary gpurun_out",
@@ -956,20 +1168,20 @@ def config_summary(src, dst):
         print(f"config {cfg}: {gbs:.1f} GB/s ({100 * gbs / HBM_PEAK_GBS:.1f} % of peak)")
 
 
-def damped_summary(src, dst, runs, src_hash, wl, nc, ne, nv, N, rows, counter):
+def damped_summary(src, dst, runs, src_hash, wl, nc, ne, nv, N):
     """Durations and HBM bytes of the kernels only the options run (fourth-
     order damping, the diffusion's two passes, the sponge's column builds,
     the four tracer kernels with four tracers), from runs that time the
     damped and tracer forms next to the plain ones."""
     from collections import defaultdict
     alg = algorithmic_bytes(nc, ne, nv, N, "fp64")
-    stats = rows(os.path.join(src, "prof_dtrace", "dtrace_kernel_stats.csv"))
+    stats = _rows(os.path.join(src, "prof_dtrace", "dtrace_kernel_stats.csv"))
     dur = {}
     for r in stats:
         k, prec = _kernel_id(r["Name"])
         if prec == "fp64" and k in OPTION_KERNELS:
             dur[k] = (float(r["AverageNs"]) / 1e3, int(r["Calls"]))
-    fetch, write = counter("dfetch", "FETCH_SIZE"), counter("dwrite", "WRITE_SIZE")
+    fetch, write = _counter(src, "dfetch", "FETCH_SIZE"), _counter(src, "dwrite", "WRITE_SIZE")
     copy = [k for k in fetch if "copyBuffer" in k]
     cf, cw = fetch[copy[0]][-1], write[copy[0]][-1]
     fs, ws = (1 << 30) / (cf * 1024), (1 << 30) / (cw * 1024)
@@ -1013,9 +1225,15 @@ def damped_summary(src, dst, runs, src_hash, wl, nc, ne, nv, N, rows, counter):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=98)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 48 of the headline's 50-step run; with --config, "
+                         "the workload's own count less the warm-up)")
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", type=int, default=2, choices=[2, 3, 4, 5])
+    ap.add_argument("--headline", type=int, default=5, choices=[2, 5],
+                    help="workload of the value: 5 = R2B8x90 (default), 2 = R2B6x90")
+    ap.add_argument("--config", type=int, default=None, choices=[3, 4, 5],
+                    help="one other workload alone (for its counter passes): 3 = R2B7x90 mixed, "
+                         "4 = the batch of 16, 5 = R2B8x90 mixed")
     ap.add_argument("--timing-steps", type=int, default=4)
     ap.add_argument("--error-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -1028,8 +1246,12 @@ def main():
                          "error table, sequential runs or autotuning), for a hardware-counter pass")
     ap.add_argument("--tiles", type=lambda x: [int(v) for v in x.split(",")], default=[0, 0, 0],
                     help="config 4 with --counters: level tiles lt_edge,lt_cell,lt_vert")
-    ap.add_argument("--forms", default="upwind,damped,tracers",
-                    help="options timed next to the FP64 and mixed forms: upwind, damped, tracers")
+    ap.add_argument("--forms", default="r2b6,config3,config4",
+                    help="other workloads carried in the line's forms: r2b6 (R2B6x90 in both forms "
+                         "with the options), config3 (R2B7x90 mixed with its error after 100 steps), "
+                         "config4 (the batch of 16 against sequential runs); 'none' for none")
+    ap.add_argument("--options", default="upwind,damped,tracers",
+                    help="options timed on the R2B6x90 FP64 step: upwind, damped, tracers; 'none'")
     ap.add_argument("--profile-summary", metavar="DIR",
                     help="reduce the rocprofv3 CSVs under DIR to the summaries in profiles/ and exit")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -1047,8 +1269,14 @@ def main():
     from paper_2511_02021_amd import nhdc
     from paper_2511_02021_amd.inputs import case as CS
     torch.cuda.set_device(0)
-    if args.config == 2:
-        out = bench_default(args, torch, nhdc, CS)
+    if args.forms == "none":
+        args.forms = ""
+    if args.options == "none":
+        args.options = ""
+    if args.config is None:
+        if args.steps is None:
+            args.steps = 48
+        out = bench_headline(args, torch, nhdc, CS)
     elif args.config == 4:
         out = bench_batch(args, torch, nhdc, CS)
     else:
