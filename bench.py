@@ -617,17 +617,32 @@ def bench_batch_form(args, torch, nhdc, CS, stream):
     ms = timed_steps(torch, lambda: b.step(dts, 5, 1, stream), steps, 1, stream)
     for d in ds:
         d.check_finite()
+    # the persistent path: each step's substeps as one cooperative launch
+    b.set_persistent(True)
+    pbest = b.autotune(dts, 5)
+    pms = timed_steps(torch, lambda: b.step(dts, 5, 1, stream), steps, 1, stream)
+    for d in ds:
+        d.check_finite()
+    grid = b.persistent_grid
     b.close()
     for d in ds:
         d.close()
     out = {"value": units / (ms / 1e3), "ms_per_step": ms / steps, "steps": steps,
+           "path": "graph of launches (one launch per kernel over all instances, a step captured once)",
            "instances": [f"R2B{c.grid.k}x{c.n_lev}" for c in cases],
-           "tiles": {"lt_edge": best[0], "lt_cell": best[1], "lt_vert": best[2]},
+           "shapes": {"lt_edge": best[0], "lt_cell": best[1], "lt_vert": best[2],
+                      "block_column": best[3], "block_vertex": best[4]},
            "speedup_vs_sequential_fp64": res["sequential_fp64_ms"] / ms,
            "speedup_vs_sequential_mixed": res["sequential_mixed_ms"] / ms,
-           "sequential_ms": res}
+           "sequential_ms": res,
+           "persistent": {"value": units / (pms / 1e3), "ms_per_step": pms / steps, "grid_blocks": grid,
+                          "shapes": {"lt_edge": pbest[0], "lt_cell": pbest[1], "lt_vert": pbest[2]},
+                          "vs_graph": ms / pms,
+                          "speedup_vs_sequential_fp64": res["sequential_fp64_ms"] / pms,
+                          "speedup_vs_sequential_mixed": res["sequential_mixed_ms"] / pms}}
     log(f"  batch {ms / steps:.3f} ms/step ({out['value']:.4e}); x{out['speedup_vs_sequential_fp64']:.2f} "
-        f"vs sequential fp64, x{out['speedup_vs_sequential_mixed']:.2f} vs sequential mixed")
+        f"vs sequential fp64, x{out['speedup_vs_sequential_mixed']:.2f} vs sequential mixed; "
+        f"persistent {pms / steps:.3f} ms/step on {grid} blocks")
     return out
 
 

@@ -268,12 +268,23 @@ int nhdc_sizes(const nhdc_ctx *ctx, int64_t *n_cells, int64_t *n_edges, int64_t 
  * are tiled separately. */
 int nhdc_set_tiles(nhdc_ctx *ctx, int lt_edge, int lt_cell, int lt_vert);
 
-/* Search the level tiles for this context's grid by timing whole steps of
- * (dt, nsubsteps) on `stream`, keep the fastest, and report it in best[4]
- * = {lt_edge, lt_cell, lt_vert, ms per step}.  The state is saved before and
- * restored after the search.  If cache_path is not NULL it names a JSON file
- * (object of "key": [lt_edge, lt_cell, lt_vert, ms]) that is read first (a
- * hit skips the search) and updated after a search. */
+/* Block sizes (lanes per workgroup: 64, 128 or 256) of the column and the
+ * vertex kernels, the kernels whose work needs no per-block tables; the
+ * others run in blocks of 256.  Results do not depend on them; only speed
+ * does (smaller blocks spread a launch over more workgroups and shorten its
+ * tail).  EINVAL for another size, ESTATE before nhdc_upload_grid. */
+int nhdc_set_block_sizes(nhdc_ctx *ctx, int column, int vertex);
+
+/* The autotuner (the paper tunes its GPU kernels per configuration, Sec.
+ * 3.2; here a search the library runs itself): a coordinate search over the
+ * level tiles and the block sizes of this context's grid, each candidate
+ * timed over whole steps of (dt, nsubsteps) on `stream`; keeps the fastest
+ * and reports it in best[6] = {lt_edge, lt_cell, lt_vert, block_column,
+ * block_vertex, ms per step}.  The state is saved before and restored after
+ * the search.  If cache_path is not NULL it names a JSON file (object of
+ * "key": [lt_edge, lt_cell, lt_vert, block_column, block_vertex, ms], the key
+ * naming the precision, the launch path and the instances' shapes) that is
+ * read first (a hit skips the search) and updated after a search. */
 int nhdc_autotune(nhdc_ctx *ctx, double dt, int nsubsteps, const char *cache_path,
                   double *best, void *stream);
 
@@ -299,7 +310,23 @@ int nhdc_batch_create(nhdc_batch **out, nhdc_ctx *const *instances, int n);
 /* nsteps steps of (dt[i], nsubsteps) for every instance i, enqueued on stream. */
 int nhdc_batch_step(nhdc_batch *b, const double *dt, int nsubsteps, int nsteps, void *stream);
 int nhdc_batch_set_tiles(nhdc_batch *b, int lt_edge, int lt_cell, int lt_vert);
-/* As nhdc_autotune, over the whole batch. */
+/* As nhdc_set_block_sizes, for the batch's launches (not the persistent one). */
+int nhdc_batch_set_block_sizes(nhdc_batch *b, int column, int vertex);
+/* Persistent form (on = 1): each step's substeps run as ONE cooperative
+ * launch over every instance, with as many blocks as the GPU holds at once
+ * (blocks_per_cu > 0 caps the blocks per compute unit below that); its
+ * blocks take each phase's tiles in turn and a grid barrier separates the
+ * phases.  The options' once-per-step work (diffusion, tracers) runs as
+ * launches around it.  Results are bitwise those of the graph of launches.
+ * on = 0 returns to the graph of launches.  EINVAL when an instance's
+ * numbering leaves an edge block with more distinct cells than lanes or
+ * without cell_vt's block tables (the persistent kernel is built for the
+ * numbering along the curve), or without cooperative launch. */
+int nhdc_batch_set_persistent(nhdc_batch *b, int on, int blocks_per_cu);
+/* Blocks of the persistent launch (0 when the batch is not persistent). */
+int nhdc_batch_persistent_grid(const nhdc_batch *b);
+/* As nhdc_autotune, over the whole batch, on its current path (the
+ * persistent path searches the level tiles only). */
 int nhdc_batch_autotune(nhdc_batch *b, const double *dt, int nsubsteps, const char *cache_path,
                         double *best, void *stream);
 const char *nhdc_batch_last_error(const nhdc_batch *b);

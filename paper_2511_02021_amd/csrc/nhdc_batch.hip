@@ -24,6 +24,10 @@ struct nhdc_batch {
     std::vector<double> graph_dt;       // the step the graph holds
     int graph_nsub = 0;
     Tune graph_tune;
+    // persistent form: the substeps of a step as one cooperative launch
+    bool persistent = false;
+    PMaps *d_pm = nullptr;  // the maps in device memory (block size BLOCK for every kind)
+    int grid = 0;           // blocks of the persistent launch
     std::string err;
 };
 
@@ -35,6 +39,29 @@ void drop_graph(nhdc_batch *b) {
     b->exec = nullptr;
     b->graph = nullptr;
     b->graph_dt.clear();
+}
+
+// The persistent launch's maps: the batch's level tiles, every kind in
+// blocks of BLOCK lanes (the one block size of the persistent kernel).
+int upload_pmaps(nhdc_batch *b, const Tune &t) {
+    Tune tp = t;
+    tp.blk_col = tp.blk_vert = BLOCK;
+    Launcher tmp;
+    rebuild_maps(tmp, b->ctxs, tp);
+    PMaps h;
+    for (int k = 0; k < KIND_NUM; ++k) {
+        h.maps[k] = tmp.maps[k];
+        h.nblocks[k] = tmp.nblocks[k];
+    }
+    if (!b->d_pm) {
+        b->d_pm = static_cast<PMaps *>(dev_alloc(b->L.al, sizeof(PMaps)));
+        if (!b->d_pm) return set_err(b->err, NHDC_ENOMEM, "batch: persistent maps: allocation failed");
+    }
+    hipError_t e = hipStreamSynchronize(b->cap);
+    if (e == hipSuccess) e = hipDeviceSynchronize();  // no launch may still read the old maps
+    if (e == hipSuccess) e = hipMemcpy(b->d_pm, &h, sizeof(PMaps), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(b->err, e, "batch: persistent maps");
+    return NHDC_OK;
 }
 
 bool graph_matches(const nhdc_batch *b, const double *dt, int nsub) {
@@ -124,8 +151,15 @@ int nhdc_batch_step(nhdc_batch *b, const double *dt, int nsub, int nsteps, void 
     if (rc) return rc;
     if (nsteps < 0) return set_err(b->err, NHDC_EINVAL, "batch: nsteps must be >= 0");
     if (hipSetDevice(b->device) != hipSuccess) return set_err(b->err, NHDC_EHIP, "batch: hipSetDevice");
-    if (!graph_matches(b, dt, nsub) && (rc = capture(b, dt, nsub))) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (b->persistent) {
+        for (int i = 0; i < nsteps; ++i) {
+            hipError_t e = run_step_persistent(b->L, b->d_pm, b->grid, dt, nsub, s);
+            if (e != hipSuccess) return hip_fail(b->err, e, "batch: persistent launch");
+        }
+        return NHDC_OK;
+    }
+    if (!graph_matches(b, dt, nsub) && (rc = capture(b, dt, nsub))) return rc;
     for (int i = 0; i < nsteps; ++i) {
         hipError_t e = hipGraphLaunch(b->exec, s);
         if (e != hipSuccess) return hip_fail(b->err, e, "batch: hipGraphLaunch");
@@ -141,8 +175,48 @@ int nhdc_batch_set_tiles(nhdc_batch *b, int lt_edge, int lt_cell, int lt_vert) {
     b->tune.lt_cell = lt_cell;
     b->tune.lt_vert = lt_vert;
     rebuild_maps(b->L, b->ctxs, b->tune);
+    return b->persistent ? upload_pmaps(b, b->tune) : NHDC_OK;
+}
+
+int nhdc_batch_set_block_sizes(nhdc_batch *b, int column, int vertex) {
+    if (!b) return NHDC_EINVAL;
+    if (!valid_block(column) || !valid_block(vertex))
+        return set_err(b->err, NHDC_EINVAL, "batch: block sizes must be 64, 128 or 256");
+    b->tune.blk_col = column;
+    b->tune.blk_vert = vertex;
+    rebuild_maps(b->L, b->ctxs, b->tune);
     return NHDC_OK;
 }
+
+int nhdc_batch_set_persistent(nhdc_batch *b, int on, int blocks_per_cu) {
+    if (!b) return NHDC_EINVAL;
+    if (hipSetDevice(b->device) != hipSuccess) return set_err(b->err, NHDC_EHIP, "batch: hipSetDevice");
+    if (!on) {
+        b->persistent = false;
+        return NHDC_OK;
+    }
+    if (blocks_per_cu < 0) return set_err(b->err, NHDC_EINVAL, "batch: blocks_per_cu must be >= 0");
+    if (b->L.vt_two || !b->L.cvt_lds)
+        return set_err(b->err, NHDC_EINVAL,
+                       "batch: the persistent form needs every instance numbered along the curve "
+                       "(edge blocks with at most one distinct cell per lane and cell_vt's block tables)");
+    int coop = 0, ncu = 0, per_cu = 0;
+    hipError_t e = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, b->device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, b->device);
+    if (e == hipSuccess)
+        e = b->L.precision == NHDC_MIXED ? persistent_blocks_per_cu_mixed(b->L, &per_cu)
+                                         : persistent_blocks_per_cu_fp64(b->L, &per_cu);
+    if (e != hipSuccess) return hip_fail(b->err, e, "batch: persistent launch properties");
+    if (!coop || per_cu < 1) return set_err(b->err, NHDC_EINVAL, "batch: no cooperative launch on this device");
+    const int use = blocks_per_cu > 0 && blocks_per_cu < per_cu ? blocks_per_cu : per_cu;
+    int rc = upload_pmaps(b, b->tune);
+    if (rc) return rc;
+    b->grid = use * ncu;
+    b->persistent = true;
+    return NHDC_OK;
+}
+
+int nhdc_batch_persistent_grid(const nhdc_batch *b) { return b && b->persistent ? b->grid : 0; }
 
 int nhdc_batch_autotune(nhdc_batch *b, const double *dt, int nsub, const char *cache_path,
                         double *best, void *stream) {
@@ -151,8 +225,24 @@ int nhdc_batch_autotune(nhdc_batch *b, const double *dt, int nsub, const char *c
     if (rc) return rc;
     if (hipSetDevice(b->device) != hipSuccess) return set_err(b->err, NHDC_EHIP, "batch: hipSetDevice");
     drop_graph(b);
+    Stepper stepper;
+    if (b->persistent) {
+        // the persistent kernel runs every kind in blocks of BLOCK lanes:
+        // only the level tiles are searched
+        stepper.block_sizes = false;
+        stepper.prepare = [b](const Tune &t) -> hipError_t {
+            return upload_pmaps(b, t) == NHDC_OK ? hipSuccess : hipErrorUnknown;
+        };
+        stepper.step = [b](const double *d, int ns, hipStream_t st) {
+            return run_step_persistent(b->L, b->d_pm, b->grid, d, ns, st);
+        };
+    } else {
+        const Launcher &L = b->L;
+        stepper.step = [&L](const double *d, int ns, hipStream_t st) { return run_step(L, d, ns, nullptr, st); };
+    }
     return autotune(b->L, b->tune, b->ctxs, dt, nsub, cache_path, best,
-                    static_cast<hipStream_t>(stream), b->err);
+                    static_cast<hipStream_t>(stream), b->err, stepper,
+                    b->persistent ? "persistent" : "launches");
 }
 
 const char *nhdc_batch_last_error(const nhdc_batch *b) { return b ? b->err.c_str() : "no batch"; }
@@ -163,6 +253,7 @@ void nhdc_batch_destroy(nhdc_batch *b) {
         (void)hipDeviceSynchronize();  // replays still in flight read the descriptors
         drop_graph(b);
         dev_free(b->L.al, b->L.d_insts);
+        dev_free(b->L.al, b->d_pm);
         if (b->cap) (void)hipStreamDestroy(b->cap);
     }
     for (auto *c : b->ctxs) {

@@ -171,16 +171,28 @@ struct Map {
     int32_t lt[MAX_INST] = {0};
 };
 
+// Block maps and tile counts of every kind, in device memory for the
+// persistent launch.
+struct PMaps {
+    Map maps[KIND_NUM];
+    int64_t nblocks[KIND_NUM];
+};
+
 // Per-launch scalars of one substep.
 struct Sub {
     double dt[MAX_INST];
     int32_t nsub, first, last;  // substeps per step; first / last substep of the step
 };
 
-// Level-tile sizes (levels per lane) of the marching kernels; 0 = whole column.
+// Level-tile sizes (levels per lane) of the marching kernels (0 = whole
+// column), and the block sizes of the kernels that take several (the column
+// and vertex kernels: 64, 128 or 256 lanes; the others keep BLOCK, which
+// their per-block tables and LDS arrays are built for).
 struct Tune {
     int lt_edge = 0, lt_cell = 0, lt_vert = 0;
+    int blk_col = BLOCK, blk_vert = BLOCK;
 };
+inline bool valid_block(int b) { return b == 64 || b == 128 || b == 256; }
 
 enum KernelId { K_VT_EDGE = 0, K_VERTEX, K_CELL_VT, K_EDGE_PRED, K_COLUMN_PRED, K_EDGE_CORR,
                 K_COLUMN_CORR, K_CELL_GRAD, K_DIV4, K_SMAG_CELL, K_SMAG_EDGE, K_TR_SAVE,
@@ -222,6 +234,7 @@ struct Launcher {
     bool cvt_lds = false;          // every instance has cell_vt's block tables
     Map maps[KIND_NUM];
     int64_t nblocks[KIND_NUM] = {0};
+    int block[KIND_NUM] = {BLOCK, BLOCK, BLOCK, BLOCK};  // lanes per block of each kind's launches
 };
 
 // kernels (nhdc_fp64.hip / nhdc_mixed.hip)
@@ -234,6 +247,14 @@ hipError_t launch_diffusion_mixed(const Launcher &L, const Sub &sub, Timing *tm,
 // transports over the step (sub.dt: the step's dt per instance)
 hipError_t launch_tracers_fp64(const Launcher &L, const Sub &sub, int phase, Timing *tm, hipStream_t st);
 hipError_t launch_tracers_mixed(const Launcher &L, const Sub &sub, int phase, Timing *tm, hipStream_t st);
+// the persistent form of a batch step's substeps: one cooperative launch of
+// `grid` blocks (sub.nsub substeps); and how many of its blocks a CU holds
+hipError_t launch_persistent_fp64(const Launcher &L, const PMaps *d_pm, const Sub &sub, int grid,
+                                  hipStream_t st);
+hipError_t launch_persistent_mixed(const Launcher &L, const PMaps *d_pm, const Sub &sub, int grid,
+                                   hipStream_t st);
+hipError_t persistent_blocks_per_cu_fp64(const Launcher &L, int *blocks);
+hipError_t persistent_blocks_per_cu_mixed(const Launcher &L, int *blocks);
 // set-up and diagnostics (nhdc_util.hip)
 hipError_t launch_metrics(const Grid &g, hipStream_t st);
 // out[i] |= 1 where row i of the [nlev][n] array a has an entry whose bits
@@ -252,9 +273,10 @@ hipError_t launch_exner_x(const Grid &g, const State &s, double eps, hipStream_t
 // timing helpers (nhdc_runtime.hip); no-ops when tm is null or off
 hipError_t timing_begin(Timing *tm, int id, hipStream_t st);
 hipError_t timing_end(Timing *tm, hipStream_t st);
-// block map of one kind over a set of grids
+// block map of one kind over a set of grids, with that kind's block size
 void build_map(Map &m, int64_t &nblocks, Kind kind, const Grid *const *grids, int n,
                const Tune &t);
+int kind_block(Kind kind, const Tune &t);
 
 }  // namespace nhdc
 

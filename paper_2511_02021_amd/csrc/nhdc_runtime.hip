@@ -99,11 +99,35 @@ hipError_t run_step(const Launcher &L, const double *dt, int nsub, Timing *tm, h
     return hipSuccess;
 }
 
+hipError_t run_step_persistent(const Launcher &L, const PMaps *d_pm, int grid, const double *dt,
+                               int nsub, hipStream_t st) {
+    Sub sub;
+    for (int i = 0; i < L.n; ++i) sub.dt[i] = dt[i] / nsub;
+    for (int i = L.n; i < MAX_INST; ++i) sub.dt[i] = 0.0;
+    sub.nsub = nsub;
+    sub.first = 1;
+    sub.last = nsub == 1;
+    Sub whole = sub;
+    for (int i = 0; i < L.n; ++i) whole.dt[i] = dt[i];
+    const bool mixed = L.precision == NHDC_MIXED;
+    hipError_t e = hipSuccess;
+    if (L.tracers) e = mixed ? launch_tracers_mixed(L, whole, 0, nullptr, st) : launch_tracers_fp64(L, whole, 0, nullptr, st);
+    if (e != hipSuccess) return e;
+    e = mixed ? launch_persistent_mixed(L, d_pm, sub, grid, st) : launch_persistent_fp64(L, d_pm, sub, grid, st);
+    if (e != hipSuccess) return e;
+    if (L.smag) e = mixed ? launch_diffusion_mixed(L, whole, nullptr, st) : launch_diffusion_fp64(L, whole, nullptr, st);
+    if (e != hipSuccess) return e;
+    if (L.tracers) e = mixed ? launch_tracers_mixed(L, whole, 1, nullptr, st) : launch_tracers_fp64(L, whole, 1, nullptr, st);
+    return e;
+}
+
 void rebuild_maps(Launcher &L, const std::vector<nhdc_ctx *> &ctxs, const Tune &t) {
     std::vector<const Grid *> grids;
     for (auto *c : ctxs) grids.push_back(&c->g);
-    for (int k = 0; k < KIND_NUM; ++k)
+    for (int k = 0; k < KIND_NUM; ++k) {
         build_map(L.maps[k], L.nblocks[k], Kind(k), grids.data(), int(grids.size()), t);
+        L.block[k] = kind_block(Kind(k), t);
+    }
 }
 
 // The descriptor of one instance in the precision of its work arrays.
@@ -200,8 +224,10 @@ static int snapshot(const Allocator &al, const std::vector<nhdc_ctx *> &ctxs,
     return NHDC_OK;
 }
 
-// ---- JSON cache: one entry per line, "key": [lt_edge, lt_cell, lt_vert, ms] ----
-static bool cache_lookup(const char *path, const std::string &key, double best[4]) {
+// ---- JSON cache: one entry per line,
+// "key": [lt_edge, lt_cell, lt_vert, block_column, block_vertex, ms] ----
+constexpr int kBest = 6;
+static bool cache_lookup(const char *path, const std::string &key, double best[kBest]) {
     if (!path) return false;
     std::ifstream f(path);
     if (!f) return false;
@@ -215,14 +241,14 @@ static bool cache_lookup(const char *path, const std::string &key, double best[4
         for (char &ch : body)
             if (ch == ',') ch = ' ';
         std::istringstream is(body);
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < kBest; ++i)
             if (!(is >> best[i])) return false;
-        return true;
+        return valid_block(int(best[3])) && valid_block(int(best[4]));
     }
     return false;
 }
 
-static void cache_store(const char *path, const std::string &key, const double best[4]) {
+static void cache_store(const char *path, const std::string &key, const double best[kBest]) {
     if (!path) return;
     std::vector<std::string> entries;
     {
@@ -235,8 +261,8 @@ static void cache_store(const char *path, const std::string &key, const double b
         }
     }
     char buf[512];
-    std::snprintf(buf, sizeof(buf), "  \"%s\": [%d, %d, %d, %.6f]", key.c_str(), int(best[0]),
-                  int(best[1]), int(best[2]), best[3]);
+    std::snprintf(buf, sizeof(buf), "  \"%s\": [%d, %d, %d, %d, %d, %.6f]", key.c_str(), int(best[0]),
+                  int(best[1]), int(best[2]), int(best[3]), int(best[4]), best[5]);
     entries.push_back(buf);
     std::ofstream f(path, std::ios::trunc);
     f << "{\n";
@@ -247,20 +273,27 @@ static void cache_store(const char *path, const std::string &key, const double b
 
 int autotune(Launcher &L, Tune &tune, const std::vector<nhdc_ctx *> &ctxs, const double *dt,
              int nsub, const char *cache_path, double *best_out, hipStream_t st,
-             std::string &err) {
+             std::string &err, const Stepper &stepper, const char *path_tag) {
     std::ostringstream ks;
-    ks << (L.precision == NHDC_MIXED ? "mixed" : "fp64") << "|b" << BLOCK << "|";
+    ks << (L.precision == NHDC_MIXED ? "mixed" : "fp64") << "|" << path_tag << "|";
     for (size_t i = 0; i < ctxs.size(); ++i)
         ks << (i ? "," : "") << ctxs[i]->g.nc << "x" << ctxs[i]->g.N;
     const std::string key = ks.str();
-    double best[4];
+    double best[kBest];
+    auto apply = [&](const Tune &t) -> hipError_t {
+        rebuild_maps(L, ctxs, t);
+        return stepper.prepare ? stepper.prepare(t) : hipSuccess;
+    };
     if (cache_lookup(cache_path, key, best)) {
         tune.lt_edge = int(best[0]);
         tune.lt_cell = int(best[1]);
         tune.lt_vert = int(best[2]);
-        rebuild_maps(L, ctxs, tune);
+        tune.blk_col = int(best[3]);
+        tune.blk_vert = int(best[4]);
+        hipError_t e = apply(tune);
+        if (e != hipSuccess) return hip_fail(err, e, "autotune: set-up");
         if (best_out)
-            for (int i = 0; i < 4; ++i) best_out[i] = best[i];
+            for (int i = 0; i < kBest; ++i) best_out[i] = best[i];
         return NHDC_OK;
     }
     std::vector<void *> snap;
@@ -272,10 +305,10 @@ int autotune(Launcher &L, Tune &tune, const std::vector<nhdc_ctx *> &ctxs, const
         return set_err(err, NHDC_EHIP, "autotune: hipEventCreate failed");
     }
     auto measure = [&](const Tune &t, double &ms) -> int {
-        rebuild_maps(L, ctxs, t);
-        hipError_t e = run_step(L, dt, nsub, nullptr, st);  // warm-up
+        hipError_t e = apply(t);
+        if (e == hipSuccess) e = stepper.step(dt, nsub, st);  // warm-up
         if (e == hipSuccess) e = hipEventRecord(e0, st);
-        for (int r = 0; r < 2 && e == hipSuccess; ++r) e = run_step(L, dt, nsub, nullptr, st);
+        for (int r = 0; r < 2 && e == hipSuccess; ++r) e = stepper.step(dt, nsub, st);
         if (e == hipSuccess) e = hipEventRecord(e1, st);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         float f = 0.f;
@@ -284,17 +317,23 @@ int autotune(Launcher &L, Tune &tune, const std::vector<nhdc_ctx *> &ctxs, const
         ms = f / 2.0;
         return NHDC_OK;
     };
+    // coordinate search: each parameter in turn over its candidates, keeping
+    // the best so far (level tiles of edges, cells, vertices; block sizes of
+    // the column and vertex kernels, when the path takes them)
     Tune bt = tune;
     double bms = 0.0;
     rc = measure(bt, bms);
     const int cand_ec[] = {0, 48, 32, 16, 8};
     const int cand_v[] = {0, 32, 16};
-    for (int param = 0; param < 3 && !rc; ++param) {
-        const int *cand = param < 2 ? cand_ec : cand_v;
+    const int cand_b[] = {256, 128, 64};
+    const int nparam = stepper.block_sizes ? 5 : 3;
+    for (int param = 0; param < nparam && !rc; ++param) {
+        const int *cand = param < 2 ? cand_ec : param == 2 ? cand_v : cand_b;
         const int ncand = param < 2 ? 5 : 3;
         for (int q = 0; q < ncand; ++q) {
             Tune t = bt;
-            int &slot = param == 0 ? t.lt_edge : param == 1 ? t.lt_cell : t.lt_vert;
+            int &slot = param == 0 ? t.lt_edge : param == 1 ? t.lt_cell : param == 2 ? t.lt_vert
+                      : param == 3 ? t.blk_col : t.blk_vert;
             if (slot == cand[q]) continue;
             slot = cand[q];
             double ms = 0.0;
@@ -312,14 +351,17 @@ int autotune(Launcher &L, Tune &tune, const std::vector<nhdc_ctx *> &ctxs, const
     if (rc) return rc;
     if (rc2) return set_err(err, rc2, err2);
     tune = bt;
-    rebuild_maps(L, ctxs, tune);
+    hipError_t e = apply(tune);
+    if (e != hipSuccess) return hip_fail(err, e, "autotune: set-up");
     best[0] = tune.lt_edge;
     best[1] = tune.lt_cell;
     best[2] = tune.lt_vert;
-    best[3] = bms;
+    best[3] = tune.blk_col;
+    best[4] = tune.blk_vert;
+    best[5] = bms;
     cache_store(cache_path, key, best);
     if (best_out)
-        for (int i = 0; i < 4; ++i) best_out[i] = best[i];
+        for (int i = 0; i < kBest; ++i) best_out[i] = best[i];
     return NHDC_OK;
 }
 
@@ -874,6 +916,18 @@ int nhdc_step(nhdc_ctx *ctx, double dt, int nsub, void *stream) {
     return timing_collect(ctx, s);
 }
 
+int nhdc_set_block_sizes(nhdc_ctx *ctx, int column, int vertex) {
+    if (!ctx) return NHDC_EINVAL;
+    if (!ctx->grid_ready) return set_err(ctx, NHDC_ESTATE, "set_block_sizes: no grid uploaded");
+    if (!valid_block(column) || !valid_block(vertex))
+        return set_err(ctx, NHDC_EINVAL, "set_block_sizes: block sizes must be 64, 128 or 256");
+    ctx->tune.blk_col = column;
+    ctx->tune.blk_vert = vertex;
+    std::vector<nhdc_ctx *> one{ctx};
+    rebuild_maps(ctx->L, one, ctx->tune);
+    return NHDC_OK;
+}
+
 int nhdc_set_tiles(nhdc_ctx *ctx, int lt_edge, int lt_cell, int lt_vert) {
     if (!ctx) return NHDC_EINVAL;
     if (!ctx->grid_ready) return set_err(ctx, NHDC_ESTATE, "set_tiles: no grid uploaded");
@@ -895,8 +949,11 @@ int nhdc_autotune(nhdc_ctx *ctx, double dt, int nsub, const char *cache_path, do
     if (!ctx->state_ready) return set_err(ctx, NHDC_ESTATE, "autotune: state not initialised");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     std::vector<nhdc_ctx *> one{ctx};
+    Stepper stepper;
+    const Launcher &L = ctx->L;
+    stepper.step = [&L](const double *d, int ns, hipStream_t st) { return run_step(L, d, ns, nullptr, st); };
     return autotune(ctx->L, ctx->tune, one, &dt, nsub, cache_path, best,
-                    static_cast<hipStream_t>(stream), ctx->err);
+                    static_cast<hipStream_t>(stream), ctx->err, stepper, "launches");
 }
 
 int nhdc_get_state(nhdc_ctx *ctx, const nhdc_state_view *dst, void *stream) {

@@ -206,8 +206,14 @@ const char *const kKernelNames[K_NUM] = {"vt_edge",   "vertex",      "cell_vt",
                                          "smag_cell",   "smag_edge",   "tr_save",
                                          "tr_recon",    "tr_horiz",    "tr_vert"};
 
+int kind_block(Kind kind, const Tune &t) {
+    const int b = kind == KIND_COLUMN ? t.blk_col : kind == KIND_VERT ? t.blk_vert : BLOCK;
+    return valid_block(b) ? b : BLOCK;
+}
+
 void build_map(Map &m, int64_t &nblocks, Kind kind, const Grid *const *grids, int n,
                const Tune &t) {
+    const int64_t B = kind_block(kind, t);
     m.n = n;
     m.off[0] = 0;
     for (int i = 0; i < n; ++i) {
@@ -216,7 +222,7 @@ void build_map(Map &m, int64_t &nblocks, Kind kind, const Grid *const *grids, in
         int lt = kind == KIND_EDGE ? t.lt_edge : kind == KIND_VERT ? t.lt_vert
                : kind == KIND_CELL ? t.lt_cell : 0;
         if (lt <= 0 || lt > g.N) lt = g.N;
-        int64_t nbe = (ent + BLOCK - 1) / BLOCK;
+        int64_t nbe = (ent + B - 1) / B;
         int64_t tiles = (g.N + lt - 1) / lt;
         m.nbe[i] = int32_t(nbe);
         m.lt[i] = lt;

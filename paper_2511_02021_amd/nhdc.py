@@ -25,7 +25,8 @@ EXPORTS = ("nhdc_create", "nhdc_upload_grid", "nhdc_init_state", "nhdc_step", "n
            "nhdc_kernel_stats", "nhdc_last_error", "nhdc_destroy", "nhdc_batch_create",
            "nhdc_batch_step", "nhdc_batch_set_tiles", "nhdc_batch_autotune",
            "nhdc_batch_last_error", "nhdc_batch_destroy", "nhdc_set_tracers", "nhdc_get_tracers",
-           "nhdc_n_tracers", "nhdc_diag_noalloc", "nhdc_set_allocator")
+           "nhdc_n_tracers", "nhdc_diag_noalloc", "nhdc_set_allocator", "nhdc_set_block_sizes",
+           "nhdc_batch_set_block_sizes", "nhdc_batch_set_persistent", "nhdc_batch_persistent_grid")
 
 
 class NhdcError(RuntimeError):
@@ -125,6 +126,10 @@ def lib():
         L.nhdc_check_finite.argtypes = [vp, vp]
         L.nhdc_sizes.argtypes = [vp] + [vp] * 4
         L.nhdc_set_tiles.argtypes = [vp, i, i, i]
+        L.nhdc_set_block_sizes.argtypes = [vp, i, i]
+        L.nhdc_batch_set_block_sizes.argtypes = [vp, i, i]
+        L.nhdc_batch_set_persistent.argtypes = [vp, i, i]
+        L.nhdc_batch_persistent_grid.argtypes = [vp]
         L.nhdc_autotune.argtypes = [vp, d, i, C.c_char_p, C.POINTER(d), vp]
         L.nhdc_batch_create.argtypes = [C.POINTER(vp), C.POINTER(vp), i]
         L.nhdc_batch_step.argtypes = [vp, C.POINTER(d), i, i, vp]
@@ -319,14 +324,19 @@ class Dycore:
         """Levels per lane of the marching kernels (0 = whole column)."""
         self._check(self.L.nhdc_set_tiles(self.h, int(lt_edge), int(lt_cell), int(lt_vert)))
 
+    def set_block_sizes(self, column=256, vertex=256):
+        """Lanes per block of the column and vertex kernels (64, 128, 256)."""
+        self._check(self.L.nhdc_set_block_sizes(self.h, int(column), int(vertex)))
+
     def autotune(self, dt, nsub, cache_path=None, stream=None):
-        """Search the level tiles by timing whole steps; the state is restored.
-        Returns (lt_edge, lt_cell, lt_vert, ms_per_step)."""
-        best = (C.c_double * 4)()
+        """Search the level tiles and block sizes by timing whole steps; the
+        state is restored.  Returns (lt_edge, lt_cell, lt_vert, block_column,
+        block_vertex, ms_per_step)."""
+        best = (C.c_double * 6)()
         path = cache_path.encode() if cache_path else None
         self._check(self.L.nhdc_autotune(self.h, float(dt), int(nsub), path, best,
                                          _stream_ptr(stream)))
-        return int(best[0]), int(best[1]), int(best[2]), best[3]
+        return tuple(int(x) for x in best[:5]) + (best[5],)
 
     def set_timing(self, on):
         self._check(self.L.nhdc_set_timing(self.h, int(bool(on))))
@@ -393,12 +403,24 @@ class Batch:
     def set_tiles(self, lt_edge=0, lt_cell=0, lt_vert=0):
         self._check(self.L.nhdc_batch_set_tiles(self.h, int(lt_edge), int(lt_cell), int(lt_vert)))
 
+    def set_block_sizes(self, column=256, vertex=256):
+        self._check(self.L.nhdc_batch_set_block_sizes(self.h, int(column), int(vertex)))
+
+    def set_persistent(self, on=True, blocks_per_cu=0):
+        """Run each step's substeps as one persistent cooperative launch."""
+        self._check(self.L.nhdc_batch_set_persistent(self.h, int(bool(on)), int(blocks_per_cu)))
+
+    @property
+    def persistent_grid(self):
+        return self.L.nhdc_batch_persistent_grid(self.h)
+
     def autotune(self, dt, nsub, cache_path=None, stream=None):
-        best = (C.c_double * 4)()
+        """As Dycore.autotune, over the batch on its current path."""
+        best = (C.c_double * 6)()
         path = cache_path.encode() if cache_path else None
         self._check(self.L.nhdc_batch_autotune(self.h, self._dts(dt), int(nsub), path, best,
                                                _stream_ptr(stream)))
-        return int(best[0]), int(best[1]), int(best[2]), best[3]
+        return tuple(int(x) for x in best[:5]) + (best[5],)
 
     def close(self):
         if getattr(self, "h", None):

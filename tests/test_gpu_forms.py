@@ -132,11 +132,12 @@ def test_autotune_restores_state_and_caches(tmp_path):
     after = d.get_state()
     for f in FIELDS:
         assert np.array_equal(before[f], after[f]), f
-    assert all(t in (0, 48, 32, 16, 8) for t in best[:3]) and best[3] > 0
+    assert all(t in (0, 48, 32, 16, 8) for t in best[:3]) and best[5] > 0
+    assert best[3] in (64, 128, 256) and best[4] in (64, 128, 256)
     txt = open(path).read()
-    assert "fp64|b256|" in txt and str(c.grid.n_cells) in txt
+    assert "fp64|launches|" in txt and str(c.grid.n_cells) in txt
     again = d.autotune(c.dt, 5, cache_path=path)   # cache hit: same tiles, no search
-    assert again[:3] == best[:3] and abs(again[3] - best[3]) < 1e-5
+    assert again[:5] == best[:5] and abs(again[5] - best[5]) < 1e-5
     d.step(c.dt, 5)
     ref, _, _ = _run(c, 2)
     s = d.get_state()
