@@ -52,8 +52,11 @@ def algorithmic_bytes(nc, ne, nv, N, prec="fp64", nsub=5, nt=4):
     register-carried levels and column scratch round trips not counted).
     Tendency-side arrays are FP32 in the mixed form; state, fluxes and the
     column are FP64 in both.  The Exner history is written on the last of
-    `nsub` substeps only, so it counts 1/nsub per corrector column launch."""
+    `nsub` substeps only, so it counts 1/nsub per corrector column launch.
+    The stored normal velocity (vn, and the predicted vn*) takes 4 bytes in
+    the mixed_vn32 variant, 8 otherwise."""
     r = 8 if prec == "fp64" else 4
+    vb = 4 if prec == "mixed_vn32" else 8
     C, C1, Ci = N * nc, (N + 1) * nc, (N - 1) * nc        # entity-level counts
     E, V, V1, Vi = N * ne, N * nv, (N + 1) * nv, (N - 1) * nv
     gc = nc * 3 * (4 + 4 + 4 + r) + nc * r                 # c_e, c_n, c_v, c_sl; area
@@ -61,19 +64,19 @@ def algorithmic_bytes(nc, ne, nv, N, prec="fp64", nsub=5, nt=4):
     gv = nv * 6 * (4 + 4 + r + r) + 2 * nv * r
     recon = 2 * ne * (3 * 4 + 16 * r) + 3 * ne * r         # two cells' reconstruction coeffs + tangent
     t = {
-        "vt_edge": [E * 8 + E * r + recon],
-        "vertex": [E * 8 + Ci * 8 + V * r + Vi * r + gv],
+        "vt_edge": [E * vb + E * r + recon],
+        "vertex": [E * vb + Ci * 8 + V * r + Vi * r + gv],
         # vn, vt, w, wv, zh, zhv -> kc, wcc, tw (+ div vn in the corrector)
-        "cell_vt": [E * 8 + E * r + C1 * 8 + Vi * r + C1 * 8 + V1 * 8 + C * r + 2 * C1 * r + gc + ge,
-                    E * 8 + E * r + C1 * 8 + Vi * r + C1 * 8 + V1 * 8 + 2 * C * r + 2 * C1 * r + gc + ge],
+        "cell_vt": [E * vb + E * r + C1 * 8 + Vi * r + C1 * 8 + V1 * 8 + C * r + 2 * C1 * r + gc + ge,
+                    E * vb + E * r + C1 * 8 + Vi * r + C1 * 8 + V1 * 8 + 2 * C * r + 2 * C1 * r + gc + ge],
         # kc, zeta, vt, vn, w, wcc, px, thv, zh -> tvn, vns
-        "edge_pred": [C * r + V * r + E * r + E * 8 + C1 * 8 + C1 * r + 2 * C * 8 + C1 * 8
-                      + E * r + E * 8 + ge],
+        "edge_pred": [C * r + V * r + E * r + E * vb + C1 * 8 + C1 * r + 2 * C * 8 + C1 * 8
+                      + E * r + E * vb + ge],
         # kc, zeta, vt, vns, ws, wcc1, thvs, tvn0, px, dvn, vn, thv, rho, zh, facc -> vn, flx, hfl, facc
-        "edge_corr": [C * r + V * r + E * r + E * 8 + C1 * 8 + C1 * r + C * 8 + E * r + C * 8 + C * r
-                      + E * 8 + 2 * C * 8 + C1 * 8 + E * 8 + 4 * E * 8 + ge],
+        "edge_corr": [C * r + V * r + E * r + E * vb + C1 * 8 + C1 * r + C * 8 + E * r + C * 8 + C * r
+                      + E * vb + 2 * C * 8 + C1 * 8 + E * 8 + E * vb + 3 * E * 8 + ge],
         # vns, rho, thv, pi, pi_ref, theta_ref, w, wcc, tw, zh -> ws, rhos, thvs
-        "column_pred": [E * 8 + 5 * C * 8 + C1 * 8 + 2 * C1 * r + C1 * 8 + 2 * C * 8 + gc],
+        "column_pred": [E * vb + 5 * C * 8 + C1 * 8 + 2 * C1 * r + C1 * 8 + 2 * C * 8 + gc],
         # flx, hfl, rho, thv, pi, pi_ref, theta_ref, w, rhos, thvs, wcc1, tw0, tw1, zh, wacc
         #   -> w, rho, thv, pi, px, wacc (+ pi_prev on the last substep)
         "column_corr": [2 * E * 8 + 5 * C * 8 + C1 * 8 + 2 * C * 8 + 3 * C1 * r + C1 * 8 + C1 * 8
@@ -384,7 +387,7 @@ def time_form(args, torch, nhdc, case, prec, stream, steps=None, warmup=None, ta
     return out
 
 
-def error_table_device(torch, nhdc, case, steps):
+def error_table_device(torch, nhdc, case, steps, precision="mixed"):
     """Per field: E = rel-L2(mixed - FP64), S = rel-L2 between two FP64 runs
     whose initial states differ by seeded relative noise 2^-24 (the
     FP32-rounding floor), after `steps` steps from the initial state.  The
@@ -404,7 +407,7 @@ def error_table_device(torch, nhdc, case, steps):
         return {f: out[f] for f in FIELDS}
 
     f64 = run("fp64")
-    mix = run("mixed")
+    mix = run(precision)
     gen = torch.Generator(device=dev)
     gen.manual_seed(7)
     pert = {f: v * (1.0 + 2.0 ** -24 * torch.randn(v.shape, generator=gen, device=dev,
@@ -487,6 +490,7 @@ def bench_headline(args, torch, nhdc, CS):
     units_per_step = g.n_cells * case.n_lev * case.nsub
     log(f"case R2B{g.k}x{case.n_lev}: {g.n_cells} cells, {g.n_edges} edges ({time.time() - t0:.1f}s)")
     forms, tables = {}, {}
+    want = [f for f in args.forms.split(",") if f]
     for prec in ("fp64", "mixed"):
         forms[prec] = time_form(args, torch, nhdc, case, prec, stream)
         tables[prec] = forms[prec].pop("_table")
@@ -497,6 +501,17 @@ def bench_headline(args, torch, nhdc, CS):
         log(f"per-field error of the mixed form, {args.error_steps} steps ...")
         forms["mixed"]["per_field_error"] = error_table_device(torch, nhdc, case, args.error_steps)
         forms["mixed"]["error_steps"] = args.error_steps
+    if "vn32" in want:  # the mixed form's variant with vn stored in FP32
+        r = time_form(args, torch, nhdc, case, "mixed_vn32", stream)
+        tab = r.pop("_table")
+        r["speedup_vs_fp64"] = forms["fp64"]["ms_per_step"] / r["ms_per_step"]
+        r["speedup_vs_mixed"] = forms["mixed"]["ms_per_step"] / r["ms_per_step"]
+        r["kernels"] = short_table(tab)
+        log(f"mixed_vn32: {r['ms_per_step']:.3f} ms/step, {r['value']:.4e} cell-level updates/s")
+        if args.error_steps > 0:
+            r["per_field_error"] = error_table_device(torch, nhdc, case, args.error_steps, "mixed_vn32")
+            r["error_steps"] = args.error_steps
+        forms["mixed_vn32"] = r
     src_hash = kernel_source_hash()
     kern = tables["fp64"]
     for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["share"]):
@@ -525,12 +540,11 @@ def bench_headline(args, torch, nhdc, CS):
     workload = (f"R2B{g.k} ({g.n_cells} cells) x {case.n_lev} levels to 75 km, terrain, "
                 f"dt={case.dt:g}s, {case.nsub} substeps, FP64 plain")
     del case
-    want = [f for f in args.forms.split(",") if f]
     if "r2b6" in want and cfg != 2:  # the R2B6x90 workload: both forms and the options
         c2 = CS.config_case(2, order=args.order)
         log("R2B6x90 ...")
         r6 = {}
-        for prec in ("fp64", "mixed"):
+        for prec in ("fp64", "mixed") + (("mixed_vn32",) if "vn32" in want else ()):
             r6[prec] = time_form(args, torch, nhdc, c2, prec, stream)
             r6[prec]["kernels"] = short_table(r6[prec].pop("_table"))
             log(f"  {prec}: {r6[prec]['ms_per_step']:.3f} ms/step, {r6[prec]['value']:.4e}")
@@ -540,6 +554,13 @@ def bench_headline(args, torch, nhdc, CS):
     elif cfg == 2:
         forms.update(options_forms(args, torch, nhdc, CS, CS.config_case(2, order=args.order), stream,
                                    forms["fp64"]["ms_per_step"]))
+    if "config1" in want:  # the small flat case: its working set fits the 256 MB Infinity Cache
+        c1 = CS.config_case(1, order=args.order)
+        r1 = time_form(args, torch, nhdc, c1, "fp64", stream, steps=20, warmup=2, table=False)
+        r1["workload"] = "R2B4 (20480 cells) x 20 levels to 30 km, flat, dt=300s, 5 substeps, FP64 plain"
+        r1["steps"] = 20
+        forms["config1_r2b4x20"] = r1
+        log(f"R2B4x20 fp64: {r1['ms_per_step']:.3f} ms/step ({r1['value']:.4e})")
     if "config3" in want:
         log("R2B7x90 mixed ...")
         forms["config3_r2b7x90_mixed"] = bench_config3(args, torch, nhdc, CS, stream)
@@ -631,7 +652,7 @@ def bench_batch_form(args, torch, nhdc, CS, stream):
            "path": "graph of launches (one launch per kernel over all instances, a step captured once)",
            "instances": [f"R2B{c.grid.k}x{c.n_lev}" for c in cases],
            "shapes": {"lt_edge": best[0], "lt_cell": best[1], "lt_vert": best[2],
-                      "block_column": best[3], "block_vertex": best[4]},
+                      "block_column": best[3], "block_vertex": best[4], "column_waves": best[5]},
            "speedup_vs_sequential_fp64": res["sequential_fp64_ms"] / ms,
            "speedup_vs_sequential_mixed": res["sequential_mixed_ms"] / ms,
            "sequential_ms": res,
@@ -771,7 +792,9 @@ def _prof_cmds(tag, extra):
     """rocprofv3 commands of one profiled workload: a kernel trace, then one
     FETCH_SIZE and one WRITE_SIZE pass over a short run that ends with the
     calibration copy."""
-    base = "python3 -u bench.py --forms none --error-steps 0 --no-cpu-baseline" + extra
+    base = "python3 -u bench.py --error-steps 0 --no-cpu-baseline" + extra
+    if "--forms" not in extra:
+        base += " --forms none"
     return {
         "trace": f"rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_{tag}trace "
                  f"-o {tag}trace -- {base} --steps 10 --warmup 2 --timing-steps 4 "
@@ -789,7 +812,7 @@ def _prof_cmds(tag, extra):
 # R2B6x90 step with the upwind option next to it; the R2B6x90 damped and
 # tracer forms (the kernels only the options run)
 PROFILE_SETS = {
-    "h": {"tag": "r2b8x90", "cmds": _prof_cmds("h", " --headline 5 --options none")},
+    "h": {"tag": "r2b8x90", "cmds": _prof_cmds("h", " --headline 5 --options none --forms vn32")},
     "s": {"tag": "r2b6x90", "cmds": _prof_cmds("s", " --headline 2 --options upwind")},
     "d": {"tag": "r2b6x90", "cmds": _prof_cmds("d", " --headline 2 --options damped,tracers")},
 }
@@ -843,6 +866,7 @@ def _kernel_id(name):
     if not m:
         return None, None
     k = m.group(1)
+    form = "fp64" if m.group(2) == "double" else ("mixed_vn32" if "vn32::" in name else "mixed")
     flags = re.findall(r"true|false", m.group(3))
     upwind = k == "cell_grad"
     if k == "column":  # flags: corrector, upwind build, sponge build
@@ -854,7 +878,7 @@ def _kernel_id(name):
         upwind = flags[0] == "true"
     if upwind and k != "cell_grad":
         k += "_upwind"
-    return k, ("fp64" if m.group(2) == "double" else "mixed")
+    return k, form
 
 
 def _cell_vt_phase(name):
@@ -929,22 +953,23 @@ def summarise_set(src, dst, key, tag):
              f"command: {cmds['trace']}",
              f"summarised by: python3 bench.py --profile-summary gpurun_out",
              "", "## per instantiation (rocprofv3 --stats)",
-             f"{'kernel':24s} {'form':6s} {'calls':>6s} {'avg_us':>9s} {'min_us':>9s} {'max_us':>9s} {'share%':>7s}"]
+             f"{'kernel':24s} {'form':10s} {'calls':>6s} {'avg_us':>9s} {'min_us':>9s} {'max_us':>9s} {'share%':>7s}"]
     agg = defaultdict(lambda: [0.0, 0])
     for r in stats:
         k, prec = _kernel_id(r["Name"])
         if not k:
             continue
         var = f"cell_vt({_cell_vt_phase(r['Name'])})" if k == "cell_vt" else k
-        lines.append(f"{var:24s} {prec:6s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:9.2f} "
+        lines.append(f"{var:24s} {prec:10s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:9.2f} "
                      f"{float(r['MinNs']) / 1e3:9.2f} {float(r['MaxNs']) / 1e3:9.2f} "
                      f"{float(r['Percentage']):7.2f}")
         agg[(k, prec)][0] += float(r["TotalDurationNs"])
         agg[(k, prec)][1] += int(r["Calls"])
     lines += ["", "## per kernel id, against the HIP-event averages bench.py measured in the same run",
-              f"{'kernel':14s} {'form':6s} {'rocprof_avg_us':>15s} {'hip_event_avg_us':>17s} {'diff%':>7s}"]
+              f"{'kernel':14s} {'form':10s} {'rocprof_avg_us':>15s} {'hip_event_avg_us':>17s} {'diff%':>7s}"]
     ev = {"fp64": dict(runs["trace"]["kernels"]),
-          "mixed": runs["trace"]["forms"]["mixed"].get("kernels", {})}
+          "mixed": runs["trace"]["forms"]["mixed"].get("kernels", {}),
+          "mixed_vn32": runs["trace"]["forms"].get("mixed_vn32", {}).get("kernels", {})}
     for k, v in runs["trace"]["forms"].get("fp64_upwind", {}).get("kernels", {}).items():
         if k == "cell_grad" or k in ("edge_pred", "edge_corr", "column_pred", "column_corr"):
             ev["fp64"][k if k == "cell_grad" else k + "_upwind"] = v
@@ -952,9 +977,9 @@ def summarise_set(src, dst, key, tag):
         a = tot / n / 1e3
         e = ev.get(prec, {}).get(k, {}).get("avg_ms")
         if e is None:
-            lines.append(f"{k:14s} {prec:6s} {a:15.2f} {'-':>17s} {'-':>7s}")
+            lines.append(f"{k:14s} {prec:10s} {a:15.2f} {'-':>17s} {'-':>7s}")
         else:
-            lines.append(f"{k:14s} {prec:6s} {a:15.2f} {e * 1e3:17.2f} {100 * (a / (e * 1e3) - 1):7.2f}")
+            lines.append(f"{k:14s} {prec:10s} {a:15.2f} {e * 1e3:17.2f} {100 * (a / (e * 1e3) - 1):7.2f}")
     os.makedirs(dst, exist_ok=True)
     with open(os.path.join(dst, f"dycore_{tag}_kernel_trace.txt"), "w") as f:
         f.write("\n".join(lines) + "\n")
@@ -964,7 +989,7 @@ def summarise_set(src, dst, key, tag):
     # the calibration copy is the last device copy of the profiled run
     cf, cw = fetch[copy[0]][-1], write[copy[0]][-1]
     fs, ws = (1 << 30) / (cf * 1024), (1 << 30) / (cw * 1024)
-    for prec in ("fp64", "mixed"):
+    for prec in ("fp64", "mixed", "mixed_vn32"):
         alg = algorithmic_bytes(nc, ne, nv, N, prec)
         per = defaultdict(lambda: [[], []])
         for kname, vals in fetch.items():
@@ -1261,8 +1286,10 @@ def main():
                          "error table, sequential runs or autotuning), for a hardware-counter pass")
     ap.add_argument("--tiles", type=lambda x: [int(v) for v in x.split(",")], default=[0, 0, 0],
                     help="config 4 with --counters: level tiles lt_edge,lt_cell,lt_vert")
-    ap.add_argument("--forms", default="r2b6,config3,config4",
-                    help="other workloads carried in the line's forms: r2b6 (R2B6x90 in both forms "
+    ap.add_argument("--forms", default="vn32,config1,r2b6,config3,config4",
+                    help="other forms and workloads carried in the line: vn32 (the mixed form with vn "
+                         "stored in FP32, same workload), config1 (R2B4x20 FP64), "
+                         "r2b6 (R2B6x90 in both forms "
                          "with the options), config3 (R2B7x90 mixed with its error after 100 steps), "
                          "config4 (the batch of 16 against sequential runs); 'none' for none")
     ap.add_argument("--options", default="upwind,damped,tracers",

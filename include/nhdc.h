@@ -68,7 +68,13 @@ enum {
     NHDC_ETOOBIG = -7    /* input larger than a fixed maximum (nhdc_diag_noalloc) */
 };
 
-enum { NHDC_FP64 = 0, NHDC_MIXED = 1 };
+/* Precision forms: NHDC_FP64 (every operation FP64); NHDC_MIXED (FP32
+ * horizontal stencils and tendencies, FP64 state, vertical solve,
+ * reference-state perturbations and mass fluxes); NHDC_MIXED_VN32 (as
+ * NHDC_MIXED with the normal velocity, prognostic and predicted, stored in
+ * FP32: its FP64 sum is rounded where it is stored; the boundary still takes
+ * and gives FP64 vn). */
+enum { NHDC_FP64 = 0, NHDC_MIXED = 1, NHDC_MIXED_VN32 = 2 };
 
 typedef struct nhdc_ctx nhdc_ctx;
 
@@ -147,9 +153,9 @@ typedef struct nhdc_state_view {
 
 /* Create a context on HIP device `device` with precision NHDC_FP64 (every
  * operation in FP64, the precision the paper's memory accounting assumes,
- * Sec. 1) or NHDC_MIXED (horizontal stencils and tendencies in FP32; vertical
+ * Sec. 1), NHDC_MIXED (horizontal stencils and tendencies in FP32; vertical
  * solve, reference-state perturbations and mass fluxes FP64; the paper has no
- * reduced-precision form).  No device memory is taken yet.
+ * reduced-precision form) or NHDC_MIXED_VN32.  No device memory is taken yet.
  * Errors: EINVAL for out NULL or an unknown precision, EHIP for a device that
  * does not exist, ENOMEM when the host context cannot be made. */
 int nhdc_create(nhdc_ctx **out, int precision, int device);
@@ -268,21 +274,25 @@ int nhdc_sizes(const nhdc_ctx *ctx, int64_t *n_cells, int64_t *n_edges, int64_t 
  * are tiled separately. */
 int nhdc_set_tiles(nhdc_ctx *ctx, int lt_edge, int lt_cell, int lt_vert);
 
-/* Block sizes (lanes per workgroup: 64, 128 or 256) of the column and the
- * vertex kernels, the kernels whose work needs no per-block tables; the
- * others run in blocks of 256.  Results do not depend on them; only speed
- * does (smaller blocks spread a launch over more workgroups and shorten its
- * tail).  EINVAL for another size, ESTATE before nhdc_upload_grid. */
-int nhdc_set_block_sizes(nhdc_ctx *ctx, int column, int vertex);
+/* Block shapes: the block sizes (lanes per workgroup: 64, 128 or 256) of the
+ * column and the vertex kernels, the kernels whose work needs no per-block
+ * tables (the others run in blocks of 256), and column_waves, the waves per
+ * SIMD the column kernel may occupy (2 or 3, reserved through LDS; 0 = as
+ * many as its registers allow, 4; the default is 3: fewer columns in flight
+ * keep more of the solve's scratch round trip in the caches).  Results do not
+ * depend on them; only speed does.  EINVAL for another value, ESTATE before
+ * nhdc_upload_grid. */
+int nhdc_set_block_sizes(nhdc_ctx *ctx, int column, int vertex, int column_waves);
 
 /* The autotuner (the paper tunes its GPU kernels per configuration, Sec.
  * 3.2; here a search the library runs itself): a coordinate search over the
  * level tiles and the block sizes of this context's grid, each candidate
  * timed over whole steps of (dt, nsubsteps) on `stream`; keeps the fastest
- * and reports it in best[6] = {lt_edge, lt_cell, lt_vert, block_column,
- * block_vertex, ms per step}.  The state is saved before and restored after
+ * and reports it in best[7] = {lt_edge, lt_cell, lt_vert, block_column,
+ * block_vertex, column_waves, ms per step}.  The state is saved before and restored after
  * the search.  If cache_path is not NULL it names a JSON file (object of
- * "key": [lt_edge, lt_cell, lt_vert, block_column, block_vertex, ms], the key
+ * "key": [lt_edge, lt_cell, lt_vert, block_column, block_vertex, column_waves,
+ * ms], the key
  * naming the precision, the launch path and the instances' shapes) that is
  * read first (a hit skips the search) and updated after a search. */
 int nhdc_autotune(nhdc_ctx *ctx, double dt, int nsubsteps, const char *cache_path,
@@ -311,7 +321,7 @@ int nhdc_batch_create(nhdc_batch **out, nhdc_ctx *const *instances, int n);
 int nhdc_batch_step(nhdc_batch *b, const double *dt, int nsubsteps, int nsteps, void *stream);
 int nhdc_batch_set_tiles(nhdc_batch *b, int lt_edge, int lt_cell, int lt_vert);
 /* As nhdc_set_block_sizes, for the batch's launches (not the persistent one). */
-int nhdc_batch_set_block_sizes(nhdc_batch *b, int column, int vertex);
+int nhdc_batch_set_block_sizes(nhdc_batch *b, int column, int vertex, int column_waves);
 /* Persistent form (on = 1): each step's substeps run as ONE cooperative
  * launch over every instance, with as many blocks as the GPU holds at once
  * (blocks_per_cu > 0 caps the blocks per compute unit below that); its

@@ -178,12 +178,14 @@ int nhdc_batch_set_tiles(nhdc_batch *b, int lt_edge, int lt_cell, int lt_vert) {
     return b->persistent ? upload_pmaps(b, b->tune) : NHDC_OK;
 }
 
-int nhdc_batch_set_block_sizes(nhdc_batch *b, int column, int vertex) {
+int nhdc_batch_set_block_sizes(nhdc_batch *b, int column, int vertex, int column_waves) {
     if (!b) return NHDC_EINVAL;
-    if (!valid_block(column) || !valid_block(vertex))
-        return set_err(b->err, NHDC_EINVAL, "batch: block sizes must be 64, 128 or 256");
+    if (!valid_block(column) || !valid_block(vertex) || !valid_waves(column_waves))
+        return set_err(b->err, NHDC_EINVAL,
+                       "batch: block sizes must be 64, 128 or 256 and column_waves 0, 2 or 3");
     b->tune.blk_col = column;
     b->tune.blk_vert = vertex;
+    b->tune.col_waves = column_waves;
     rebuild_maps(b->L, b->ctxs, b->tune);
     return NHDC_OK;
 }
@@ -204,8 +206,7 @@ int nhdc_batch_set_persistent(nhdc_batch *b, int on, int blocks_per_cu) {
     hipError_t e = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, b->device);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, b->device);
     if (e == hipSuccess)
-        e = b->L.precision == NHDC_MIXED ? persistent_blocks_per_cu_mixed(b->L, &per_cu)
-                                         : persistent_blocks_per_cu_fp64(b->L, &per_cu);
+        e = form_ops(b->L.precision).persistent_blocks(b->L, &per_cu);
     if (e != hipSuccess) return hip_fail(b->err, e, "batch: persistent launch properties");
     if (!coop || per_cu < 1) return set_err(b->err, NHDC_EINVAL, "batch: no cooperative launch on this device");
     const int use = blocks_per_cu > 0 && blocks_per_cu < per_cu ? blocks_per_cu : per_cu;

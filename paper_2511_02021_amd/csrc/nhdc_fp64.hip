@@ -10,6 +10,7 @@
 #pragma clang fp contract(off)
 
 namespace nhdc {
+using VNT = double;  // the stored normal velocity
 #include "nhdc_step.inc"
 
 hipError_t launch_substep_fp64(const Launcher &L, const Sub &sub, Timing *tm, hipStream_t st) {

@@ -188,11 +188,23 @@ struct Sub {
 // column), and the block sizes of the kernels that take several (the column
 // and vertex kernels: 64, 128 or 256 lanes; the others keep BLOCK, which
 // their per-block tables and LDS arrays are built for).
+// col_waves caps the waves per SIMD of the column kernel (0: as many as its
+// registers allow, 4) by reserving LDS per block: fewer columns in flight at
+// once keep more of their scratch round trip in the caches (3 measured best).
 struct Tune {
     int lt_edge = 0, lt_cell = 0, lt_vert = 0;
     int blk_col = BLOCK, blk_vert = BLOCK;
+    int col_waves = 3;
 };
 inline bool valid_block(int b) { return b == 64 || b == 128 || b == 256; }
+inline bool valid_waves(int w) { return w == 0 || w == 2 || w == 3; }
+// LDS per block that lets a CU (160 KB of LDS, 4 SIMDs of 64-lane waves)
+// hold `waves` waves per SIMD of `block`-lane blocks but not one block more
+inline unsigned occupancy_lds(int waves, int block) {
+    if (waves <= 0) return 0;
+    const int blocks = waves * 4 * 64 / block;
+    return unsigned(163840 / (blocks + 1) + 256);
+}
 
 enum KernelId { K_VT_EDGE = 0, K_VERTEX, K_CELL_VT, K_EDGE_PRED, K_COLUMN_PRED, K_EDGE_CORR,
                 K_COLUMN_CORR, K_CELL_GRAD, K_DIV4, K_SMAG_CELL, K_SMAG_EDGE, K_TR_SAVE,
@@ -235,11 +247,16 @@ struct Launcher {
     Map maps[KIND_NUM];
     int64_t nblocks[KIND_NUM] = {0};
     int block[KIND_NUM] = {BLOCK, BLOCK, BLOCK, BLOCK};  // lanes per block of each kind's launches
+    unsigned dyn_lds[KIND_NUM] = {0, 0, 0, 0};           // LDS reserved per block (occupancy cap)
 };
 
-// kernels (nhdc_fp64.hip / nhdc_mixed.hip)
+// kernels (nhdc_fp64.hip / nhdc_mixed.hip / nhdc_mixed_vn32.hip)
 hipError_t launch_substep_fp64(const Launcher &L, const Sub &sub, Timing *tm, hipStream_t st);
 hipError_t launch_substep_mixed(const Launcher &L, const Sub &sub, Timing *tm, hipStream_t st);
+hipError_t launch_substep_mixed_vn32(const Launcher &L, const Sub &sub, Timing *tm, hipStream_t st);
+hipError_t launch_diffusion_mixed_vn32(const Launcher &L, const Sub &sub, Timing *tm, hipStream_t st);
+hipError_t launch_tracers_mixed_vn32(const Launcher &L, const Sub &sub, int phase, Timing *tm,
+                                     hipStream_t st);
 // the diffusion after the substeps of a step (sub.dt: the step's dt per instance)
 hipError_t launch_diffusion_fp64(const Launcher &L, const Sub &sub, Timing *tm, hipStream_t st);
 hipError_t launch_diffusion_mixed(const Launcher &L, const Sub &sub, Timing *tm, hipStream_t st);
@@ -253,16 +270,33 @@ hipError_t launch_persistent_fp64(const Launcher &L, const PMaps *d_pm, const Su
                                   hipStream_t st);
 hipError_t launch_persistent_mixed(const Launcher &L, const PMaps *d_pm, const Sub &sub, int grid,
                                    hipStream_t st);
+hipError_t launch_persistent_mixed_vn32(const Launcher &L, const PMaps *d_pm, const Sub &sub, int grid,
+                                        hipStream_t st);
 hipError_t persistent_blocks_per_cu_fp64(const Launcher &L, int *blocks);
 hipError_t persistent_blocks_per_cu_mixed(const Launcher &L, int *blocks);
+hipError_t persistent_blocks_per_cu_mixed_vn32(const Launcher &L, int *blocks);
+// The launches of one precision form.
+struct FormOps {
+    hipError_t (*substep)(const Launcher &, const Sub &, Timing *, hipStream_t);
+    hipError_t (*diffusion)(const Launcher &, const Sub &, Timing *, hipStream_t);
+    hipError_t (*tracers)(const Launcher &, const Sub &, int, Timing *, hipStream_t);
+    hipError_t (*persistent)(const Launcher &, const PMaps *, const Sub &, int, hipStream_t);
+    hipError_t (*persistent_blocks)(const Launcher &, int *);
+};
+const FormOps &form_ops(int precision);
+// the stencils of a precision run in FP32 (the mixed forms)
+inline bool fp32_stencils(int precision) { return precision != NHDC_FP64; }
+// bytes of one stored normal velocity (FP32 in the mixed form's FP32-vn variant)
+inline int vn_bytes(int precision) { return precision == NHDC_MIXED_VN32 ? 4 : 8; }
 // set-up and diagnostics (nhdc_util.hip)
 hipError_t launch_metrics(const Grid &g, hipStream_t st);
 // out[i] |= 1 where row i of the [nlev][n] array a has an entry whose bits
 // differ from its first entry's
 hipError_t launch_level_nonflat(const double *a, int64_t n, int nlev, int32_t *out, hipStream_t st);
 hipError_t launch_to_float(const double *src, float *dst, int64_t n, hipStream_t st);
+hipError_t launch_to_double(const float *src, double *dst, int64_t n, hipStream_t st);
 hipError_t launch_diag(const Grid &g, const State &s, double *part, double *out2, hipStream_t st);
-hipError_t launch_finite(const Grid &g, const State &s, int *flag, hipStream_t st);
+hipError_t launch_finite(const Grid &g, const State &s, int vn_size, int *flag, hipStream_t st);
 // release a context's device memory and the context (nhdc_destroy, or the
 // last batch holding a context whose destroy was deferred)
 void free_context(nhdc_ctx *ctx);

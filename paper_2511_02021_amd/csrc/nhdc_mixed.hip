@@ -11,6 +11,7 @@
 #pragma clang fp contract(fast)
 
 namespace nhdc {
+using VNT = double;  // the stored normal velocity
 #include "nhdc_step.inc"
 
 hipError_t launch_substep_mixed(const Launcher &L, const Sub &sub, Timing *tm, hipStream_t st) {

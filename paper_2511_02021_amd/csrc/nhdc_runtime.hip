@@ -67,7 +67,19 @@ hipError_t timing_end(Timing *tm, hipStream_t st) {
     return hipEventRecord(tm->ev[2 * (tm->ids.size() - 1) + 1], st);
 }
 
+const FormOps &form_ops(int precision) {
+    static const FormOps fp64{launch_substep_fp64, launch_diffusion_fp64, launch_tracers_fp64,
+                              launch_persistent_fp64, persistent_blocks_per_cu_fp64};
+    static const FormOps mixed{launch_substep_mixed, launch_diffusion_mixed, launch_tracers_mixed,
+                               launch_persistent_mixed, persistent_blocks_per_cu_mixed};
+    static const FormOps vn32{launch_substep_mixed_vn32, launch_diffusion_mixed_vn32,
+                              launch_tracers_mixed_vn32, launch_persistent_mixed_vn32,
+                              persistent_blocks_per_cu_mixed_vn32};
+    return precision == NHDC_MIXED ? mixed : precision == NHDC_MIXED_VN32 ? vn32 : fp64;
+}
+
 hipError_t run_step(const Launcher &L, const double *dt, int nsub, Timing *tm, hipStream_t st) {
+    const FormOps &f = form_ops(L.precision);
     Sub sub;
     for (int i = 0; i < L.n; ++i) sub.dt[i] = dt[i] / nsub;
     for (int i = L.n; i < MAX_INST; ++i) sub.dt[i] = 0.0;
@@ -75,25 +87,21 @@ hipError_t run_step(const Launcher &L, const double *dt, int nsub, Timing *tm, h
     Sub whole = sub;  // the step's dt per instance (diffusion, tracers)
     for (int i = 0; i < L.n; ++i) whole.dt[i] = dt[i];
     if (L.tracers) {
-        hipError_t e = L.precision == NHDC_MIXED ? launch_tracers_mixed(L, whole, 0, tm, st)
-                                                 : launch_tracers_fp64(L, whole, 0, tm, st);
+        hipError_t e = f.tracers(L, whole, 0, tm, st);
         if (e != hipSuccess) return e;
     }
     for (int s = 0; s < nsub; ++s) {
         sub.first = s == 0;
         sub.last = s == nsub - 1;
-        hipError_t e = L.precision == NHDC_MIXED ? launch_substep_mixed(L, sub, tm, st)
-                                                 : launch_substep_fp64(L, sub, tm, st);
+        hipError_t e = f.substep(L, sub, tm, st);
         if (e != hipSuccess) return e;
     }
     if (L.smag) {  // the diffusion of vn over the whole step
-        hipError_t e = L.precision == NHDC_MIXED ? launch_diffusion_mixed(L, whole, tm, st)
-                                                 : launch_diffusion_fp64(L, whole, tm, st);
+        hipError_t e = f.diffusion(L, whole, tm, st);
         if (e != hipSuccess) return e;
     }
     if (L.tracers) {  // tracer transport with the step's averaged mass fluxes
-        hipError_t e = L.precision == NHDC_MIXED ? launch_tracers_mixed(L, whole, 1, tm, st)
-                                                 : launch_tracers_fp64(L, whole, 1, tm, st);
+        hipError_t e = f.tracers(L, whole, 1, tm, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -109,15 +117,15 @@ hipError_t run_step_persistent(const Launcher &L, const PMaps *d_pm, int grid, c
     sub.last = nsub == 1;
     Sub whole = sub;
     for (int i = 0; i < L.n; ++i) whole.dt[i] = dt[i];
-    const bool mixed = L.precision == NHDC_MIXED;
+    const FormOps &f = form_ops(L.precision);
     hipError_t e = hipSuccess;
-    if (L.tracers) e = mixed ? launch_tracers_mixed(L, whole, 0, nullptr, st) : launch_tracers_fp64(L, whole, 0, nullptr, st);
+    if (L.tracers) e = f.tracers(L, whole, 0, nullptr, st);
     if (e != hipSuccess) return e;
-    e = mixed ? launch_persistent_mixed(L, d_pm, sub, grid, st) : launch_persistent_fp64(L, d_pm, sub, grid, st);
+    e = f.persistent(L, d_pm, sub, grid, st);
     if (e != hipSuccess) return e;
-    if (L.smag) e = mixed ? launch_diffusion_mixed(L, whole, nullptr, st) : launch_diffusion_fp64(L, whole, nullptr, st);
+    if (L.smag) e = f.diffusion(L, whole, nullptr, st);
     if (e != hipSuccess) return e;
-    if (L.tracers) e = mixed ? launch_tracers_mixed(L, whole, 1, nullptr, st) : launch_tracers_fp64(L, whole, 1, nullptr, st);
+    if (L.tracers) e = f.tracers(L, whole, 1, nullptr, st);
     return e;
 }
 
@@ -127,6 +135,7 @@ void rebuild_maps(Launcher &L, const std::vector<nhdc_ctx *> &ctxs, const Tune &
     for (int k = 0; k < KIND_NUM; ++k) {
         build_map(L.maps[k], L.nblocks[k], Kind(k), grids.data(), int(grids.size()), t);
         L.block[k] = kind_block(Kind(k), t);
+        L.dyn_lds[k] = k == KIND_COLUMN ? occupancy_lds(t.col_waves, L.block[k]) : 0u;
     }
 }
 
@@ -146,7 +155,7 @@ int upload_insts(Launcher &L, const std::vector<nhdc_ctx *> &ctxs, std::string &
     const int n = int(ctxs.size());
     const int prec = ctxs[0]->precision;
     std::vector<char> host;
-    if (prec == NHDC_MIXED) {
+    if (fp32_stencils(prec)) {
         std::vector<Inst<float>> v;
         for (auto *c : ctxs) v.push_back(make_inst<float>(c, c->wf));
         const char *b = reinterpret_cast<const char *>(v.data());
@@ -184,10 +193,12 @@ int upload_insts(Launcher &L, const std::vector<nhdc_ctx *> &ctxs, std::string &
 }
 
 // ---- state snapshot (autotuning runs real steps) ----
+// the state's arrays and their sizes in bytes
 static void state_arrays(nhdc_ctx *c, std::vector<std::pair<double *, size_t>> &out) {
-    const size_t NC = size_t(c->g.N) * c->g.nc, NC1 = size_t(c->g.N + 1) * c->g.nc,
-                 NE = size_t(c->g.N) * c->g.ne;
-    out = {{c->s.vn, NE}, {c->s.w, NC1}, {c->s.rho, NC}, {c->s.pi, NC}, {c->s.thv, NC},
+    const size_t NC = size_t(c->g.N) * c->g.nc * 8, NC1 = size_t(c->g.N + 1) * c->g.nc * 8,
+                 NE = size_t(c->g.N) * c->g.ne * 8;
+    const size_t NEV = size_t(c->g.N) * c->g.ne * size_t(vn_bytes(c->precision));
+    out = {{c->s.vn, NEV}, {c->s.w, NC1}, {c->s.rho, NC}, {c->s.pi, NC}, {c->s.thv, NC},
            {c->s.pi_prev, NC}, {c->s.facc, NE}, {c->s.wacc, NC1}, {c->s.px, NC}};
     if (c->tr.nt) out.push_back({c->tr.q, size_t(c->tr.nt) * NC});
 }
@@ -201,16 +212,16 @@ static int snapshot(const Allocator &al, const std::vector<nhdc_ctx *> &ctxs,
         for (auto &a : arr) {
             hipError_t e;
             if (!restore) {
-                void *b = dev_alloc(al, a.second * 8);
+                void *b = dev_alloc(al, a.second);
                 if (!b) {
                     for (void *x : buf) dev_free(al, x);
                     buf.clear();
                     return set_err(err, NHDC_ENOMEM, "autotune: no memory for the state snapshot");
                 }
                 buf.push_back(b);
-                e = hipMemcpyAsync(b, a.first, a.second * 8, hipMemcpyDeviceToDevice, st);
+                e = hipMemcpyAsync(b, a.first, a.second, hipMemcpyDeviceToDevice, st);
             } else {
-                e = hipMemcpyAsync(a.first, buf[q++], a.second * 8, hipMemcpyDeviceToDevice, st);
+                e = hipMemcpyAsync(a.first, buf[q++], a.second, hipMemcpyDeviceToDevice, st);
             }
             if (e != hipSuccess) return hip_fail(err, e, "autotune: state copy");
         }
@@ -225,8 +236,8 @@ static int snapshot(const Allocator &al, const std::vector<nhdc_ctx *> &ctxs,
 }
 
 // ---- JSON cache: one entry per line,
-// "key": [lt_edge, lt_cell, lt_vert, block_column, block_vertex, ms] ----
-constexpr int kBest = 6;
+// "key": [lt_edge, lt_cell, lt_vert, block_column, block_vertex, column_waves, ms] ----
+constexpr int kBest = 7;
 static bool cache_lookup(const char *path, const std::string &key, double best[kBest]) {
     if (!path) return false;
     std::ifstream f(path);
@@ -243,7 +254,7 @@ static bool cache_lookup(const char *path, const std::string &key, double best[k
         std::istringstream is(body);
         for (int i = 0; i < kBest; ++i)
             if (!(is >> best[i])) return false;
-        return valid_block(int(best[3])) && valid_block(int(best[4]));
+        return valid_block(int(best[3])) && valid_block(int(best[4])) && valid_waves(int(best[5]));
     }
     return false;
 }
@@ -261,8 +272,8 @@ static void cache_store(const char *path, const std::string &key, const double b
         }
     }
     char buf[512];
-    std::snprintf(buf, sizeof(buf), "  \"%s\": [%d, %d, %d, %d, %d, %.6f]", key.c_str(), int(best[0]),
-                  int(best[1]), int(best[2]), int(best[3]), int(best[4]), best[5]);
+    std::snprintf(buf, sizeof(buf), "  \"%s\": [%d, %d, %d, %d, %d, %d, %.6f]", key.c_str(), int(best[0]),
+                  int(best[1]), int(best[2]), int(best[3]), int(best[4]), int(best[5]), best[6]);
     entries.push_back(buf);
     std::ofstream f(path, std::ios::trunc);
     f << "{\n";
@@ -275,7 +286,8 @@ int autotune(Launcher &L, Tune &tune, const std::vector<nhdc_ctx *> &ctxs, const
              int nsub, const char *cache_path, double *best_out, hipStream_t st,
              std::string &err, const Stepper &stepper, const char *path_tag) {
     std::ostringstream ks;
-    ks << (L.precision == NHDC_MIXED ? "mixed" : "fp64") << "|" << path_tag << "|";
+    ks << (L.precision == NHDC_MIXED ? "mixed" : L.precision == NHDC_MIXED_VN32 ? "mixed_vn32" : "fp64")
+       << "|" << path_tag << "|";
     for (size_t i = 0; i < ctxs.size(); ++i)
         ks << (i ? "," : "") << ctxs[i]->g.nc << "x" << ctxs[i]->g.N;
     const std::string key = ks.str();
@@ -290,6 +302,7 @@ int autotune(Launcher &L, Tune &tune, const std::vector<nhdc_ctx *> &ctxs, const
         tune.lt_vert = int(best[2]);
         tune.blk_col = int(best[3]);
         tune.blk_vert = int(best[4]);
+        tune.col_waves = int(best[5]);
         hipError_t e = apply(tune);
         if (e != hipSuccess) return hip_fail(err, e, "autotune: set-up");
         if (best_out)
@@ -326,14 +339,15 @@ int autotune(Launcher &L, Tune &tune, const std::vector<nhdc_ctx *> &ctxs, const
     const int cand_ec[] = {0, 48, 32, 16, 8};
     const int cand_v[] = {0, 32, 16};
     const int cand_b[] = {256, 128, 64};
-    const int nparam = stepper.block_sizes ? 5 : 3;
+    const int cand_w[] = {3, 0, 2};
+    const int nparam = stepper.block_sizes ? 6 : 3;
     for (int param = 0; param < nparam && !rc; ++param) {
-        const int *cand = param < 2 ? cand_ec : param == 2 ? cand_v : cand_b;
+        const int *cand = param < 2 ? cand_ec : param == 2 ? cand_v : param < 5 ? cand_b : cand_w;
         const int ncand = param < 2 ? 5 : 3;
         for (int q = 0; q < ncand; ++q) {
             Tune t = bt;
             int &slot = param == 0 ? t.lt_edge : param == 1 ? t.lt_cell : param == 2 ? t.lt_vert
-                      : param == 3 ? t.blk_col : t.blk_vert;
+                      : param == 3 ? t.blk_col : param == 4 ? t.blk_vert : t.col_waves;
             if (slot == cand[q]) continue;
             slot = cand[q];
             double ms = 0.0;
@@ -358,7 +372,8 @@ int autotune(Launcher &L, Tune &tune, const std::vector<nhdc_ctx *> &ctxs, const
     best[2] = tune.lt_vert;
     best[3] = tune.blk_col;
     best[4] = tune.blk_vert;
-    best[5] = bms;
+    best[5] = tune.col_waves;
+    best[6] = bms;
     cache_store(cache_path, key, best);
     if (best_out)
         for (int i = 0; i < kBest; ++i) best_out[i] = best[i];
@@ -420,6 +435,44 @@ int upload_f32(nhdc_ctx *ctx, float **p, const double *dsrc, int64_t n) {
 }
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0; }
+
+// The FP32-vn variant's conversions at the boundary: FP64 vn (host or
+// device) into the FP32 store, and the FP32 store out as FP64; host data
+// pass through a temporary device buffer.  Synchronous on `s` when a host
+// buffer is involved.
+int vn_to_f32(nhdc_ctx *ctx, const double *src, bool on_device, hipStream_t s) {
+    const int64_t NE = int64_t(ctx->g.N) * ctx->g.ne;
+    float *dst = reinterpret_cast<float *>(ctx->s.vn);
+    if (on_device) {
+        HIP_TRY(ctx, launch_to_float(src, dst, NE, s));
+        return NHDC_OK;
+    }
+    double *tmp = static_cast<double *>(dev_alloc(ctx->al, size_t(NE) * 8));
+    if (!tmp) return set_err(ctx, NHDC_ENOMEM, "init_state: no memory to convert vn");
+    hipError_t e = hipMemcpyAsync(tmp, src, size_t(NE) * 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_to_float(tmp, dst, NE, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    dev_free(ctx->al, tmp);
+    if (e != hipSuccess) return nhdc::hip_fail(ctx->err, e, "init_state: vn to FP32");
+    return NHDC_OK;
+}
+
+int vn_to_f64(nhdc_ctx *ctx, double *dst, bool on_device, hipStream_t s) {
+    const int64_t NE = int64_t(ctx->g.N) * ctx->g.ne;
+    const float *src = reinterpret_cast<const float *>(ctx->s.vn);
+    if (on_device) {
+        HIP_TRY(ctx, launch_to_double(src, dst, NE, s));
+        return NHDC_OK;
+    }
+    double *tmp = static_cast<double *>(dev_alloc(ctx->al, size_t(NE) * 8));
+    if (!tmp) return set_err(ctx, NHDC_ENOMEM, "get_state: no memory to convert vn");
+    hipError_t e = launch_to_double(src, tmp, NE, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(dst, tmp, size_t(NE) * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    dev_free(ctx->al, tmp);
+    if (e != hipSuccess) return nhdc::hip_fail(ctx->err, e, "get_state: vn to FP64");
+    return NHDC_OK;
+}
 
 int validate(nhdc_ctx *ctx, const nhdc_grid *g, const nhdc_vertical *v) {
     const int64_t nc = g->n_cells, ne = g->n_edges, nv = g->n_verts;
@@ -507,7 +560,7 @@ int alloc_work(nhdc_ctx *ctx, Work<RT> &W) {
     for (auto q : d_c)
         if ((rc = dalloc(ctx, q, NC))) return rc;
     if ((rc = dalloc(ctx, &W.ws, NC1))) return rc;
-    if ((rc = dalloc(ctx, &W.vns, NE))) return rc;
+    if ((rc = dalloc(ctx, &W.vns, vn_bytes(ctx->precision) == 4 ? (NE + 1) / 2 : NE))) return rc;
     // pairs of doubles read and written together
     if ((rc = dalloc(ctx, &W.rp, 2 * NC))) return rc;
     if ((rc = dalloc(ctx, &W.cd, 2 * NC1))) return rc;
@@ -541,7 +594,8 @@ extern "C" {
 int nhdc_create(nhdc_ctx **out, int precision, int device) {
     if (!out) return NHDC_EINVAL;
     *out = nullptr;
-    if (precision != NHDC_FP64 && precision != NHDC_MIXED) return NHDC_EINVAL;
+    if (precision != NHDC_FP64 && precision != NHDC_MIXED && precision != NHDC_MIXED_VN32)
+        return NHDC_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
         (void)hipGetLastError();
@@ -839,7 +893,7 @@ int nhdc_upload_grid(nhdc_ctx *ctx, const nhdc_grid *g, const nhdc_vertical *v,
         G.flat_r = 0;
         while (G.flat_r < N && h_pr[G.flat_r] == 0 && h_tr[G.flat_r] == 0) ++G.flat_r;
     }
-    if (ctx->precision == NHDC_MIXED) {
+    if (fp32_stencils(ctx->precision)) {
         Geo<float> &F = G.gf;
         if ((rc = upload_f32(ctx, &F.c_sl, D.c_sl, 3 * nc))) return rc;
         if ((rc = upload_f32(ctx, &F.c_dv, D.c_dv, 9 * nc))) return rc;
@@ -862,9 +916,10 @@ int nhdc_upload_grid(nhdc_ctx *ctx, const nhdc_grid *g, const nhdc_vertical *v,
         if ((rc = dalloc(ctx, q, NC))) return rc;
     if ((rc = dalloc(ctx, &S.w, NC1))) return rc;
     if ((rc = dalloc(ctx, &S.wacc, NC1))) return rc;
-    if ((rc = dalloc(ctx, &S.vn, NE))) return rc;
+    // the stored normal velocity: FP64, or FP32 (half the bytes) in the FP32-vn variant
+    if ((rc = dalloc(ctx, &S.vn, vn_bytes(ctx->precision) == 4 ? (NE + 1) / 2 : NE))) return rc;
     if ((rc = dalloc(ctx, &S.facc, NE))) return rc;
-    if (ctx->precision == NHDC_MIXED) rc = alloc_work<float>(ctx, ctx->wf);
+    if (fp32_stencils(ctx->precision)) rc = alloc_work<float>(ctx, ctx->wf);
     else rc = alloc_work<double>(ctx, ctx->wd);
     if (rc) return rc;
     if ((rc = dalloc(ctx, &ctx->red, 2 * ((nc + BLOCK - 1) / BLOCK) + 2))) return rc;
@@ -889,7 +944,12 @@ int nhdc_init_state(nhdc_ctx *ctx, const nhdc_state_view *st, void *stream) {
     const size_t NC = size_t(G.N) * G.nc * 8, NC1 = size_t(G.N + 1) * G.nc * 8,
                  NE = size_t(G.N) * G.ne * 8;
     hipMemcpyKind kind = st->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->s.vn, st->vn, NE, kind, s));
+    if (vn_bytes(ctx->precision) == 4) {  // FP64 in, stored in FP32
+        int rc = vn_to_f32(ctx, st->vn, st->on_device != 0, s);
+        if (rc) return rc;
+    } else {
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->s.vn, st->vn, NE, kind, s));
+    }
     HIP_TRY(ctx, hipMemcpyAsync(ctx->s.w, st->w, NC1, kind, s));
     HIP_TRY(ctx, hipMemcpyAsync(ctx->s.rho, st->rho, NC, kind, s));
     HIP_TRY(ctx, hipMemcpyAsync(ctx->s.pi, st->pi, NC, kind, s));
@@ -916,13 +976,15 @@ int nhdc_step(nhdc_ctx *ctx, double dt, int nsub, void *stream) {
     return timing_collect(ctx, s);
 }
 
-int nhdc_set_block_sizes(nhdc_ctx *ctx, int column, int vertex) {
+int nhdc_set_block_sizes(nhdc_ctx *ctx, int column, int vertex, int column_waves) {
     if (!ctx) return NHDC_EINVAL;
     if (!ctx->grid_ready) return set_err(ctx, NHDC_ESTATE, "set_block_sizes: no grid uploaded");
-    if (!valid_block(column) || !valid_block(vertex))
-        return set_err(ctx, NHDC_EINVAL, "set_block_sizes: block sizes must be 64, 128 or 256");
+    if (!valid_block(column) || !valid_block(vertex) || !valid_waves(column_waves))
+        return set_err(ctx, NHDC_EINVAL,
+                       "set_block_sizes: block sizes must be 64, 128 or 256 and column_waves 0, 2 or 3");
     ctx->tune.blk_col = column;
     ctx->tune.blk_vert = vertex;
+    ctx->tune.col_waves = column_waves;
     std::vector<nhdc_ctx *> one{ctx};
     rebuild_maps(ctx->L, one, ctx->tune);
     return NHDC_OK;
@@ -966,7 +1028,12 @@ int nhdc_get_state(nhdc_ctx *ctx, const nhdc_state_view *dst, void *stream) {
     const size_t NC = size_t(G.N) * G.nc * 8, NC1 = size_t(G.N + 1) * G.nc * 8,
                  NE = size_t(G.N) * G.ne * 8;
     hipMemcpyKind kind = dst->on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-    if (dst->vn) HIP_TRY(ctx, hipMemcpyAsync(dst->vn, ctx->s.vn, NE, kind, s));
+    if (dst->vn && vn_bytes(ctx->precision) == 4) {  // stored in FP32, FP64 out
+        int rc = vn_to_f64(ctx, dst->vn, dst->on_device != 0, s);
+        if (rc) return rc;
+    } else if (dst->vn) {
+        HIP_TRY(ctx, hipMemcpyAsync(dst->vn, ctx->s.vn, NE, kind, s));
+    }
     if (dst->w) HIP_TRY(ctx, hipMemcpyAsync(dst->w, ctx->s.w, NC1, kind, s));
     if (dst->rho) HIP_TRY(ctx, hipMemcpyAsync(dst->rho, ctx->s.rho, NC, kind, s));
     if (dst->pi) HIP_TRY(ctx, hipMemcpyAsync(dst->pi, ctx->s.pi, NC, kind, s));
@@ -1010,7 +1077,7 @@ int nhdc_check_finite(nhdc_ctx *ctx, void *stream) {
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(ctx, hipMemsetAsync(ctx->flag, 0, sizeof(int), s));
-    HIP_TRY(ctx, launch_finite(ctx->g, ctx->s, ctx->flag, s));
+    HIP_TRY(ctx, launch_finite(ctx->g, ctx->s, vn_bytes(ctx->precision), ctx->flag, s));
     int h = 0;
     HIP_TRY(ctx, hipMemcpyAsync(&h, ctx->flag, sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));

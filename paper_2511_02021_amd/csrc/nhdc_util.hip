@@ -45,6 +45,11 @@ __global__ void k_to_float(const double *__restrict__ src, float *__restrict__ d
     if (i < n) dst[i] = float(src[i]);
 }
 
+__global__ void k_to_double(const float *__restrict__ src, double *__restrict__ dst, int64_t n) {
+    int64_t i = lin();
+    if (i < n) dst[i] = double(src[i]);
+}
+
 __global__ void k_init_prev(int64_t n, const double *__restrict__ pi, const double *__restrict__ pi_ref,
                             double *__restrict__ prev) {
     int64_t i = lin();
@@ -115,7 +120,8 @@ __global__ void k_diag_final(int nparts, const double *__restrict__ part, double
     }
 }
 
-__global__ void k_finite(int64_t n, const double *__restrict__ x, int *__restrict__ flag) {
+template <class T>
+__global__ void k_finite(int64_t n, const T *__restrict__ x, int *__restrict__ flag) {
     int64_t i = lin();
     if (i < n && !isfinite(x[i])) flag[0] = 1;  // benign race: every writer stores 1
 }
@@ -135,6 +141,11 @@ hipError_t launch_level_nonflat(const double *a, int64_t n, int nlev, int32_t *o
 
 hipError_t launch_to_float(const double *src, float *dst, int64_t n, hipStream_t st) {
     hipLaunchKernelGGL(k_to_float, dim3(nb(n)), dim3(BLOCK), 0, st, src, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_double(const float *src, double *dst, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_to_double, dim3(nb(n)), dim3(BLOCK), 0, st, src, dst, n);
     return hipGetLastError();
 }
 
@@ -159,13 +170,17 @@ hipError_t launch_diag(const Grid &g, const State &s, double *part, double *out2
     return hipGetLastError();
 }
 
-hipError_t launch_finite(const Grid &g, const State &s, int *flag, hipStream_t st) {
+hipError_t launch_finite(const Grid &g, const State &s, int vn_size, int *flag, hipStream_t st) {
     const int64_t NC = int64_t(g.N) * g.nc, NC1 = int64_t(g.N + 1) * g.nc, NE = int64_t(g.N) * g.ne;
     const double *arrs[4] = {s.rho, s.pi, s.thv, s.pi_prev};
     for (int i = 0; i < 4; ++i)
-        hipLaunchKernelGGL(k_finite, dim3(nb(NC)), dim3(BLOCK), 0, st, NC, arrs[i], flag);
-    hipLaunchKernelGGL(k_finite, dim3(nb(NC1)), dim3(BLOCK), 0, st, NC1, s.w, flag);
-    hipLaunchKernelGGL(k_finite, dim3(nb(NE)), dim3(BLOCK), 0, st, NE, s.vn, flag);
+        hipLaunchKernelGGL(k_finite<double>, dim3(nb(NC)), dim3(BLOCK), 0, st, NC, arrs[i], flag);
+    hipLaunchKernelGGL(k_finite<double>, dim3(nb(NC1)), dim3(BLOCK), 0, st, NC1, s.w, flag);
+    if (vn_size == 4)
+        hipLaunchKernelGGL(k_finite<float>, dim3(nb(NE)), dim3(BLOCK), 0, st, NE,
+                           reinterpret_cast<const float *>(s.vn), flag);
+    else
+        hipLaunchKernelGGL(k_finite<double>, dim3(nb(NE)), dim3(BLOCK), 0, st, NE, s.vn, flag);
     return hipGetLastError();
 }
 

@@ -12,9 +12,9 @@ import numpy as np
 
 from . import _build
 
-NHDC_FP64, NHDC_MIXED = 0, 1
+NHDC_FP64, NHDC_MIXED, NHDC_MIXED_VN32 = 0, 1, 2
 MAX_INST = 64  # NHDC_MAX_INST: instances of one batch
-PRECISIONS = {"fp64": NHDC_FP64, "mixed": NHDC_MIXED}
+PRECISIONS = {"fp64": NHDC_FP64, "mixed": NHDC_MIXED, "mixed_vn32": NHDC_MIXED_VN32}
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EGRID", -5: "ESTATE", -6: "EUNSTABLE",
           -7: "ETOOBIG"}
 NOALLOC_MAX_CELLS = 65536 * 256  # NHDC_NOALLOC_MAX_CELLS
@@ -126,8 +126,8 @@ def lib():
         L.nhdc_check_finite.argtypes = [vp, vp]
         L.nhdc_sizes.argtypes = [vp] + [vp] * 4
         L.nhdc_set_tiles.argtypes = [vp, i, i, i]
-        L.nhdc_set_block_sizes.argtypes = [vp, i, i]
-        L.nhdc_batch_set_block_sizes.argtypes = [vp, i, i]
+        L.nhdc_set_block_sizes.argtypes = [vp, i, i, i]
+        L.nhdc_batch_set_block_sizes.argtypes = [vp, i, i, i]
         L.nhdc_batch_set_persistent.argtypes = [vp, i, i]
         L.nhdc_batch_persistent_grid.argtypes = [vp]
         L.nhdc_autotune.argtypes = [vp, d, i, C.c_char_p, C.POINTER(d), vp]
@@ -324,19 +324,20 @@ class Dycore:
         """Levels per lane of the marching kernels (0 = whole column)."""
         self._check(self.L.nhdc_set_tiles(self.h, int(lt_edge), int(lt_cell), int(lt_vert)))
 
-    def set_block_sizes(self, column=256, vertex=256):
-        """Lanes per block of the column and vertex kernels (64, 128, 256)."""
-        self._check(self.L.nhdc_set_block_sizes(self.h, int(column), int(vertex)))
+    def set_block_sizes(self, column=256, vertex=256, column_waves=3):
+        """Lanes per block of the column and vertex kernels (64, 128, 256) and
+        the column kernel's waves per SIMD (2, 3; 0 = uncapped)."""
+        self._check(self.L.nhdc_set_block_sizes(self.h, int(column), int(vertex), int(column_waves)))
 
     def autotune(self, dt, nsub, cache_path=None, stream=None):
         """Search the level tiles and block sizes by timing whole steps; the
         state is restored.  Returns (lt_edge, lt_cell, lt_vert, block_column,
-        block_vertex, ms_per_step)."""
-        best = (C.c_double * 6)()
+        block_vertex, column_waves, ms_per_step)."""
+        best = (C.c_double * 7)()
         path = cache_path.encode() if cache_path else None
         self._check(self.L.nhdc_autotune(self.h, float(dt), int(nsub), path, best,
                                          _stream_ptr(stream)))
-        return tuple(int(x) for x in best[:5]) + (best[5],)
+        return tuple(int(x) for x in best[:6]) + (best[6],)
 
     def set_timing(self, on):
         self._check(self.L.nhdc_set_timing(self.h, int(bool(on))))
@@ -403,8 +404,9 @@ class Batch:
     def set_tiles(self, lt_edge=0, lt_cell=0, lt_vert=0):
         self._check(self.L.nhdc_batch_set_tiles(self.h, int(lt_edge), int(lt_cell), int(lt_vert)))
 
-    def set_block_sizes(self, column=256, vertex=256):
-        self._check(self.L.nhdc_batch_set_block_sizes(self.h, int(column), int(vertex)))
+    def set_block_sizes(self, column=256, vertex=256, column_waves=3):
+        self._check(self.L.nhdc_batch_set_block_sizes(self.h, int(column), int(vertex),
+                                                      int(column_waves)))
 
     def set_persistent(self, on=True, blocks_per_cu=0):
         """Run each step's substeps as one persistent cooperative launch."""
@@ -416,11 +418,11 @@ class Batch:
 
     def autotune(self, dt, nsub, cache_path=None, stream=None):
         """As Dycore.autotune, over the batch on its current path."""
-        best = (C.c_double * 6)()
+        best = (C.c_double * 7)()
         path = cache_path.encode() if cache_path else None
         self._check(self.L.nhdc_batch_autotune(self.h, self._dts(dt), int(nsub), path, best,
                                                _stream_ptr(stream)))
-        return tuple(int(x) for x in best[:5]) + (best[5],)
+        return tuple(int(x) for x in best[:6]) + (best[6],)
 
     def close(self):
         if getattr(self, "h", None):

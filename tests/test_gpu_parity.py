@@ -89,6 +89,20 @@ def test_full_size_r2b6_one_step():
     assert rel(gf[0], of[0]) <= 1e-12 and rel(gf[1], of[1]) <= 1e-12
 
 
+def test_full_size_r2b6_ten_steps():
+    """The R2B6x90 workload's grid for 10 steps (the oracle's part takes about
+    a minute and a half on the host's threads): every field within 1e-12 of
+    the oracle, and bitwise equal."""
+    c = CS.config_case(2)
+    print("R2B6x90, 10 steps on both sides", flush=True)
+    gs, gf, os_, of = _run_both(c, 10)
+    _compare(gs, os_, 1e-12, "R2B6x90 10 steps")
+    assert rel(gf[0], of[0]) <= 1e-12 and rel(gf[1], of[1]) <= 1e-12
+    diff = {f: int(np.count_nonzero(gs[f] != os_[f])) for f in FIELDS}
+    print("bitwise differing entries", diff, flush=True)
+    assert all(v == 0 for v in diff.values()), diff
+
+
 def test_run_to_run_bitwise(cfg1):
     out = []
     for _ in range(2):

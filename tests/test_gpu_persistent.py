@@ -104,21 +104,24 @@ def test_persistent_refused_for_other_numberings():
     d.close()
 
 
-@pytest.mark.parametrize("column,vertex", [(64, 64), (128, 256), (256, 128), (64, 128)])
-def test_block_sizes_are_result_neutral(column, vertex):
+@pytest.mark.parametrize("column,vertex,waves", [(64, 64, 3), (128, 256, 0), (256, 128, 2),
+                                                (64, 128, 0), (256, 256, 0)])
+def test_block_sizes_are_result_neutral(column, vertex, waves):
     nhdc = _nhdc()
     c = CS.config_case(2, k=4, n_lev=30)
     ref = nhdc.Dycore(c)
     d = nhdc.Dycore(c)
-    d.set_block_sizes(column, vertex)
+    d.set_block_sizes(column, vertex, waves)
     for _ in range(3):
         ref.step(c.dt, 5)
         d.step(c.dt, 5)
     s, r = d.get_state(), ref.get_state()
     for f in FIELDS:
-        assert np.array_equal(s[f], r[f]), (column, vertex, f)
+        assert np.array_equal(s[f], r[f]), (column, vertex, waves, f)
     with pytest.raises(nhdc.NhdcError):
         d.set_block_sizes(96, 256)
+    with pytest.raises(nhdc.NhdcError):
+        d.set_block_sizes(256, 256, 1)
     d.close()
     ref.close()
 
@@ -131,7 +134,7 @@ def test_persistent_batch_autotune_restores_state(tmp_path):
     b.set_persistent(True)
     before = [d.get_state() for d in ds]
     best = b.autotune([c.dt for c in cases], 5, cache_path=str(tmp_path / "t.json"))
-    assert all(t in (0, 48, 32, 16, 8) for t in best[:3]) and best[5] > 0
+    assert all(t in (0, 48, 32, 16, 8) for t in best[:3]) and best[6] > 0
     assert "persistent" in open(tmp_path / "t.json").read()
     for d, s0 in zip(ds, before):
         s = d.get_state()
