@@ -115,7 +115,8 @@ def algorithmic_bytes(nc, ne, nv, N, prec="fp64", nsub=5, nt=4):
     return {k: sum(v) / len(v) for k, v in t.items()}
 
 
-KERNEL_SOURCES = ("nhdc_step.inc", "nhdc_fp64.hip", "nhdc_mixed.hip", "nhdc_internal.h")
+KERNEL_SOURCES = ("nhdc_step.inc", "nhdc_fp64.hip", "nhdc_mixed.hip", "nhdc_mixed_vn32.hip",
+                  "nhdc_internal.h")
 
 
 def kernel_source_hash():

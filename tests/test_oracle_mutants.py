@@ -86,16 +86,40 @@ MUTANTS = [
 ]
 
 
-@pytest.mark.parametrize("what,old,new,pins", MUTANTS, ids=[m[0] for m in MUTANTS])
-def test_planted_mistake_is_caught(tmp_path, what, old, new, pins):
+def _run_mutant(workdir, old, new, pins, threads):
+    """Build the oracle with one planted mistake and run the named pins
+    against it in a child pytest; returns (build ok, pytest return code, output)."""
     src = open(SRC).read()
-    assert src.count(old) == 1, f"the text to change is not unique in the oracle: {old!r}"
-    mutant = tmp_path / "nhdc_oracle.c"
-    mutant.write_text(src.replace(old, new))
-    so = str(tmp_path / "liboracle_mutant.so")
-    r = subprocess.run(OB.command(str(mutant), so), capture_output=True, text=True)
-    assert r.returncode == 0, r.stderr
-    env = dict(os.environ, ORACLE_SO=so, OMP_NUM_THREADS=os.environ.get("OMP_NUM_THREADS", "8"))
+    mutant = os.path.join(workdir, "nhdc_oracle.c")
+    with open(mutant, "w") as f:
+        f.write(src.replace(old, new))
+    so = os.path.join(workdir, "liboracle_mutant.so")
+    r = subprocess.run(OB.command(mutant, so), capture_output=True, text=True)
+    if r.returncode != 0:
+        return False, r.returncode, r.stderr
+    env = dict(os.environ, ORACLE_SO=so, OMP_NUM_THREADS=str(threads))
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", *pins],
-                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
-    assert r.returncode == 1 and "failed" in r.stdout, (what, r.stdout[-2000:])
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=900)
+    return True, r.returncode, r.stdout
+
+
+@pytest.fixture(scope="module")
+def mutant_runs(tmp_path_factory):
+    """All planted mistakes, built and run a few at a time (each child with
+    a share of the cores), so that builds and start-up overlap."""
+    from concurrent.futures import ThreadPoolExecutor
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 8))
+    workers = max(1, min(4, cores // 2))
+    threads = max(1, cores // workers)
+    dirs = {m[0]: str(tmp_path_factory.mktemp("mutant")) for m in MUTANTS}
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        futs = {m[0]: ex.submit(_run_mutant, dirs[m[0]], m[1], m[2], m[3], threads) for m in MUTANTS}
+        return {k: f.result() for k, f in futs.items()}
+
+
+@pytest.mark.parametrize("what,old,new,pins", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_planted_mistake_is_caught(mutant_runs, what, old, new, pins):
+    assert open(SRC).read().count(old) == 1, f"the text to change is not unique in the oracle: {old!r}"
+    built, rc, out = mutant_runs[what]
+    assert built, out
+    assert rc == 1 and "failed" in out, (what, out[-2000:])
