@@ -862,7 +862,8 @@ def _kernel_id(name):
     """rocprofv3 kernel name -> (kernel id as in kernel_stats, precision); the
     builds of the upwind option get the suffix _upwind."""
     m = re.search(r"k_(vt_edge|vertex|cell_vt|edge_pred|edge_corr|column|cell_grad|div4|smag_cell|"
-                  r"smag_edge|tr_save|tr_recon|tr_horiz|tr_vert)<(double|float)((?:, (?:true|false))*)>",
+                  r"smag_edge|tr_save|tr_recon|tr_horiz|tr_vert)<(double|float)((?:, (?:true|false))*)"
+                  r"(?:, \d+)?>",
                   name)
     if not m:
         return None, None
