@@ -536,8 +536,6 @@ def bench_headline(args, torch, nhdc, CS):
     mcount = step_traffic(src_hash, "mixed", case.nsub, args.order, tag)
     forms["mixed"]["roofline"]["step"] = step_accounting(
         forms["mixed"]["value"], "mixed", None if mcount is None else mcount / units_per_step)
-    if args.copy_calibration:
-        calibration_copy(torch)
     workload = (f"R2B{g.k} ({g.n_cells} cells) x {case.n_lev} levels to 75 km, terrain, "
                 f"dt={case.dt:g}s, {case.nsub} substeps, FP64 plain")
     del case
@@ -568,6 +566,8 @@ def bench_headline(args, torch, nhdc, CS):
     if "config4" in want:
         log("batch of 16 ...")
         forms["config4_batch16"] = bench_batch_form(args, torch, nhdc, CS, stream)
+    if args.copy_calibration:  # the run's last device work: the copy the counters are scaled by
+        calibration_copy(torch)
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -988,8 +988,9 @@ def summarise_set(src, dst, key, tag):
     # ---- HBM counters ----
     fetch, write = _counter(src, f"{key}fetch", "FETCH_SIZE"), _counter(src, f"{key}write", "WRITE_SIZE")
     copy = [k for k in fetch if "copyBuffer" in k]
-    # the calibration copy is the last device copy of the profiled run
-    cf, cw = fetch[copy[0]][-1], write[copy[0]][-1]
+    # the calibration copy: the largest device copy of the profiled run (1 GiB;
+    # the state copies of the run are smaller)
+    cf, cw = max(fetch[copy[0]]), max(write[copy[0]])
     fs, ws = (1 << 30) / (cf * 1024), (1 << 30) / (cw * 1024)
     for prec in ("fp64", "mixed", "mixed_vn32"):
         alg = algorithmic_bytes(nc, ne, nv, N, prec)
@@ -1115,7 +1116,7 @@ def order_summary(src, dst):
                 k, p = _kernel_id(r["Kernel_Name"])
                 if k and p == "fp64":
                     vals[k].append(float(r["Counter_Value"]))
-            cal[kind] = (1 << 30) / (copies[-1] * 1024)
+            cal[kind] = (1 << 30) / (max(copies) * 1024)
             acc[kind] = {k: sum(v) / len(v) * 1024 * cal[kind] for k, v in vals.items()}
         for k in acc["fetch"]:
             out[k] = acc["fetch"][k] + acc["write"].get(k, 0.0)
@@ -1182,7 +1183,7 @@ def config_summary(src, dst):
                 k, _ = _kernel_id(r["Kernel_Name"])
                 if k:
                     acc[k] += float(r["Counter_Value"])
-            cal[kind] = (1 << 30) / (copies[-1] * 1024)
+            cal[kind] = (1 << 30) / (max(copies) * 1024)
             per[kind] = {k: v * 1024 * cal[kind] / meta[kind]["steps_run"] for k, v in acc.items()}
             tot[kind] = sum(per[kind].values())
         step_bytes = tot["fetch"] + tot["write"]
@@ -1225,7 +1226,7 @@ def damped_summary(src, dst, runs, src_hash, wl, nc, ne, nv, N):
             dur[k] = (float(r["AverageNs"]) / 1e3, int(r["Calls"]))
     fetch, write = _counter(src, "dfetch", "FETCH_SIZE"), _counter(src, "dwrite", "WRITE_SIZE")
     copy = [k for k in fetch if "copyBuffer" in k]
-    cf, cw = fetch[copy[0]][-1], write[copy[0]][-1]
+    cf, cw = max(fetch[copy[0]]), max(write[copy[0]])
     fs, ws = (1 << 30) / (cf * 1024), (1 << 30) / (cw * 1024)
     per = defaultdict(lambda: [[], []])
     for kname, vals in fetch.items():
