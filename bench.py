@@ -744,6 +744,8 @@ def bench_batch(args, torch, nhdc, CS):
         ds = [nhdc.Dycore(c, precision="mixed") for c in cases]
         b = nhdc.Batch(ds)
         b.set_tiles(*args.tiles)
+        if args.persistent:
+            b.set_persistent(True)
         dts = [c.dt for c in cases]
         ms = timed_steps(torch, lambda: b.step(dts, 5, 1, stream), steps, args.warmup, stream)
         b.close()
@@ -825,6 +827,14 @@ CONFIG_CMDS = {
                    f"--counters --no-cpu-baseline{{tiles}} > gpurun_out/prof_c{cfg}{kind}.json"
              for kind, ctr in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE"))}}
     for cfg in (3, 4, 5)}
+# kernel traces of the batch of 16 on its two paths (graph of launches,
+# persistent launch) over the warm-up and timed steps at fixed tiles: how much
+# of a step the GPU spends between launches
+BATCH_TRACE_CMDS = {
+    path: f"rocprofv3 --kernel-trace --output-format csv -d gpurun_out/prof_b{path} -o b{path} -- "
+          f"python3 -u bench.py --config 4 --steps 3 --warmup 1 --counters --no-cpu-baseline"
+          f"{' --persistent' if path == 'persistent' else ''} > gpurun_out/prof_b{path}.json"
+    for path in ("graph", "persistent")}
 # the same workload in a 3-D Hilbert numbering, the bisection's own and a
 # random one, against the bisection-curve numbering of the main runs
 ORDER_CMDS = {
@@ -925,6 +935,7 @@ def profile_summary(src, dst):
         damped_summary(src, dst, runs, runs["dtrace"]["kernel_source_sha256_16"], wl, nc,
                        nc * 3 // 2, nc // 2 + 2, N)
     config_summary(src, dst)
+    batch_trace_summary(src, dst)
     order_summary(src, dst)
     if all(os.path.exists(os.path.join(src, f"prof_{k}.json")) for k in ISSUE_CMDS):
         issue_summary(src, dst)
@@ -1155,6 +1166,46 @@ def order_summary(src, dst):
     print("numbering: " + ", ".join(f"{o} {r['ms']:.2f} ms" for o, r in res.items()))
 
 
+def batch_trace_summary(src, dst):
+    """profiles/dycore_config4_batch_paths.txt: per step of the batch of 16,
+    the span from the first kernel's start to the last one's end, the sum of
+    the kernel durations and the gaps between launches, on the graph path and
+    on the persistent path (one launch per step), from the kernel traces."""
+    runs = {}
+    for path in BATCH_TRACE_CMDS:
+        f = os.path.join(src, f"prof_b{path}", f"b{path}_kernel_trace.csv")
+        j = os.path.join(src, f"prof_b{path}.json")
+        if not (os.path.exists(f) and os.path.exists(j)):
+            return
+        meta = json.loads(open(j).read().strip().splitlines()[-1])
+        rows_ = [r for r in _rows(f) if _kernel_id(r["Kernel_Name"])[0] or "k_persistent" in r["Kernel_Name"]]
+        rows_.sort(key=lambda r: int(r["Start_Timestamp"]))
+        nsteps = meta["steps_run"]
+        per_step = len(rows_) // nsteps
+        steps = []
+        for i in range(1, nsteps):  # the warm-up step aside
+            blk = rows_[i * per_step:(i + 1) * per_step]
+            t0 = min(int(r["Start_Timestamp"]) for r in blk)
+            t1 = max(int(r["End_Timestamp"]) for r in blk)
+            busy = sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in blk)
+            steps.append((t1 - t0, busy, len(blk)))
+        span = sum(x[0] for x in steps) / len(steps) / 1e6
+        busy = sum(x[1] for x in steps) / len(steps) / 1e6
+        runs[path] = (span, busy, steps[0][2], meta)
+    lines = ["# the batch of 16 (R2B4-R2B6 x 30-90 levels, FP32-mixed) on its two paths: kernel traces",
+             f"kernel_source_sha256_16: {runs['graph'][3]['kernel_source_sha256_16']}"]
+    lines += [f"command ({p}): {c}" for p, c in BATCH_TRACE_CMDS.items()]
+    lines += ["summarised by: python3 bench.py --profile-summary gpurun_out",
+              "per step (the timed steps of each trace): span = last kernel end - first kernel start; "
+              "busy = sum of kernel durations; gaps = span - busy (one stream: kernels do not overlap)", "",
+              f"{'path':12s} {'launches':>9s} {'span_ms':>9s} {'busy_ms':>9s} {'gaps_ms':>8s} {'gaps%':>6s}"]
+    for p, (span, busy, n, _) in runs.items():
+        lines.append(f"{p:12s} {n:9d} {span:9.3f} {busy:9.3f} {span - busy:8.3f} {100 * (span - busy) / span:6.2f}")
+    with open(os.path.join(dst, "dycore_config4_batch_paths.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("batch paths: " + ", ".join(f"{p} span {v[0]:.2f} ms, gaps {v[0] - v[1]:.3f} ms" for p, v in runs.items()))
+
+
 def config_summary(src, dst):
     """profiles/dycore_config{3,4,5}_hbm.txt: whole-step HBM bytes of each
     workload from its counter passes (every dispatch of a step kernel, summed,
@@ -1287,6 +1338,8 @@ def main():
     ap.add_argument("--counters", action="store_true",
                     help="configs 3-5: run only the warm-up and timed steps (no kernel table, "
                          "error table, sequential runs or autotuning), for a hardware-counter pass")
+    ap.add_argument("--persistent", action="store_true",
+                    help="config 4 with --counters: the persistent path")
     ap.add_argument("--tiles", type=lambda x: [int(v) for v in x.split(",")], default=[0, 0, 0],
                     help="config 4 with --counters: level tiles lt_edge,lt_cell,lt_vert")
     ap.add_argument("--forms", default="vn32,config1,r2b6,config3,config4",

@@ -278,8 +278,9 @@ int nhdc_set_tiles(nhdc_ctx *ctx, int lt_edge, int lt_cell, int lt_vert);
  * column and the vertex kernels, the kernels whose work needs no per-block
  * tables (the others run in blocks of 256), and column_waves, the waves per
  * SIMD the column kernel may occupy (2 or 3, reserved through LDS; 0 = as
- * many as its registers allow, 4; the default is 3: fewer columns in flight
- * keep more of the solve's scratch round trip in the caches).  Results do not
+ * many as its registers allow, 4).  The defaults are 256, 64 and 3 (fewer
+ * columns in flight keep more of the solve's scratch round trip in the
+ * caches).  Results do not
  * depend on them; only speed does.  EINVAL for another value, ESTATE before
  * nhdc_upload_grid. */
 int nhdc_set_block_sizes(nhdc_ctx *ctx, int column, int vertex, int column_waves);

@@ -191,9 +191,12 @@ struct Sub {
 // col_waves caps the waves per SIMD of the column kernel (0: as many as its
 // registers allow, 4) by reserving LDS per block: fewer columns in flight at
 // once keep more of their scratch round trip in the caches (3 measured best).
+// The defaults are the shapes the autotuner picks for the R2B6x90 and
+// R2B8x90 workloads (the vertex kernel in blocks of 64: 1 % faster at R2B6,
+// the same at R2B8).
 struct Tune {
     int lt_edge = 0, lt_cell = 0, lt_vert = 0;
-    int blk_col = BLOCK, blk_vert = BLOCK;
+    int blk_col = BLOCK, blk_vert = 64;
     int col_waves = 3;
 };
 inline bool valid_block(int b) { return b == 64 || b == 128 || b == 256; }

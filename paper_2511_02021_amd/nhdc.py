@@ -174,8 +174,9 @@ class Dycore:
     """One dynamical-core instance resident on a GPU."""
 
     def __init__(self, case, precision="fp64", device=0, init=True, allocator=None):
-        """allocator: None (the library's hipMalloc) or "torch" (PyTorch's
-        caching allocator, through nhdc_set_allocator)."""
+        """allocator: None (the library's hipMalloc), "torch" (PyTorch's
+        caching allocator) or an object whose `alloc` and `free` are
+        nhdc_set_allocator callbacks (ctypes functions it keeps alive)."""
         self.L = lib()
         self.case = case
         self.grid = case.grid
@@ -190,10 +191,13 @@ class Dycore:
         self.allocator = None
         if allocator == "torch":
             self.allocator = TorchAllocator(device)
-            self._check(self.L.nhdc_set_allocator(self.h, self.allocator.alloc,
-                                                  self.allocator.free, None))
+        elif allocator is not None and hasattr(allocator, "alloc") and hasattr(allocator, "free"):
+            self.allocator = allocator  # an object with nhdc_set_allocator callbacks
         elif allocator is not None:
             raise ValueError(f"unknown allocator {allocator!r}")
+        if self.allocator is not None:
+            self._check(self.L.nhdc_set_allocator(self.h, self.allocator.alloc,
+                                                  self.allocator.free, None))
         g = case.grid
         keep = {}
 
@@ -324,9 +328,10 @@ class Dycore:
         """Levels per lane of the marching kernels (0 = whole column)."""
         self._check(self.L.nhdc_set_tiles(self.h, int(lt_edge), int(lt_cell), int(lt_vert)))
 
-    def set_block_sizes(self, column=256, vertex=256, column_waves=3):
+    def set_block_sizes(self, column=256, vertex=64, column_waves=3):
         """Lanes per block of the column and vertex kernels (64, 128, 256) and
-        the column kernel's waves per SIMD (2, 3; 0 = uncapped)."""
+        the column kernel's waves per SIMD (2, 3; 0 = uncapped); the
+        defaults are the library's."""
         self._check(self.L.nhdc_set_block_sizes(self.h, int(column), int(vertex), int(column_waves)))
 
     def autotune(self, dt, nsub, cache_path=None, stream=None):
@@ -404,7 +409,7 @@ class Batch:
     def set_tiles(self, lt_edge=0, lt_cell=0, lt_vert=0):
         self._check(self.L.nhdc_batch_set_tiles(self.h, int(lt_edge), int(lt_cell), int(lt_vert)))
 
-    def set_block_sizes(self, column=256, vertex=256, column_waves=3):
+    def set_block_sizes(self, column=256, vertex=64, column_waves=3):
         self._check(self.L.nhdc_batch_set_block_sizes(self.h, int(column), int(vertex),
                                                       int(column_waves)))
 
