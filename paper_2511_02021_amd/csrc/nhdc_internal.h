@@ -331,6 +331,13 @@ struct nhdc_ctx {
     int in_batches = 0;             // live batches holding this context's descriptor
     bool destroy_pending = false;   // nhdc_destroy came while batched: freed by the last batch
     nhdc::Allocator al;             // device memory source (nhdc_set_allocator)
+    // mixed forms: one device allocation holding the grid, state and work
+    // arrays of the context (sized at upload), from which they are carved in
+    // turn at 2 MiB boundaries: one contiguous range instead of some sixty
+    // separate allocations measured 5-7 % faster steps at R2B8x90 (the FP64
+    // form measured the same or slower and keeps separate allocations)
+    char *arena = nullptr;
+    size_t arena_size = 0, arena_used = 0;
     nhdc::Tune tune;
     nhdc::Launcher L;
     nhdc::Timing tm;

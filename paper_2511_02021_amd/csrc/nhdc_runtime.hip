@@ -387,6 +387,7 @@ void free_context(nhdc_ctx *ctx) {
         dev_free(ctx->al, ctx->L.d_insts);
         for (void *q : ctx->allocs) dev_free(ctx->al, q);
         for (void *q : ctx->tr_allocs) dev_free(ctx->al, q);
+        dev_free(ctx->al, ctx->arena);
     }
     delete ctx;
 }
@@ -406,9 +407,74 @@ int set_err(nhdc_ctx *ctx, int code, const std::string &msg) {
         if (e_ != hipSuccess) return nhdc::hip_fail((ctx)->err, e_, #call); \
     } while (0)
 
+// Arrays carved from the arena start on 2 MiB boundaries (measured faster
+// than packing them at 256 bytes).
+constexpr size_t kArenaAlign = size_t(2) << 20;
+
+// Bytes of the arena: every array nhdc_upload_grid allocates, in its order,
+// each rounded to kArenaAlign (cell_vt's block tables counted whether or not
+// the grid's blocks fit them).
+size_t arena_bytes(const nhdc_grid *g, const nhdc_vertical *v, const nhdc_params *p, int precision) {
+    const int64_t nc = g->n_cells, ne = g->n_edges, nv = g->n_verts, N = v->n_lev;
+    const int64_t NC = N * nc, NC1 = (N + 1) * nc, NE = N * ne, NV = N * nv, NV1 = (N + 1) * nv;
+    const int64_t nbc = (nc + BLOCK - 1) / BLOCK, nbe = (ne + BLOCK - 1) / BLOCK;
+    size_t total = 0;
+    auto add = [&](int64_t n, size_t size) {
+        total += (size_t(n > 0 ? n : 1) * size + kArenaAlign - 1) & ~(kArenaAlign - 1);
+    };
+    const bool f32 = fp32_stencils(precision);
+    const size_t rt = f32 ? 4 : 8, vb = size_t(vn_bytes(precision));
+    // connectivity and block tables (int32)
+    for (int i = 0; i < 3; ++i) add(3 * nc, 4);                        // c_e, c_n, c_v
+    add(nbc * CVT_E, 4); add(nbc * CVT_V, 4); add(nbc * CVT_X, 4); add(3 * nbc, 4);
+    for (int i = 0; i < 3; ++i) add(3 * nc, 4);                        // c_el, c_vl, c_nl
+    add(3 * nc, 4);                                                    // c_ns
+    add(2 * ne, 4);                                                    // e_c
+    add(nbe * 2 * BLOCK, 4); add(nbe, 4); add(2 * ne, 4);              // eb_cells, eb_n, e_loc
+    add(2 * ne, 4); add(6 * nv, 4); add(6 * nv, 4);                    // e_v, v_e, v_c
+    // FP64 coefficients, and their FP32 copies in the mixed forms
+    const int64_t geo[] = {3 * nc, 9 * nc, 3 * nc, nc, nc, ne, ne, 3 * ne, ne, 6 * nv, 6 * nv, nv, nv};
+    for (int64_t n : geo) add(n, 8);
+    if (f32)
+        for (int i = 0; i < 13; ++i)
+            if (i != 3) add(geo[i], 4);                                // (no FP32 cell area)
+    // heights and reference profiles
+    add(NC1, 8); add(NC, 8); add(NC, 8); add(NV1, 8);
+    if (p->upwind) { add(3 * ne, 8); add(3 * ne, 8); }
+    if (g->edge_normal) add(3 * ne, 8);
+    if (g->dual_frac) add(ne, 8);
+    if (v->w_damp) add(N + 1, 8);
+    add(2 * (N + 1) + 2 * N, 4);                                       // flat-top rows
+    // state and accumulators
+    for (int i = 0; i < 5; ++i) add(NC, 8);                            // rho, pi, thv, pi_prev, px
+    add(NC1, 8); add(NC1, 8);                                          // w, wacc
+    add(vb == 4 ? (NE + 1) / 2 : NE, 8); add(NE, 8);                   // vn, facc
+    // work arrays
+    add(NC, rt); add(NC, rt);                                          // kc, dvn
+    for (int i = 0; i < 4; ++i) add(NC1, rt);                          // wcc0, tw0, wcc1, tw1
+    add(NE, rt); add(NE, rt);                                          // vt, tvn0
+    add(NV, rt); add(NV1, rt);                                         // zeta, wv
+    add(NC, 8); add(NC, 8); add(NC1, 8);                               // rhos, thvs, ws
+    add(vb == 4 ? (NE + 1) / 2 : NE, 8);                               // vns
+    add(2 * NC, 8); add(2 * NC1, 8); add(2 * NE, 8);                   // rp, cd, fh
+    if (p->upwind) add(6 * NC, 8);
+    if (p->div_damp4 != 0.0) add(NC, rt);
+    if (p->smag > 0.0) add(NC, rt);
+    add(2 * nbc + 2, 8); add(1, 4);                                    // reduction partials, flag
+    return total;
+}
+
+// Device array of n elements: carved from the context's arena while it has
+// room, else a device allocation of its own.
 template <class T>
-int dalloc(nhdc_ctx *ctx, T **p, int64_t n) {
+int dalloc(nhdc_ctx *ctx, T **p, int64_t n, bool arena = true) {
     size_t bytes = size_t(n > 0 ? n : 1) * sizeof(T);
+    const size_t carve = (bytes + kArenaAlign - 1) & ~(kArenaAlign - 1);
+    if (arena && ctx->arena && ctx->arena_used + carve <= ctx->arena_size) {
+        *p = reinterpret_cast<T *>(ctx->arena + ctx->arena_used);
+        ctx->arena_used += carve;
+        return NHDC_OK;
+    }
     void *q = dev_alloc(ctx->al, bytes);
     if (!q)
         return set_err(ctx, NHDC_ENOMEM, "device allocation of " + std::to_string(bytes) +
@@ -614,7 +680,7 @@ int nhdc_set_allocator(nhdc_ctx *ctx, void *(*alloc)(size_t bytes, void *user),
     if (!ctx) return NHDC_EINVAL;
     if ((alloc == nullptr) != (free_ == nullptr))
         return set_err(ctx, NHDC_EINVAL, "set_allocator: give both callbacks or neither");
-    if (ctx->grid_ready || !ctx->allocs.empty())
+    if (ctx->grid_ready || !ctx->allocs.empty() || ctx->arena)
         return set_err(ctx, NHDC_ESTATE, "set_allocator: must come before nhdc_upload_grid");
     ctx->al = Allocator{alloc, free_, alloc ? user : nullptr};
     ctx->L.al = ctx->al;
@@ -667,6 +733,16 @@ int nhdc_upload_grid(nhdc_ctx *ctx, const nhdc_grid *g, const nhdc_vertical *v,
     ctx->p = Params{prm->omega, prm->grav, prm->rd, prm->cpd, prm->p00, prm->beta,
                     prm->wgt_corr, prm->extrap, prm->div_damp, prm->upwind, prm->div_damp4,
                     prm->smag};
+    if (fp32_stencils(ctx->precision)) {
+        // the mixed forms: one allocation for the arrays below (without it,
+        // no memory for one piece, each array is allocated on its own).  The
+        // FP64 form keeps separate allocations: from one range it measured
+        // the same or slower.
+        const size_t want = arena_bytes(g, v, prm, ctx->precision);
+        ctx->arena = static_cast<char *>(dev_alloc(ctx->al, want));
+        ctx->arena_size = ctx->arena ? want : 0;
+        ctx->arena_used = 0;
+    }
 
     // ---- stencil coefficients on the host (each formed exactly as the
     // operators form it, so device sums see the same operands) ----
@@ -1141,7 +1217,7 @@ int nhdc_set_tracers(nhdc_ctx *ctx, int n_tracers, const double *q, int on_devic
         double **arr[] = {&ctx->tr.q, &ctx->tr.rec, &ctx->tr.qs, &ctx->tr.rs, &ctx->tr.rho0};
         const int64_t len[] = {n_tracers * NC, 3 * n_tracers * NC, n_tracers * NC, NC, NC};
         for (int i = 0; i < 5; ++i) {
-            int rc = dalloc(ctx, arr[i], len[i]);
+            int rc = dalloc(ctx, arr[i], len[i], false);
             if (rc) return rc;
             ctx->allocs.pop_back();  // owned by the tracer list, freed on replacement
             ctx->tr_allocs.push_back(*arr[i]);

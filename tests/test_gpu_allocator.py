@@ -31,7 +31,8 @@ def test_torch_allocator_owns_the_context_memory_and_results_are_bitwise():
     # [N+1][nc]; rho, pi, theta_v, pi_prev and the extrapolated Exner [N][nc]
     state_bytes = 8 * (2 * N * ne + 2 * (N + 1) * nc + 5 * N * nc)
     assert grown >= state_bytes, (grown, state_bytes)
-    assert d.allocator.live > 30
+    # FP64: every array an allocation of its own
+    assert d.allocator.live > 30, d.allocator.live
     ref = nhdc.Dycore(c)  # hipMalloc
     assert torch.cuda.memory_allocated(0) - base == grown  # the library's own memory is not torch's
     for _ in range(3):
@@ -102,3 +103,26 @@ def test_destroying_a_batched_context_defers_its_release():
     ds[1].close()
     torch.cuda.synchronize()
     assert torch.cuda.memory_allocated(0) == base
+
+
+@pytest.mark.parametrize("precision", ["mixed", "mixed_vn32"])
+def test_arena_holds_every_array_with_every_option(precision):
+    """The mixed forms take their arrays from one arena: with the upwind,
+    damping, sponge and diffusion options (the most arrays) they all fit it,
+    nothing falls back to an allocation of its own (two allocations in all:
+    the arena and the launch descriptors), and the results are bitwise those
+    of the library's own allocations."""
+    nhdc = _nhdc()
+    c = CS.with_params(CS.with_damping(CS.config_case(2, k=3, n_lev=20), sponge_base=20000.0),
+                       upwind=1)
+    d = nhdc.Dycore(c, precision=precision, allocator="torch")
+    assert d.allocator.live == 2, d.allocator.live
+    ref = nhdc.Dycore(c, precision=precision)
+    for _ in range(2):
+        d.step(c.dt, 5)
+        ref.step(c.dt, 5)
+    s, r = d.get_state(), ref.get_state()
+    for f in FIELDS:
+        assert np.array_equal(s[f], r[f]), (precision, f)
+    d.close()
+    ref.close()
