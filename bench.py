@@ -560,6 +560,9 @@ def bench_headline(args, torch, nhdc, CS):
         r1["steps"] = 20
         forms["config1_r2b4x20"] = r1
         log(f"R2B4x20 fp64: {r1['ms_per_step']:.3f} ms/step ({r1['value']:.4e})")
+    if "small" in want:
+        log("small shares ...")
+        forms["small_shares"] = bench_small_shares(args, torch, nhdc, CS, stream)
     if "config3" in want:
         log("R2B7x90 mixed ...")
         forms["config3_r2b7x90_mixed"] = bench_config3(args, torch, nhdc, CS, stream)
@@ -595,6 +598,52 @@ def bench_headline(args, torch, nhdc, CS):
         "kernels": short_table(kern),
         "kernel_source_sha256_16": src_hash,
     }
+
+
+def bench_small_shares(args, torch, nhdc, CS, stream):
+    """Shares of one GPU near the paper's strong-scaling floor (about 10 800
+    cells per GPU at 90 levels, Sec. 5): R2B3 (5120 cells) and R2B4 (20480
+    cells) x 90 levels of the R2B6x90 recipe, FP64.  Each with the library's
+    starting shapes for its size (level tiles, the level-parallel column),
+    with whole columns and the streaming column, and with the autotuner's
+    shapes; and the two column builds' kernel times."""
+    out = {}
+    for k in (3, 4):
+        c = CS.config_case(2, k=k, order=args.order)
+        units = c.grid.n_cells * c.n_lev * c.nsub
+        d = nhdc.Dycore(c)
+        steps = 30
+        r = {"workload": f"R2B{k} ({c.grid.n_cells} cells) x {c.n_lev} levels to 75 km, terrain, "
+                         f"dt={c.dt:g}s, {c.nsub} substeps, FP64 plain"}
+
+        def run(tag):
+            ms = timed_steps(torch, lambda: d.step(c.dt, c.nsub, stream), steps, 3, stream) / steps
+            r[tag] = {"ms_per_step": ms, "value": units / (ms / 1e3)}
+            return ms
+
+        run("starting_shapes")
+        cols = {}
+        for mode, name in ((1, "levels"), (0, "stream")):
+            d.set_column_mode(mode)
+            tab = kernel_table(d, c, 4, stream, "fp64")
+            cols[name] = {kk: round(tab[kk]["avg_ms"], 4) for kk in ("column_pred", "column_corr")}
+        r["column_kernels_ms"] = cols
+        d.set_tiles(0, 0, 0)
+        d.set_column_mode(0)
+        run("whole_columns_stream")
+        best = d.autotune(c.dt, c.nsub)
+        run("autotuned")
+        r["autotuned"]["shapes"] = {"lt_edge": best[0], "lt_cell": best[1], "lt_vert": best[2],
+                                    "column_mode": best[7]}
+        d.check_finite()
+        d.close()
+        r["speedup_starting_vs_whole_stream"] = (r["whole_columns_stream"]["ms_per_step"]
+                                                 / r["starting_shapes"]["ms_per_step"])
+        log(f"  R2B{k}x90: starting shapes {r['starting_shapes']['ms_per_step']:.3f} ms/step, whole columns "
+            f"{r['whole_columns_stream']['ms_per_step']:.3f}, autotuned {r['autotuned']['ms_per_step']:.3f}; "
+            f"columns levels {cols['levels']} stream {cols['stream']}")
+        out[f"r2b{k}x90"] = r
+    return out
 
 
 def bench_config3(args, torch, nhdc, CS, stream):
@@ -1342,11 +1391,13 @@ def main():
                     help="config 4 with --counters: the persistent path")
     ap.add_argument("--tiles", type=lambda x: [int(v) for v in x.split(",")], default=[0, 0, 0],
                     help="config 4 with --counters: level tiles lt_edge,lt_cell,lt_vert")
-    ap.add_argument("--forms", default="vn32,config1,r2b6,config3,config4",
+    ap.add_argument("--forms", default="vn32,config1,r2b6,small,config3,config4",
                     help="other forms and workloads carried in the line: vn32 (the mixed form with vn "
                          "stored in FP32, same workload), config1 (R2B4x20 FP64), "
                          "r2b6 (R2B6x90 in both forms "
-                         "with the options), config3 (R2B7x90 mixed with its error after 100 steps), "
+                         "with the options), small (R2B3x90 and R2B4x90 FP64: shares near the paper's "
+                         "strong-scaling floor, the column builds and shapes), "
+                         "config3 (R2B7x90 mixed with its error after 100 steps), "
                          "config4 (the batch of 16 against sequential runs); 'none' for none")
     ap.add_argument("--options", default="upwind,damped,tracers",
                     help="options timed on the R2B6x90 FP64 step: upwind, damped, tracers; 'none'")

@@ -271,7 +271,11 @@ int nhdc_sizes(const nhdc_ctx *ctx, int64_t *n_cells, int64_t *n_edges, int64_t 
 /* Level tiles of the marching kernels: each lane handles lt levels of one
  * entity (0 = the whole column).  Results do not depend on the tiles; only
  * speed does.  Edge kernels, the cell tendency kernel and the vertex kernel
- * are tiled separately. */
+ * are tiled separately.  nhdc_upload_grid (and nhdc_batch_create, by the
+ * cells of all its instances) picks the starting shapes by size: up to 40960
+ * cells, tiles of 8, 8 and 16 levels and the level-parallel column
+ * (NHDC_COLUMN_LEVELS); up to 163840 cells, tiles of 32, 16 and 32; beyond,
+ * whole columns.  The calls below override them. */
 int nhdc_set_tiles(nhdc_ctx *ctx, int lt_edge, int lt_cell, int lt_vert);
 
 /* Block shapes: the block sizes (lanes per workgroup: 64, 128 or 256) of the
@@ -285,17 +289,38 @@ int nhdc_set_tiles(nhdc_ctx *ctx, int lt_edge, int lt_cell, int lt_vert);
  * nhdc_upload_grid. */
 int nhdc_set_block_sizes(nhdc_ctx *ctx, int column, int vertex, int column_waves);
 
+/* Column solver build (the implicit vertical solve of Sec. 2, run by the
+ * column kernels of both the predictor and the corrector):
+ *   NHDC_COLUMN_STREAM (the default above 40960 cells): one lane per column marches down its
+ *     levels forming the explicit parts and the Thomas factors, then back up
+ *     with the back substitution and the level updates; the factors and the
+ *     explicit parts of every level go to device memory in between.
+ *   NHDC_COLUMN_LEVELS: the levels of a column are shared among the lanes of
+ *     a block (16 columns per block of 256 lanes, 8 beyond 200 levels); the
+ *     lanes form their levels' explicit parts in parallel into LDS, one lane
+ *     per column runs the Thomas recurrence and the back substitution there,
+ *     and the lanes apply their levels' updates in parallel.  For small
+ *     shares of the GPU, where one lane's march down a whole column sets the
+ *     step time.
+ * Both give the same results to the bit (the same values formed by the same
+ * operations in the same order); only speed differs.  EINVAL for another
+ * mode, ESTATE before nhdc_upload_grid. */
+#define NHDC_COLUMN_STREAM 0
+#define NHDC_COLUMN_LEVELS 1
+int nhdc_set_column_mode(nhdc_ctx *ctx, int mode);
+
 /* The autotuner (the paper tunes its GPU kernels per configuration, Sec.
  * 3.2; here a search the library runs itself): a coordinate search over the
- * level tiles and the block sizes of this context's grid, each candidate
- * timed over whole steps of (dt, nsubsteps) on `stream`; keeps the fastest
- * and reports it in best[7] = {lt_edge, lt_cell, lt_vert, block_column,
- * block_vertex, column_waves, ms per step}.  The state is saved before and restored after
+ * level tiles, the block sizes and the column mode of this context's grid,
+ * each candidate timed over whole steps of (dt, nsubsteps) on `stream`;
+ * keeps the fastest and reports it in best[8] = {lt_edge, lt_cell, lt_vert,
+ * block_column, block_vertex, column_waves, ms per step, column_mode} (the
+ * caller provides 8 doubles).  The state is saved before and restored after
  * the search.  If cache_path is not NULL it names a JSON file (object of
  * "key": [lt_edge, lt_cell, lt_vert, block_column, block_vertex, column_waves,
- * ms], the key
- * naming the precision, the launch path and the instances' shapes) that is
- * read first (a hit skips the search) and updated after a search. */
+ * ms, column_mode], the key naming the precision, the launch path and the
+ * instances' shapes) that is read first (a hit skips the search) and updated
+ * after a search. */
 int nhdc_autotune(nhdc_ctx *ctx, double dt, int nsubsteps, const char *cache_path,
                   double *best, void *stream);
 
@@ -323,6 +348,9 @@ int nhdc_batch_step(nhdc_batch *b, const double *dt, int nsubsteps, int nsteps, 
 int nhdc_batch_set_tiles(nhdc_batch *b, int lt_edge, int lt_cell, int lt_vert);
 /* As nhdc_set_block_sizes, for the batch's launches (not the persistent one). */
 int nhdc_batch_set_block_sizes(nhdc_batch *b, int column, int vertex, int column_waves);
+/* As nhdc_set_column_mode, for the batch's launches (the persistent launch
+ * runs the streaming build). */
+int nhdc_batch_set_column_mode(nhdc_batch *b, int mode);
 /* Persistent form (on = 1): each step's substeps run as ONE cooperative
  * launch over every instance, with as many blocks as the GPU holds at once
  * (blocks_per_cu > 0 caps the blocks per compute unit below that); its

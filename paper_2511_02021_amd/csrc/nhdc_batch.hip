@@ -46,6 +46,7 @@ void drop_graph(nhdc_batch *b) {
 int upload_pmaps(nhdc_batch *b, const Tune &t) {
     Tune tp = t;
     tp.blk_col = tp.blk_vert = BLOCK;
+    tp.col_mode = 0;  // the persistent kernel runs the streaming column
     Launcher tmp;
     rebuild_maps(tmp, b->ctxs, tp);
     PMaps h;
@@ -66,9 +67,7 @@ int upload_pmaps(nhdc_batch *b, const Tune &t) {
 
 bool graph_matches(const nhdc_batch *b, const double *dt, int nsub) {
     if (!b->exec || b->graph_nsub != nsub) return false;
-    if (b->graph_tune.lt_edge != b->tune.lt_edge || b->graph_tune.lt_cell != b->tune.lt_cell ||
-        b->graph_tune.lt_vert != b->tune.lt_vert)
-        return false;
+    if (!same_tune(b->graph_tune, b->tune)) return false;  // tiles, block sizes, column mode
     for (size_t i = 0; i < b->ctxs.size(); ++i)
         if (b->graph_dt[i] != dt[i]) return false;
     return true;
@@ -139,6 +138,9 @@ int nhdc_batch_create(nhdc_batch **out, nhdc_ctx *const *inst, int n) {
         delete b;
         return NHDC_ENOMEM;
     }
+    int64_t cells = 0;
+    for (auto *c : b->ctxs) cells += c->g.nc;
+    b->tune = default_tune(cells);
     rebuild_maps(b->L, b->ctxs, b->tune);
     for (auto *c : b->ctxs) ++c->in_batches;
     *out = b;
@@ -186,6 +188,15 @@ int nhdc_batch_set_block_sizes(nhdc_batch *b, int column, int vertex, int column
     b->tune.blk_col = column;
     b->tune.blk_vert = vertex;
     b->tune.col_waves = column_waves;
+    rebuild_maps(b->L, b->ctxs, b->tune);
+    return NHDC_OK;
+}
+
+int nhdc_batch_set_column_mode(nhdc_batch *b, int mode) {
+    if (!b) return NHDC_EINVAL;
+    if (!valid_col_mode(mode))
+        return set_err(b->err, NHDC_EINVAL, "batch: column mode must be 0 (stream) or 1 (levels)");
+    b->tune.col_mode = mode;
     rebuild_maps(b->L, b->ctxs, b->tune);
     return NHDC_OK;
 }

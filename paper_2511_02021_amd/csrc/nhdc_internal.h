@@ -194,11 +194,52 @@ struct Sub {
 // The defaults are the shapes the autotuner picks for the R2B6x90 and
 // R2B8x90 workloads (the vertex kernel in blocks of 64: 1 % faster at R2B6,
 // the same at R2B8).
+// col_mode selects the column build: 0 one lane per column, marching down
+// and up the whole column (the streaming build); 1 the level-parallel build,
+// the levels of a column shared among lanes and the Thomas factors in LDS
+// (k_column_stg).  Both give the same results to the bit.
 struct Tune {
     int lt_edge = 0, lt_cell = 0, lt_vert = 0;
     int blk_col = BLOCK, blk_vert = 64;
     int col_waves = 3;
+    int col_mode = 0;
 };
+// The shapes a launch set starts with, by its cells summed over instances.
+// A share too small to fill the GPU with one lane per column spends its step
+// waiting on one level after another: such shares run the marching kernels
+// in level tiles and the level-parallel column.  Measured on 90-level grids
+// in FP64, ms per step with whole columns -> these shapes: R2B3 (5120 cells)
+// 6.2 -> 1.2, R2B4 (20480) 7.1 -> 3.1, R2B5 (81920, tiles only) 10.9 -> 9.2;
+// R2B6 and larger run best in whole columns with the streaming column.
+inline Tune default_tune(int64_t cells) {
+    Tune t;
+    if (cells <= 40960) {
+        t.lt_edge = t.lt_cell = 8;
+        t.lt_vert = 16;
+        t.col_mode = 1;
+    } else if (cells <= 163840) {
+        t.lt_edge = 32;
+        t.lt_cell = 16;
+        t.lt_vert = 32;
+    }
+    return t;
+}
+inline bool same_tune(const Tune &a, const Tune &b) {
+    return a.lt_edge == b.lt_edge && a.lt_cell == b.lt_cell && a.lt_vert == b.lt_vert &&
+           a.blk_col == b.blk_col && a.blk_vert == b.blk_vert && a.col_waves == b.col_waves &&
+           a.col_mode == b.col_mode;
+}
+inline bool valid_col_mode(int m) { return m == 0 || m == 1; }
+// The level-parallel column: its LDS per block for up to nmax levels (six
+// arrays of nmax + 1 rows of C + 1 doubles), and its columns per block: 16
+// (a wavefront's 16-column rows then read whole 128-byte lines), or 8 or 4
+// where the arrays would exceed the device's LDS per block
+inline unsigned stg_lds(int width, int nmax) { return unsigned(6 * (nmax + 1) * (width + 1) * 8); }
+inline int stg_width(int nmax, int max_lds) {
+    for (int w = 16; w > 4; w /= 2)
+        if (stg_lds(w, nmax) <= unsigned(max_lds)) return w;
+    return 4;
+}
 inline bool valid_block(int b) { return b == 64 || b == 128 || b == 256; }
 inline bool valid_waves(int w) { return w == 0 || w == 2 || w == 3; }
 // LDS per block that lets a CU (160 KB of LDS, 4 SIMDs of 64-lane waves)
@@ -250,7 +291,10 @@ struct Launcher {
     Map maps[KIND_NUM];
     int64_t nblocks[KIND_NUM] = {0};
     int block[KIND_NUM] = {BLOCK, BLOCK, BLOCK, BLOCK};  // lanes per block of each kind's launches
-    unsigned dyn_lds[KIND_NUM] = {0, 0, 0, 0};           // LDS reserved per block (occupancy cap)
+    unsigned dyn_lds[KIND_NUM] = {0, 0, 0, 0};           // LDS per block (occupancy cap, or the staged column's arrays)
+    int col_width = 0;             // columns per block of the level-parallel column (0: streaming build)
+    Map trmap;                     // the tracers' column march: whole columns, blocks of BLOCK lanes
+    int64_t trblocks = 0;
 };
 
 // kernels (nhdc_fp64.hip / nhdc_mixed.hip / nhdc_mixed_vn32.hip)
@@ -311,8 +355,11 @@ hipError_t launch_exner_x(const Grid &g, const State &s, double eps, hipStream_t
 hipError_t timing_begin(Timing *tm, int id, hipStream_t st);
 hipError_t timing_end(Timing *tm, hipStream_t st);
 // block map of one kind over a set of grids, with that kind's block size
+// (entities: the entities per block when > 0, else the kind's block size)
 void build_map(Map &m, int64_t &nblocks, Kind kind, const Grid *const *grids, int n,
-               const Tune &t);
+               const Tune &t, int entities = 0);
+// LDS bytes one block may use on a device (cached per device)
+int device_max_lds(int device);
 int kind_block(Kind kind, const Tune &t);
 
 }  // namespace nhdc

@@ -132,11 +132,25 @@ hipError_t run_step_persistent(const Launcher &L, const PMaps *d_pm, int grid, c
 void rebuild_maps(Launcher &L, const std::vector<nhdc_ctx *> &ctxs, const Tune &t) {
     std::vector<const Grid *> grids;
     for (auto *c : ctxs) grids.push_back(&c->g);
-    for (int k = 0; k < KIND_NUM; ++k) {
-        build_map(L.maps[k], L.nblocks[k], Kind(k), grids.data(), int(grids.size()), t);
-        L.block[k] = kind_block(Kind(k), t);
-        L.dyn_lds[k] = k == KIND_COLUMN ? occupancy_lds(t.col_waves, L.block[k]) : 0u;
+    L.col_width = 0;
+    int nmax = 0;
+    for (auto *g : grids) nmax = g->N > nmax ? g->N : nmax;
+    if (t.col_mode == 1) {  // the level-parallel column: BLOCK lanes over col_width columns
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+        L.col_width = stg_width(nmax, device_max_lds(dev));
     }
+    for (int k = 0; k < KIND_NUM; ++k) {
+        const int ent = k == KIND_COLUMN ? L.col_width : 0;
+        build_map(L.maps[k], L.nblocks[k], Kind(k), grids.data(), int(grids.size()), t, ent);
+        L.block[k] = ent ? BLOCK : kind_block(Kind(k), t);
+        L.dyn_lds[k] = ent ? stg_lds(ent, nmax)
+                     : k == KIND_COLUMN ? occupancy_lds(t.col_waves, L.block[k]) : 0u;
+    }
+    Tune tt = t;
+    tt.blk_col = BLOCK;
+    tt.col_mode = 0;
+    build_map(L.trmap, L.trblocks, KIND_COLUMN, grids.data(), int(grids.size()), tt);
 }
 
 // The descriptor of one instance in the precision of its work arrays.
@@ -236,8 +250,8 @@ static int snapshot(const Allocator &al, const std::vector<nhdc_ctx *> &ctxs,
 }
 
 // ---- JSON cache: one entry per line,
-// "key": [lt_edge, lt_cell, lt_vert, block_column, block_vertex, column_waves, ms] ----
-constexpr int kBest = 7;
+// "key": [lt_edge, lt_cell, lt_vert, block_column, block_vertex, column_waves, ms, column_mode] ----
+constexpr int kBest = 8;
 static bool cache_lookup(const char *path, const std::string &key, double best[kBest]) {
     if (!path) return false;
     std::ifstream f(path);
@@ -254,7 +268,8 @@ static bool cache_lookup(const char *path, const std::string &key, double best[k
         std::istringstream is(body);
         for (int i = 0; i < kBest; ++i)
             if (!(is >> best[i])) return false;
-        return valid_block(int(best[3])) && valid_block(int(best[4])) && valid_waves(int(best[5]));
+        return valid_block(int(best[3])) && valid_block(int(best[4])) && valid_waves(int(best[5])) &&
+               valid_col_mode(int(best[7]));
     }
     return false;
 }
@@ -272,8 +287,9 @@ static void cache_store(const char *path, const std::string &key, const double b
         }
     }
     char buf[512];
-    std::snprintf(buf, sizeof(buf), "  \"%s\": [%d, %d, %d, %d, %d, %d, %.6f]", key.c_str(), int(best[0]),
-                  int(best[1]), int(best[2]), int(best[3]), int(best[4]), int(best[5]), best[6]);
+    std::snprintf(buf, sizeof(buf), "  \"%s\": [%d, %d, %d, %d, %d, %d, %.6f, %d]", key.c_str(),
+                  int(best[0]), int(best[1]), int(best[2]), int(best[3]), int(best[4]), int(best[5]),
+                  best[6], int(best[7]));
     entries.push_back(buf);
     std::ofstream f(path, std::ios::trunc);
     f << "{\n";
@@ -303,6 +319,7 @@ int autotune(Launcher &L, Tune &tune, const std::vector<nhdc_ctx *> &ctxs, const
         tune.blk_col = int(best[3]);
         tune.blk_vert = int(best[4]);
         tune.col_waves = int(best[5]);
+        tune.col_mode = int(best[7]);
         hipError_t e = apply(tune);
         if (e != hipSuccess) return hip_fail(err, e, "autotune: set-up");
         if (best_out)
@@ -331,23 +348,29 @@ int autotune(Launcher &L, Tune &tune, const std::vector<nhdc_ctx *> &ctxs, const
         return NHDC_OK;
     };
     // coordinate search: each parameter in turn over its candidates, keeping
-    // the best so far (level tiles of edges, cells, vertices; block sizes of
-    // the column and vertex kernels, when the path takes them)
+    // the best so far (the column mode first, as it changes what the column
+    // block shapes mean; level tiles of edges, cells, vertices; block sizes
+    // of the column and vertex kernels, when the path takes them)
     Tune bt = tune;
     double bms = 0.0;
     rc = measure(bt, bms);
+    const int cand_m[] = {0, 1};
     const int cand_ec[] = {0, 48, 32, 16, 8};
     const int cand_v[] = {0, 32, 16};
     const int cand_b[] = {256, 128, 64};
     const int cand_w[] = {3, 0, 2};
-    const int nparam = stepper.block_sizes ? 6 : 3;
-    for (int param = 0; param < nparam && !rc; ++param) {
-        const int *cand = param < 2 ? cand_ec : param == 2 ? cand_v : param < 5 ? cand_b : cand_w;
-        const int ncand = param < 2 ? 5 : 3;
+    const int nparam = stepper.block_sizes ? 7 : 3;
+    for (int pi = 0; pi < nparam && !rc; ++pi) {
+        // parameter order: [mode,] tiles e, c, v [, block column, block vertex, waves]
+        const int param = stepper.block_sizes ? (pi == 0 ? 6 : pi - 1) : pi;
+        const int *cand = param == 6 ? cand_m : param < 2 ? cand_ec : param == 2 ? cand_v
+                        : param < 5 ? cand_b : cand_w;
+        const int ncand = param == 6 ? 2 : param < 2 ? 5 : 3;
         for (int q = 0; q < ncand; ++q) {
             Tune t = bt;
             int &slot = param == 0 ? t.lt_edge : param == 1 ? t.lt_cell : param == 2 ? t.lt_vert
-                      : param == 3 ? t.blk_col : param == 4 ? t.blk_vert : t.col_waves;
+                      : param == 3 ? t.blk_col : param == 4 ? t.blk_vert : param == 5 ? t.col_waves
+                      : t.col_mode;
             if (slot == cand[q]) continue;
             slot = cand[q];
             double ms = 0.0;
@@ -374,6 +397,7 @@ int autotune(Launcher &L, Tune &tune, const std::vector<nhdc_ctx *> &ctxs, const
     best[4] = tune.blk_vert;
     best[5] = tune.col_waves;
     best[6] = bms;
+    best[7] = tune.col_mode;
     cache_store(cache_path, key, best);
     if (best_out)
         for (int i = 0; i < kBest; ++i) best_out[i] = best[i];
@@ -1003,6 +1027,7 @@ int nhdc_upload_grid(nhdc_ctx *ctx, const nhdc_grid *g, const nhdc_vertical *v,
     HIP_TRY(ctx, hipDeviceSynchronize());
     std::vector<nhdc_ctx *> one{ctx};
     if ((rc = upload_insts(ctx->L, one, ctx->err))) return rc;
+    ctx->tune = default_tune(nc);
     rebuild_maps(ctx->L, one, ctx->tune);
     ctx->grid_ready = true;
     return NHDC_OK;
@@ -1061,6 +1086,17 @@ int nhdc_set_block_sizes(nhdc_ctx *ctx, int column, int vertex, int column_waves
     ctx->tune.blk_col = column;
     ctx->tune.blk_vert = vertex;
     ctx->tune.col_waves = column_waves;
+    std::vector<nhdc_ctx *> one{ctx};
+    rebuild_maps(ctx->L, one, ctx->tune);
+    return NHDC_OK;
+}
+
+int nhdc_set_column_mode(nhdc_ctx *ctx, int mode) {
+    if (!ctx) return NHDC_EINVAL;
+    if (!ctx->grid_ready) return set_err(ctx, NHDC_ESTATE, "set_column_mode: no grid uploaded");
+    if (!valid_col_mode(mode))
+        return set_err(ctx, NHDC_EINVAL, "set_column_mode: mode must be 0 (stream) or 1 (levels)");
+    ctx->tune.col_mode = mode;
     std::vector<nhdc_ctx *> one{ctx};
     rebuild_maps(ctx->L, one, ctx->tune);
     return NHDC_OK;

@@ -221,14 +221,28 @@ const char *const kKernelNames[K_NUM] = {"vt_edge",   "vertex",      "cell_vt",
                                          "smag_cell",   "smag_edge",   "tr_save",
                                          "tr_recon",    "tr_horiz",    "tr_vert"};
 
+int device_max_lds(int device) {
+    static std::mutex mu;
+    static int cached[MAX_DEVICES] = {};
+    if (device < 0 || device >= MAX_DEVICES) return 65536;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!cached[device]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess || v <= 0)
+            v = 65536;
+        cached[device] = v;
+    }
+    return cached[device];
+}
+
 int kind_block(Kind kind, const Tune &t) {
     const int b = kind == KIND_COLUMN ? t.blk_col : kind == KIND_VERT ? t.blk_vert : BLOCK;
     return valid_block(b) ? b : BLOCK;
 }
 
 void build_map(Map &m, int64_t &nblocks, Kind kind, const Grid *const *grids, int n,
-               const Tune &t) {
-    const int64_t B = kind_block(kind, t);
+               const Tune &t, int entities) {
+    const int64_t B = entities > 0 ? entities : kind_block(kind, t);
     m.n = n;
     m.off[0] = 0;
     for (int i = 0; i < n; ++i) {

@@ -18,6 +18,7 @@ PRECISIONS = {"fp64": NHDC_FP64, "mixed": NHDC_MIXED, "mixed_vn32": NHDC_MIXED_V
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EGRID", -5: "ESTATE", -6: "EUNSTABLE",
           -7: "ETOOBIG"}
 NOALLOC_MAX_CELLS = 65536 * 256  # NHDC_NOALLOC_MAX_CELLS
+COLUMN_STREAM, COLUMN_LEVELS = 0, 1  # NHDC_COLUMN_STREAM, NHDC_COLUMN_LEVELS
 
 EXPORTS = ("nhdc_create", "nhdc_upload_grid", "nhdc_init_state", "nhdc_step", "nhdc_get_state",
            "nhdc_get_mass_flux", "nhdc_diag", "nhdc_check_finite", "nhdc_sizes",
@@ -26,7 +27,8 @@ EXPORTS = ("nhdc_create", "nhdc_upload_grid", "nhdc_init_state", "nhdc_step", "n
            "nhdc_batch_step", "nhdc_batch_set_tiles", "nhdc_batch_autotune",
            "nhdc_batch_last_error", "nhdc_batch_destroy", "nhdc_set_tracers", "nhdc_get_tracers",
            "nhdc_n_tracers", "nhdc_diag_noalloc", "nhdc_set_allocator", "nhdc_set_block_sizes",
-           "nhdc_batch_set_block_sizes", "nhdc_batch_set_persistent", "nhdc_batch_persistent_grid")
+           "nhdc_batch_set_block_sizes", "nhdc_batch_set_persistent", "nhdc_batch_persistent_grid",
+           "nhdc_set_column_mode", "nhdc_batch_set_column_mode")
 
 
 class NhdcError(RuntimeError):
@@ -128,6 +130,8 @@ def lib():
         L.nhdc_set_tiles.argtypes = [vp, i, i, i]
         L.nhdc_set_block_sizes.argtypes = [vp, i, i, i]
         L.nhdc_batch_set_block_sizes.argtypes = [vp, i, i, i]
+        L.nhdc_set_column_mode.argtypes = [vp, i]
+        L.nhdc_batch_set_column_mode.argtypes = [vp, i]
         L.nhdc_batch_set_persistent.argtypes = [vp, i, i]
         L.nhdc_batch_persistent_grid.argtypes = [vp]
         L.nhdc_autotune.argtypes = [vp, d, i, C.c_char_p, C.POINTER(d), vp]
@@ -156,6 +160,11 @@ def lib():
 def _np_ptr(a):
     assert isinstance(a, np.ndarray) and a.flags.c_contiguous
     return a.ctypes.data_as(C.c_void_p)
+
+
+def _best_tuple(best):
+    """The autotuner's 8 reported values: shapes as ints, the time as a float."""
+    return tuple(int(x) for x in best[:6]) + (best[6], int(best[7]))
 
 
 def _stream_ptr(stream):
@@ -334,15 +343,21 @@ class Dycore:
         defaults are the library's."""
         self._check(self.L.nhdc_set_block_sizes(self.h, int(column), int(vertex), int(column_waves)))
 
+    def set_column_mode(self, mode):
+        """Column solver build: COLUMN_STREAM (one lane per column, the
+        default) or COLUMN_LEVELS (levels shared among lanes, the factors in
+        LDS); the same results to the bit."""
+        self._check(self.L.nhdc_set_column_mode(self.h, int(mode)))
+
     def autotune(self, dt, nsub, cache_path=None, stream=None):
-        """Search the level tiles and block sizes by timing whole steps; the
-        state is restored.  Returns (lt_edge, lt_cell, lt_vert, block_column,
-        block_vertex, column_waves, ms_per_step)."""
-        best = (C.c_double * 7)()
+        """Search the column mode, level tiles and block sizes by timing whole
+        steps; the state is restored.  Returns (lt_edge, lt_cell, lt_vert,
+        block_column, block_vertex, column_waves, ms_per_step, column_mode)."""
+        best = (C.c_double * 8)()
         path = cache_path.encode() if cache_path else None
         self._check(self.L.nhdc_autotune(self.h, float(dt), int(nsub), path, best,
                                          _stream_ptr(stream)))
-        return tuple(int(x) for x in best[:6]) + (best[6],)
+        return _best_tuple(best)
 
     def set_timing(self, on):
         self._check(self.L.nhdc_set_timing(self.h, int(bool(on))))
@@ -413,6 +428,9 @@ class Batch:
         self._check(self.L.nhdc_batch_set_block_sizes(self.h, int(column), int(vertex),
                                                       int(column_waves)))
 
+    def set_column_mode(self, mode):
+        self._check(self.L.nhdc_batch_set_column_mode(self.h, int(mode)))
+
     def set_persistent(self, on=True, blocks_per_cu=0):
         """Run each step's substeps as one persistent cooperative launch."""
         self._check(self.L.nhdc_batch_set_persistent(self.h, int(bool(on)), int(blocks_per_cu)))
@@ -423,11 +441,11 @@ class Batch:
 
     def autotune(self, dt, nsub, cache_path=None, stream=None):
         """As Dycore.autotune, over the batch on its current path."""
-        best = (C.c_double * 7)()
+        best = (C.c_double * 8)()
         path = cache_path.encode() if cache_path else None
         self._check(self.L.nhdc_batch_autotune(self.h, self._dts(dt), int(nsub), path, best,
                                                _stream_ptr(stream)))
-        return tuple(int(x) for x in best[:6]) + (best[6],)
+        return _best_tuple(best)
 
     def close(self):
         if getattr(self, "h", None):

@@ -134,10 +134,11 @@ def test_autotune_restores_state_and_caches(tmp_path):
         assert np.array_equal(before[f], after[f]), f
     assert all(t in (0, 48, 32, 16, 8) for t in best[:3]) and best[6] > 0
     assert best[3] in (64, 128, 256) and best[4] in (64, 128, 256) and best[5] in (0, 2, 3)
+    assert len(best) == 8 and best[7] in (0, 1)  # the column mode
     txt = open(path).read()
     assert "fp64|launches|" in txt and str(c.grid.n_cells) in txt
-    again = d.autotune(c.dt, 5, cache_path=path)   # cache hit: same tiles, no search
-    assert again[:6] == best[:6] and abs(again[6] - best[6]) < 1e-5
+    again = d.autotune(c.dt, 5, cache_path=path)   # cache hit: same shapes, no search
+    assert again[:6] == best[:6] and abs(again[6] - best[6]) < 1e-5 and again[7] == best[7]
     d.step(c.dt, 5)
     ref, _, _ = _run(c, 2)
     s = d.get_state()
