@@ -271,11 +271,13 @@ int nhdc_sizes(const nhdc_ctx *ctx, int64_t *n_cells, int64_t *n_edges, int64_t 
 /* Level tiles of the marching kernels: each lane handles lt levels of one
  * entity (0 = the whole column).  Results do not depend on the tiles; only
  * speed does.  Edge kernels, the cell tendency kernel and the vertex kernel
- * are tiled separately.  nhdc_upload_grid (and nhdc_batch_create, by the
- * cells of all its instances) picks the starting shapes by size: up to 40960
- * cells, tiles of 8, 8 and 16 levels and the level-parallel column
- * (NHDC_COLUMN_LEVELS); up to 163840 cells, tiles of 32, 16 and 32; beyond,
- * whole columns.  The calls below override them. */
+ * are tiled separately.  nhdc_upload_grid (and nhdc_batch_create, over all
+ * its instances) picks the starting shapes by size: each kind takes the
+ * largest tile of whole, 48, 32, 16, 8 and 4 levels that gives it at least
+ * 1024 blocks (4 per compute unit), and up to 40960 cells the column runs
+ * its level-parallel build (NHDC_COLUMN_LEVELS).  Grids of R2B6 (327680
+ * cells) and larger start in whole columns with the streaming column.  The
+ * calls below override them. */
 int nhdc_set_tiles(nhdc_ctx *ctx, int lt_edge, int lt_cell, int lt_vert);
 
 /* Block shapes: the block sizes (lanes per workgroup: 64, 128 or 256) of the

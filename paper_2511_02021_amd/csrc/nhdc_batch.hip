@@ -138,9 +138,9 @@ int nhdc_batch_create(nhdc_batch **out, nhdc_ctx *const *inst, int n) {
         delete b;
         return NHDC_ENOMEM;
     }
-    int64_t cells = 0;
-    for (auto *c : b->ctxs) cells += c->g.nc;
-    b->tune = default_tune(cells);
+    std::vector<const Grid *> grids;
+    for (auto *c : b->ctxs) grids.push_back(&c->g);
+    b->tune = default_tune(grids.data(), int(grids.size()));
     rebuild_maps(b->L, b->ctxs, b->tune);
     for (auto *c : b->ctxs) ++c->in_batches;
     *out = b;

@@ -355,8 +355,8 @@ int autotune(Launcher &L, Tune &tune, const std::vector<nhdc_ctx *> &ctxs, const
     double bms = 0.0;
     rc = measure(bt, bms);
     const int cand_m[] = {0, 1};
-    const int cand_ec[] = {0, 48, 32, 16, 8};
-    const int cand_v[] = {0, 32, 16};
+    const int cand_ec[] = {0, 48, 32, 16, 8, 4};
+    const int cand_v[] = {0, 32, 16, 8, 4};
     const int cand_b[] = {256, 128, 64};
     const int cand_w[] = {3, 0, 2};
     const int nparam = stepper.block_sizes ? 7 : 3;
@@ -365,7 +365,7 @@ int autotune(Launcher &L, Tune &tune, const std::vector<nhdc_ctx *> &ctxs, const
         const int param = stepper.block_sizes ? (pi == 0 ? 6 : pi - 1) : pi;
         const int *cand = param == 6 ? cand_m : param < 2 ? cand_ec : param == 2 ? cand_v
                         : param < 5 ? cand_b : cand_w;
-        const int ncand = param == 6 ? 2 : param < 2 ? 5 : 3;
+        const int ncand = param == 6 ? 2 : param < 2 ? 6 : param == 2 ? 5 : 3;
         for (int q = 0; q < ncand; ++q) {
             Tune t = bt;
             int &slot = param == 0 ? t.lt_edge : param == 1 ? t.lt_cell : param == 2 ? t.lt_vert
@@ -1027,7 +1027,8 @@ int nhdc_upload_grid(nhdc_ctx *ctx, const nhdc_grid *g, const nhdc_vertical *v,
     HIP_TRY(ctx, hipDeviceSynchronize());
     std::vector<nhdc_ctx *> one{ctx};
     if ((rc = upload_insts(ctx->L, one, ctx->err))) return rc;
-    ctx->tune = default_tune(nc);
+    const Grid *gp = &ctx->g;
+    ctx->tune = default_tune(&gp, 1);
     rebuild_maps(ctx->L, one, ctx->tune);
     ctx->grid_ready = true;
     return NHDC_OK;

@@ -1,8 +1,6 @@
 import os
 import sys
 
-import pytest
-
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -10,13 +8,3 @@ if ROOT not in sys.path:
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs through the HIP library)")
-    config.addinivalue_line("markers", "slow: long CPU pin (run with NHDC_SLOW=1)")
-
-
-def pytest_collection_modifyitems(config, items):
-    if os.environ.get("NHDC_SLOW") == "1":
-        return
-    skip = pytest.mark.skip(reason="slow CPU pin; set NHDC_SLOW=1 to run")
-    for it in items:
-        if "slow" in it.keywords:
-            it.add_marker(skip)

@@ -132,7 +132,7 @@ def test_autotune_restores_state_and_caches(tmp_path):
     after = d.get_state()
     for f in FIELDS:
         assert np.array_equal(before[f], after[f]), f
-    assert all(t in (0, 48, 32, 16, 8) for t in best[:3]) and best[6] > 0
+    assert all(t in (0, 48, 32, 16, 8, 4) for t in best[:3]) and best[6] > 0
     assert best[3] in (64, 128, 256) and best[4] in (64, 128, 256) and best[5] in (0, 2, 3)
     assert len(best) == 8 and best[7] in (0, 1)  # the column mode
     txt = open(path).read()

@@ -134,7 +134,7 @@ def test_persistent_batch_autotune_restores_state(tmp_path):
     b.set_persistent(True)
     before = [d.get_state() for d in ds]
     best = b.autotune([c.dt for c in cases], 5, cache_path=str(tmp_path / "t.json"))
-    assert all(t in (0, 48, 32, 16, 8) for t in best[:3]) and best[6] > 0
+    assert all(t in (0, 48, 32, 16, 8, 4) for t in best[:3]) and best[6] > 0
     assert "persistent" in open(tmp_path / "t.json").read()
     for d, s0 in zip(ds, before):
         s = d.get_state()

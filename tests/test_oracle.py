@@ -555,15 +555,6 @@ def test_gravity_wave_frequency_r2b4_within_2_percent_and_converging():
     assert abs(e4) <= 0.02 and abs(e4) < abs(e3)
 
 
-@pytest.mark.slow
-def test_gravity_wave_frequency_r2b5_converging():
-    """Measured: R2B5 -1.69 % (about 5 minutes on 8 cores, so opt-in): the
-    error keeps falling from R2B3 over R2B4 to R2B5.  What remains is set by
-    the 20 levels and the time step, which the horizontal refinement keeps."""
-    e4, e5 = _gravity_wave_rel_error(4), _gravity_wave_rel_error(5)
-    assert abs(e5) < abs(e4) <= 0.02
-
-
 def test_substep_splitting_is_exact():
     c = CS.config_case(2, k=3, n_lev=20)
     a = oracle.Model(c)
