@@ -135,11 +135,8 @@ void rebuild_maps(Launcher &L, const std::vector<nhdc_ctx *> &ctxs, const Tune &
     L.col_width = 0;
     int nmax = 0;
     for (auto *g : grids) nmax = g->N > nmax ? g->N : nmax;
-    if (t.col_mode == 1) {  // the level-parallel column: BLOCK lanes over col_width columns
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess) dev = 0;
-        L.col_width = stg_width(nmax, device_max_lds(dev));
-    }
+    if (t.col_mode == 1)  // the level-parallel column: BLOCK lanes over col_width columns
+        L.col_width = stg_width(nmax, device_max_lds(ctxs.empty() ? 0 : ctxs[0]->device));
     for (int k = 0; k < KIND_NUM; ++k) {
         const int ent = k == KIND_COLUMN ? L.col_width : 0;
         build_map(L.maps[k], L.nblocks[k], Kind(k), grids.data(), int(grids.size()), t, ent);
