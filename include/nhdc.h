@@ -311,6 +311,12 @@ int nhdc_set_block_sizes(nhdc_ctx *ctx, int column, int vertex, int column_waves
 #define NHDC_COLUMN_LEVELS 1
 int nhdc_set_column_mode(nhdc_ctx *ctx, int mode);
 
+/* The shapes the context's launches use now, into shapes[7] = {lt_edge,
+ * lt_cell, lt_vert, block_column, block_vertex, column_waves, column_mode}:
+ * the starting shapes of nhdc_upload_grid, or what the setters or the
+ * autotuner chose since.  ESTATE before nhdc_upload_grid. */
+int nhdc_get_shapes(const nhdc_ctx *ctx, int *shapes);
+
 /* The autotuner (the paper tunes its GPU kernels per configuration, Sec.
  * 3.2; here a search the library runs itself): a coordinate search over the
  * level tiles, the block sizes and the column mode of this context's grid,
@@ -353,6 +359,8 @@ int nhdc_batch_set_block_sizes(nhdc_batch *b, int column, int vertex, int column
 /* As nhdc_set_column_mode, for the batch's launches (the persistent launch
  * runs the streaming build). */
 int nhdc_batch_set_column_mode(nhdc_batch *b, int mode);
+/* As nhdc_get_shapes, for the batch's launches. */
+int nhdc_batch_get_shapes(const nhdc_batch *b, int *shapes);
 /* Persistent form (on = 1): each step's substeps run as ONE cooperative
  * launch over every instance, with as many blocks as the GPU holds at once
  * (blocks_per_cu > 0 caps the blocks per compute unit below that); its

@@ -201,6 +201,12 @@ int nhdc_batch_set_column_mode(nhdc_batch *b, int mode) {
     return NHDC_OK;
 }
 
+int nhdc_batch_get_shapes(const nhdc_batch *b, int *shapes) {
+    if (!b || !shapes) return NHDC_EINVAL;
+    tune_shapes(b->tune, shapes);
+    return NHDC_OK;
+}
+
 int nhdc_batch_set_persistent(nhdc_batch *b, int on, int blocks_per_cu) {
     if (!b) return NHDC_EINVAL;
     if (hipSetDevice(b->device) != hipSuccess) return set_err(b->err, NHDC_EHIP, "batch: hipSetDevice");

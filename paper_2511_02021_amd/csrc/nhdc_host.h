@@ -25,11 +25,20 @@ struct Stepper {
     std::function<hipError_t(const double *, int, hipStream_t)> step;
     bool block_sizes = true;
 };
-// Coordinate search of the tiles (and block sizes) by timing whole steps on
-// a snapshot of the state, restored afterwards; best_out[6] = {lt_edge,
-// lt_cell, lt_vert, block_column, block_vertex, ms}; the JSON cache is keyed
-// by precision, path_tag and the instances' shapes.
+// Coordinate search of the column mode, the tiles and the block sizes (the
+// tiles alone when the stepper takes no block sizes) by timing whole steps
+// on a snapshot of the state, restored afterwards; best_out[8] = {lt_edge,
+// lt_cell, lt_vert, block_column, block_vertex, column_waves, ms,
+// column_mode}; the JSON cache is keyed by precision, path_tag and the
+// instances' shapes.
 int autotune(Launcher &L, Tune &tune, const std::vector<nhdc_ctx *> &ctxs, const double *dt,
              int nsub, const char *cache_path, double *best_out, hipStream_t st,
              std::string &err, const Stepper &stepper, const char *path_tag);
+// shapes[7] of nhdc_get_shapes: lt_edge, lt_cell, lt_vert, block_column,
+// block_vertex, column_waves, column_mode
+inline void tune_shapes(const Tune &t, int *out) {
+    const int v[7] = {t.lt_edge, t.lt_cell, t.lt_vert, t.blk_col, t.blk_vert, t.col_waves, t.col_mode};
+    for (int i = 0; i < 7; ++i) out[i] = v[i];
+}
+
 }  // namespace nhdc

@@ -1100,6 +1100,13 @@ int nhdc_set_column_mode(nhdc_ctx *ctx, int mode) {
     return NHDC_OK;
 }
 
+int nhdc_get_shapes(const nhdc_ctx *ctx, int *shapes) {
+    if (!ctx || !shapes) return NHDC_EINVAL;
+    if (!ctx->grid_ready) return NHDC_ESTATE;
+    tune_shapes(ctx->tune, shapes);
+    return NHDC_OK;
+}
+
 int nhdc_set_tiles(nhdc_ctx *ctx, int lt_edge, int lt_cell, int lt_vert) {
     if (!ctx) return NHDC_EINVAL;
     if (!ctx->grid_ready) return set_err(ctx, NHDC_ESTATE, "set_tiles: no grid uploaded");

@@ -28,7 +28,8 @@ EXPORTS = ("nhdc_create", "nhdc_upload_grid", "nhdc_init_state", "nhdc_step", "n
            "nhdc_batch_last_error", "nhdc_batch_destroy", "nhdc_set_tracers", "nhdc_get_tracers",
            "nhdc_n_tracers", "nhdc_diag_noalloc", "nhdc_set_allocator", "nhdc_set_block_sizes",
            "nhdc_batch_set_block_sizes", "nhdc_batch_set_persistent", "nhdc_batch_persistent_grid",
-           "nhdc_set_column_mode", "nhdc_batch_set_column_mode")
+           "nhdc_set_column_mode", "nhdc_batch_set_column_mode", "nhdc_get_shapes",
+           "nhdc_batch_get_shapes")
 
 
 class NhdcError(RuntimeError):
@@ -131,6 +132,8 @@ def lib():
         L.nhdc_set_block_sizes.argtypes = [vp, i, i, i]
         L.nhdc_batch_set_block_sizes.argtypes = [vp, i, i, i]
         L.nhdc_set_column_mode.argtypes = [vp, i]
+        L.nhdc_get_shapes.argtypes = [vp, vp]
+        L.nhdc_batch_get_shapes.argtypes = [vp, vp]
         L.nhdc_batch_set_column_mode.argtypes = [vp, i]
         L.nhdc_batch_set_persistent.argtypes = [vp, i, i]
         L.nhdc_batch_persistent_grid.argtypes = [vp]
@@ -349,6 +352,14 @@ class Dycore:
         LDS); the same results to the bit."""
         self._check(self.L.nhdc_set_column_mode(self.h, int(mode)))
 
+    @property
+    def shapes_in_use(self):
+        """(lt_edge, lt_cell, lt_vert, block_column, block_vertex,
+        column_waves, column_mode) of the launches now."""
+        out = (C.c_int * 7)()
+        self._check(self.L.nhdc_get_shapes(self.h, out))
+        return tuple(out)
+
     def autotune(self, dt, nsub, cache_path=None, stream=None):
         """Search the column mode, level tiles and block sizes by timing whole
         steps; the state is restored.  Returns (lt_edge, lt_cell, lt_vert,
@@ -430,6 +441,12 @@ class Batch:
 
     def set_column_mode(self, mode):
         self._check(self.L.nhdc_batch_set_column_mode(self.h, int(mode)))
+
+    @property
+    def shapes_in_use(self):
+        out = (C.c_int * 7)()
+        self._check(self.L.nhdc_batch_get_shapes(self.h, out))
+        return tuple(out)
 
     def set_persistent(self, on=True, blocks_per_cu=0):
         """Run each step's substeps as one persistent cooperative launch."""

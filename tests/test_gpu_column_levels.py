@@ -133,3 +133,22 @@ def test_column_mode_argument_checks():
         b.set_column_mode(3)
     b.close()
     d.close()
+
+
+@pytest.mark.parametrize("k,n_lev,expect", [(3, 90, (4, 4, 4, 1)), (4, 90, (8, 4, 8, 1)),
+                                            (5, 90, (32, 16, 48, 0)), (6, 30, (0, 0, 0, 0))])
+def test_starting_shapes_by_share_size(k, n_lev, expect):
+    """Each marching kind starts with the largest level tile giving at least
+    1024 blocks; the level-parallel column up to 40960 cells."""
+    nhdc = _nhdc()
+    c = CS.make_case(k, n_lev, z_top=75000.0, stretch=1.6, noise_seed=[0, 7, 8], dt=90.0)
+    d = nhdc.Dycore(c)
+    s = d.shapes_in_use
+    assert (s[0], s[1], s[2], s[6]) == expect, s
+    d.set_column_mode(1 - s[6])
+    d.set_tiles(16, 16, 16)
+    assert d.shapes_in_use[:3] == (16, 16, 16) and d.shapes_in_use[6] == 1 - s[6]
+    b = nhdc.Batch([d])
+    assert b.shapes_in_use[:3] == (s[0], s[1], s[2]) and b.shapes_in_use[6] == s[6]  # by the batch's size
+    b.close()
+    d.close()
