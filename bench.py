@@ -378,6 +378,8 @@ def time_form(args, torch, nhdc, case, prec, stream, steps=None, warmup=None, ta
     warmup = args.warmup if warmup is None else warmup
     g = case.grid
     d = nhdc.Dycore(case, precision=prec)
+    if getattr(args, "column_mode", -1) >= 0:
+        d.set_column_mode(args.column_mode)
     ms = timed_steps(torch, lambda: d.step(case.dt, case.nsub, stream), steps, warmup, stream)
     d.check_finite()
     units = g.n_cells * case.n_lev * case.nsub
@@ -597,6 +599,7 @@ def bench_headline(args, torch, nhdc, CS):
         "forms": forms,
         "kernels": short_table(kern),
         "kernel_source_sha256_16": src_hash,
+        **({"column_mode": args.column_mode} if args.column_mode >= 0 else {}),
     }
 
 
@@ -867,6 +870,10 @@ PROFILE_SETS = {
     "h": {"tag": "r2b8x90", "cmds": _prof_cmds("h", " --headline 5 --options none --forms vn32")},
     "s": {"tag": "r2b6x90", "cmds": _prof_cmds("s", " --headline 2 --options upwind")},
     "d": {"tag": "r2b6x90", "cmds": _prof_cmds("d", " --headline 2 --options damped,tracers")},
+    # the R2B6x90 workload with the level-parallel column (its factors in LDS):
+    # the column's bytes without the scratch round trip
+    "l": {"tag": "r2b6x90_levels_column",
+          "cmds": _prof_cmds("l", " --headline 2 --options none --column-mode 1")},
 }
 PROFILE_CMDS = {k + kind: c for k, v in PROFILE_SETS.items() for kind, c in v["cmds"].items()}
 CONFIG_CMDS = {
@@ -920,7 +927,7 @@ OPTION_KERNELS = ("div4", "smag_cell", "smag_edge", "column_pred_sponge", "colum
 def _kernel_id(name):
     """rocprofv3 kernel name -> (kernel id as in kernel_stats, precision); the
     builds of the upwind option get the suffix _upwind."""
-    m = re.search(r"k_(vt_edge|vertex|cell_vt|edge_pred|edge_corr|column|cell_grad|div4|smag_cell|"
+    m = re.search(r"k_(vt_edge|vertex|cell_vt|edge_pred|edge_corr|column_stg|column|cell_grad|div4|smag_cell|"
                   r"smag_edge|tr_save|tr_recon|tr_horiz|tr_vert)<(double|float)((?:, (?:true|false))*)"
                   r"(?:, \d+)?>",
                   name)
@@ -930,7 +937,7 @@ def _kernel_id(name):
     form = "fp64" if m.group(2) == "double" else ("mixed_vn32" if "vn32::" in name else "mixed")
     flags = re.findall(r"true|false", m.group(3))
     upwind = k == "cell_grad"
-    if k == "column":  # flags: corrector, upwind build, sponge build
+    if k in ("column", "column_stg"):  # flags: corrector, upwind build, sponge build (either build)
         k = "column_corr" if flags[0] == "true" else "column_pred"
         upwind = flags[1] == "true"
         if flags[2] == "true":
@@ -1005,7 +1012,10 @@ def summarise_set(src, dst, key, tag):
     cfg = runs["trace"]["config"]
     nc, N = cfg["cells"], cfg["levels"]
     ne, nv = nc * 3 // 2, nc // 2 + 2
-    wl = f"{tag.upper().replace('X', 'x')} ({nc} cells x {N} levels, {runs['trace']['config']['workload']})"
+    wl = (f"{tag.split('_')[0].upper().replace('X', 'x')} ({nc} cells x {N} levels, "
+          f"{runs['trace']['config']['workload']})")
+    if runs["trace"].get("column_mode", -1) == 1:
+        wl += ", level-parallel column"
     numbering = cfg.get("numbering", "curve")
     # ---- kernel trace ----
     stats = _rows(os.path.join(src, f"prof_{key}trace", f"{key}trace_kernel_stats.csv"))
@@ -1387,6 +1397,9 @@ def main():
     ap.add_argument("--counters", action="store_true",
                     help="configs 3-5: run only the warm-up and timed steps (no kernel table, "
                          "error table, sequential runs or autotuning), for a hardware-counter pass")
+    ap.add_argument("--column-mode", type=int, default=-1, choices=(-1, 0, 1),
+                    help="the headline forms' column build: 0 one lane per column, 1 level-parallel "
+                         "(-1: the library's starting shapes; profile set l)")
     ap.add_argument("--persistent", action="store_true",
                     help="config 4 with --counters: the persistent path")
     ap.add_argument("--tiles", type=lambda x: [int(v) for v in x.split(",")], default=[0, 0, 0],
