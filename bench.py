@@ -605,13 +605,14 @@ def bench_headline(args, torch, nhdc, CS):
 
 def bench_small_shares(args, torch, nhdc, CS, stream):
     """Shares of one GPU near the paper's strong-scaling floor (about 10 800
-    cells per GPU at 90 levels, Sec. 5): R2B3 (5120 cells) and R2B4 (20480
-    cells) x 90 levels of the R2B6x90 recipe, FP64.  Each with the library's
-    starting shapes for its size (level tiles, the level-parallel column),
-    with whole columns and the streaming column, and with the autotuner's
-    shapes; and the two column builds' kernel times."""
+    cells per GPU at 90 levels, Sec. 5): R2B3 (5120 cells), R2B4 (20480) and
+    R2B5 (81920) x 90 levels of the R2B6x90 recipe, FP64.  Each with the
+    library's starting shapes for its size (level tiles; the level-parallel
+    column up to 40960 cells), with whole columns and the streaming column,
+    and with the autotuner's shapes; and the two column builds' kernel
+    times."""
     out = {}
-    for k in (3, 4):
+    for k in (3, 4, 5):
         c = CS.config_case(2, k=k, order=args.order)
         units = c.grid.n_cells * c.n_lev * c.nsub
         d = nhdc.Dycore(c)
@@ -1408,7 +1409,7 @@ def main():
                     help="other forms and workloads carried in the line: vn32 (the mixed form with vn "
                          "stored in FP32, same workload), config1 (R2B4x20 FP64), "
                          "r2b6 (R2B6x90 in both forms "
-                         "with the options), small (R2B3x90 and R2B4x90 FP64: shares near the paper's "
+                         "with the options), small (R2B3x90 to R2B5x90 FP64: shares near the paper's "
                          "strong-scaling floor, the column builds and shapes), "
                          "config3 (R2B7x90 mixed with its error after 100 steps), "
                          "config4 (the batch of 16 against sequential runs); 'none' for none")
