@@ -1199,15 +1199,18 @@ def order_summary(src, dst):
     if not all(os.path.exists(p) for _, p in runs.values()) or not all(
             os.path.exists(os.path.join(src, f"prof_o{o}fetch.json")) for o in ORDER_CMDS):
         return
-    res = {}
+    res, hashes = {}, set()
     for o, (tag, path) in runs.items():
         d = json.loads(open(path).read().strip().splitlines()[-1])
         res[o] = {"ms": d["ms_per_step"], "kern": d["kernels"], "bytes": bytes_per_launch(tag)}
+        hashes.add(d.get("kernel_source_sha256_16"))
+    if len(hashes) != 1:
+        raise SystemExit(f"numbering runs used different kernel sources: {hashes}")
     kernels = [k for k in res["curve"]["kern"] if k in res["random"]["kern"]]
     lines = ["# the FP64 R2B6x90 step in four numberings of cells, edges and vertices: the "
              "continuous curve over the bisection tree (the default), a 3-D Hilbert curve "
              "through the cell centres, the bisection's own order, random",
-             f"kernel_source_sha256_16: {kernel_source_hash()}"]
+             f"kernel_source_sha256_16: {hashes.pop()}"]
     for o in ORDER_CMDS:
         lines.append(f"commands ({o}): " + "; ".join(ORDER_CMDS[o][k] for k in ("run", "fetch", "write")))
     lines += ["summarised by: python3 bench.py --profile-summary gpurun_out",
