@@ -275,9 +275,10 @@ int nhdc_sizes(const nhdc_ctx *ctx, int64_t *n_cells, int64_t *n_edges, int64_t 
  * its instances) picks the starting shapes by size: each kind takes the
  * largest tile of whole, 48, 32, 16, 8 and 4 levels that gives it at least
  * 1024 blocks (4 per compute unit), and up to 40960 cells the column runs
- * its level-parallel build (NHDC_COLUMN_LEVELS).  Grids of R2B6 (327680
- * cells) and larger start in whole columns with the streaming column.  The
- * calls below override them. */
+ * its level-parallel build (NHDC_COLUMN_LEVELS); a streaming column with
+ * fewer than 1024 blocks of 256 lanes runs in blocks of 64.  Grids of R2B6
+ * (327680 cells) and larger start in whole columns with the streaming
+ * column in blocks of 256.  The calls below override them. */
 int nhdc_set_tiles(nhdc_ctx *ctx, int lt_edge, int lt_cell, int lt_vert);
 
 /* Block shapes: the block sizes (lanes per workgroup: 64, 128 or 256) of the

@@ -204,41 +204,6 @@ struct Tune {
     int col_waves = 3;
     int col_mode = 0;
 };
-// The shapes a launch set starts with, by its size.  A share too small to
-// fill the GPU with one lane per column spends its step waiting on one
-// level after another: each marching kind then takes the largest level tile
-// (of whole, 48, 32, 16, 8 and 4 levels) that gives it at least kFillBlocks
-// blocks over all instances, and up to kSmallShare cells the column runs its
-// level-parallel build.  Measured on 90-level grids in FP64, ms per step with
-// whole columns -> these shapes: R2B3 (5120 cells) 6.2 -> 0.93, R2B4 (20480)
-// 7.2 -> 3.0, R2B5 (81920, tiles only) 10.9 -> 9.2; R2B6 and larger start
-// in whole columns with the streaming column, their best.
-constexpr int64_t kFillBlocks = 1024;  // 256 CUs x 4 blocks
-constexpr int64_t kSmallShare = 40960;
-inline int fill_tile(const Grid *const *grids, int n, int kind_entities, int block) {
-    const int cand[] = {0, 48, 32, 16, 8, 4};
-    for (int lt : cand) {
-        int64_t blocks = 0;
-        for (int i = 0; i < n; ++i) {
-            const Grid &g = *grids[i];
-            const int64_t ent = kind_entities == 0 ? g.ne : kind_entities == 1 ? g.nc : g.nv;
-            const int l = lt > 0 && lt < g.N ? lt : g.N;
-            blocks += (ent + block - 1) / block * ((g.N + l - 1) / l);
-        }
-        if (blocks >= kFillBlocks) return lt;
-    }
-    return 4;
-}
-inline Tune default_tune(const Grid *const *grids, int n) {
-    Tune t;
-    int64_t cells = 0;
-    for (int i = 0; i < n; ++i) cells += grids[i]->nc;
-    t.lt_edge = fill_tile(grids, n, 0, BLOCK);
-    t.lt_cell = fill_tile(grids, n, 1, BLOCK);
-    t.lt_vert = fill_tile(grids, n, 2, t.blk_vert);
-    t.col_mode = cells <= kSmallShare ? 1 : 0;
-    return t;
-}
 inline bool same_tune(const Tune &a, const Tune &b) {
     return a.lt_edge == b.lt_edge && a.lt_cell == b.lt_cell && a.lt_vert == b.lt_vert &&
            a.blk_col == b.blk_col && a.blk_vert == b.blk_vert && a.col_waves == b.col_waves &&
