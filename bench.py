@@ -119,13 +119,41 @@ KERNEL_SOURCES = ("nhdc_step.inc", "nhdc_fp64.hip", "nhdc_mixed.hip", "nhdc_mixe
                   "nhdc_internal.h")
 
 
+def _code_tokens(src):
+    """`src` (C++ source text) without its comments, every run of white space
+    made one blank; string and character literals are kept as written."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+            out.append(" ")
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        elif c in "\"'":
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        else:
+            out.append(c)
+            i += 1
+    return re.sub(r"\s+", " ", "".join(out)).strip()
+
+
 def kernel_source_hash():
     """Identifies the device code of the step kernels (counter summaries taken
-    on other sources no longer describe them)."""
+    on other code no longer describe them); comments and layout do not count."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2511_02021_amd", "csrc")
     for f in KERNEL_SOURCES:
-        h.update(open(os.path.join(csrc, f), "rb").read())
+        with open(os.path.join(csrc, f), encoding="utf-8") as fh:
+            h.update(_code_tokens(fh.read()).encode())
+        h.update(b"\0")
     return h.hexdigest()[:16]
 
 
