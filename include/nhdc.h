@@ -298,13 +298,13 @@ int nhdc_set_block_sizes(nhdc_ctx *ctx, int column, int vertex, int column_waves
  *     levels forming the explicit parts and the Thomas factors, then back up
  *     with the back substitution and the level updates; the factors and the
  *     explicit parts of every level go to device memory in between.
- *   NHDC_COLUMN_LEVELS: the levels of a column are shared among the lanes of
- *     a block (16 columns per block of 256 lanes, 8 beyond 200 levels); the
- *     lanes form their levels' explicit parts in parallel into LDS, one lane
- *     per column runs the Thomas recurrence and the back substitution there,
- *     and the lanes apply their levels' updates in parallel.  For small
- *     shares of the GPU, where one lane's march down a whole column sets the
- *     step time.
+ *   NHDC_COLUMN_LEVELS (the default up to 40960 cells): the levels of a
+ *     column are shared among the lanes of a block (16 columns per block of
+ *     256 lanes, 8 from 200 levels on); the lanes form their levels' explicit
+ *     parts and tridiagonal rows in parallel into LDS, two lanes per column
+ *     run the Thomas recurrence and the back substitution there, and the
+ *     lanes apply their levels' updates in parallel.  For small shares of the
+ *     GPU, where one lane's march down a whole column sets the step time.
  * Both give the same results to the bit (the same values formed by the same
  * operations in the same order); only speed differs.  EINVAL for another
  * mode, ESTATE before nhdc_upload_grid. */

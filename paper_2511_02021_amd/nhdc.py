@@ -348,8 +348,9 @@ class Dycore:
 
     def set_column_mode(self, mode):
         """Column solver build: COLUMN_STREAM (one lane per column, the
-        default) or COLUMN_LEVELS (levels shared among lanes, the factors in
-        LDS); the same results to the bit."""
+        starting build above 40960 cells) or COLUMN_LEVELS (levels shared
+        among lanes, the factors in LDS; the starting build up to 40960
+        cells); the same results to the bit."""
         self._check(self.L.nhdc_set_column_mode(self.h, int(mode)))
 
     @property
