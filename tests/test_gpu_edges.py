@@ -134,6 +134,38 @@ def test_full_size_r2b7_mixed_properties():
     assert abs(m1 / m0 - 1) <= 1e-13 and abs(r1 / r0 - 1) <= 1e-13
 
 
+def test_full_size_r2b8_fp64_properties():
+    """The R2B8x90 benchmark workload (the paper's 10 km grid, 5.24 M cells)
+    in FP64, in the launch configuration the benchmark times (the starting
+    shapes): one step stays finite and conserves dry mass and rho*theta_v to
+    1e-13 relative; the same step from the same state with the level-parallel
+    column and level tiles of 16 on every marching kind (other kernels, other
+    block maps) gives the same state and mass fluxes to the bit.  The oracle
+    does not run at this size."""
+    print("R2B8x90: building the case", flush=True)
+    c = CS.config_case(5)
+    d = _nhdc().Dycore(c)
+    start = d.shapes_in_use
+    print("R2B8x90: starting shapes", start, flush=True)
+    assert start[:3] == (0, 0, 0) and start[6] == 0
+    m0, r0 = d.diag()
+    d.step(c.dt, c.nsub)
+    d.check_finite()
+    m1, r1 = d.diag()
+    a, fa = d.get_state(), d.mass_flux()
+    print(f"R2B8x90 fp64: mass {m1 / m0 - 1:.2e}  rho*theta_v {r1 / r0 - 1:.2e}", flush=True)
+    d.init_state(c.vn, c.w, c.rho, c.pi, c.theta_v)
+    d.set_column_mode(1)
+    d.set_tiles(16, 16, 16)
+    print("R2B8x90: the same step, level-parallel column, tiles of 16", flush=True)
+    d.step(c.dt, c.nsub)
+    b, fb = d.get_state(), d.mass_flux()
+    d.close()
+    assert abs(m1 / m0 - 1) <= 1e-13 and abs(r1 / r0 - 1) <= 1e-13
+    _same(a, b, "R2B8x90 two builds")
+    assert np.array_equal(fa[0], fb[0]) and np.array_equal(fa[1], fb[1])
+
+
 def test_full_size_r2b6_all_options_one_step_bitwise():
     """The R2B6x90 benchmark workload with every option on (upwind edge
     values, fourth-order divergence damping, the w sponge, the diffusion of
