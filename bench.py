@@ -1456,8 +1456,9 @@ def main():
         profile_summary(args.profile_summary, os.path.join(ROOT, "profiles"))
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); the "
-              "multi-GPU decomposition is a design, not an implementation", file=sys.stderr)
+        print(f"bench.py: the library runs one GPU per process and this benchmark one GPU "
+              f"(got --gpus {args.gpus}); the decomposition over several GPUs is designed "
+              "but not implemented", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2511_02021_amd import nhdc
