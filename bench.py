@@ -399,19 +399,42 @@ def step_accounting(rate, precision, counted_b=None):
     return out
 
 
-def time_form(args, torch, nhdc, case, prec, stream, steps=None, warmup=None, table=True):
+def time_form(args, torch, nhdc, case, prec, stream, steps=None, warmup=None, table=True,
+              handover=False):
     """One form on one case: throughput over `steps` timed steps after
-    `warmup` untimed ones, then (optionally) the per-kernel table."""
+    `warmup` untimed ones, then (optionally) the per-kernel table.  With
+    `handover`, the wall-clock time of handing the state over from pageable
+    host memory before the run and back after it, and the rate that counts
+    both beside the timed steps (the timed steps themselves start with the
+    state resident in HBM either way)."""
     steps = args.steps if steps is None else steps
     warmup = args.warmup if warmup is None else warmup
     g = case.grid
-    d = nhdc.Dycore(case, precision=prec)
+    d = nhdc.Dycore(case, precision=prec, init=not handover)
+    if handover:  # nhdc_init_state from host buffers returns once the copies are done
+        t0 = time.perf_counter()
+        d.init_state(case.vn, case.w, case.rho, case.pi, case.theta_v)
+        up_s = time.perf_counter() - t0
     if getattr(args, "column_mode", -1) >= 0:
         d.set_column_mode(args.column_mode)
     ms = timed_steps(torch, lambda: d.step(case.dt, case.nsub, stream), steps, warmup, stream)
     d.check_finite()
     units = g.n_cells * case.n_lev * case.nsub
     out = {"value": units * steps / (ms / 1e3), "ms_per_step": ms / steps}
+    if handover:  # nhdc_get_state into host buffers, likewise synchronous
+        t0 = time.perf_counter()
+        st = d.get_state()
+        down_s = time.perf_counter() - t0
+        b_in = sum(getattr(case, f).nbytes for f in ("vn", "w", "rho", "pi", "theta_v"))
+        b_out = sum(a.nbytes for a in st.values())
+        del st
+        out["host_handover"] = {
+            "bytes_in": b_in, "upload_s": round(up_s, 3), "upload_GBs": round(b_in / up_s / 1e9, 2),
+            "bytes_out": b_out, "download_s": round(down_s, 3),
+            "download_GBs": round(b_out / down_s / 1e9, 2),
+            "pcie_inclusive_value": units * steps / (ms / 1e3 + up_s + down_s),
+            "basis": f"the {steps} timed steps plus one upload of the initial state and one "
+                     "download of the final state, from and to pageable host memory"}
     if table:
         out["_table"] = kernel_table(d, case, args.timing_steps, stream, prec)
     d.close()
@@ -523,10 +546,14 @@ def bench_headline(args, torch, nhdc, CS):
     forms, tables = {}, {}
     want = [f for f in args.forms.split(",") if f]
     for prec in ("fp64", "mixed"):
-        forms[prec] = time_form(args, torch, nhdc, case, prec, stream)
+        forms[prec] = time_form(args, torch, nhdc, case, prec, stream, handover=prec == "fp64")
         tables[prec] = forms[prec].pop("_table")
         log(f"{prec}: {forms[prec]['ms_per_step']:.3f} ms/step, "
             f"{forms[prec]['value']:.4e} cell-level updates/s")
+        if "host_handover" in forms[prec]:
+            h = forms[prec]["host_handover"]
+            log(f"  state from/to host: {h['upload_s']:.2f} s in, {h['download_s']:.2f} s out; "
+                f"with them {h['pcie_inclusive_value']:.4e} cell-level updates/s")
     forms["mixed"]["speedup_vs_fp64"] = forms["fp64"]["ms_per_step"] / forms["mixed"]["ms_per_step"]
     if args.error_steps > 0:
         log(f"per-field error of the mixed form, {args.error_steps} steps ...")
