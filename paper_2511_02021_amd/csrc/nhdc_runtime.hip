@@ -328,6 +328,8 @@ int autotune(Launcher &L, Tune &tune, const std::vector<nhdc_ctx *> &ctxs, const
     if (rc) return rc;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
         snapshot(L.al, ctxs, snap, true, st, err);
         return set_err(err, NHDC_EHIP, "autotune: hipEventCreate failed");
     }
@@ -382,7 +384,10 @@ int autotune(Launcher &L, Tune &tune, const std::vector<nhdc_ctx *> &ctxs, const
     (void)hipEventDestroy(e1);
     std::string err2;
     int rc2 = snapshot(L.al, ctxs, snap, true, st, err2);
-    if (rc) return rc;
+    if (rc) {  // the launches go back to the shapes they had (the last candidate's are set)
+        (void)apply(tune);
+        return rc;
+    }
     if (rc2) return set_err(err, rc2, err2);
     tune = bt;
     hipError_t e = apply(tune);
