@@ -22,7 +22,9 @@ def probe(tmp_path_factory):
         pytest.skip("hipcc not available")
     exe = str(tmp_path_factory.mktemp("shapes") / "shapes_probe")
     csrc = os.path.join(os.path.dirname(_build.NHDC_SO), "csrc")
-    subprocess.run([hipcc, "-x", "hip", "--offload-arch=gfx950", "-O1", "-I", csrc, "-I", _build.INCLUDE,
+    subprocess.run([hipcc, "-x", "hip", "--offload-arch=gfx950", "-O1",
+                    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                    "-I", csrc, "-I", _build.INCLUDE,
                     os.path.join(HERE, "shapes_probe.cpp"), "-o", exe],
                    check=True, capture_output=True, text=True)
 
