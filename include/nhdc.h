@@ -348,9 +348,12 @@ typedef struct nhdc_batch nhdc_batch;
 #define NHDC_MAX_INST 64
 
 /* Borrow n (1..NHDC_MAX_INST) contexts, all on one device and of one
- * precision, each with grid and state; they must outlive the batch.
- * NHDC_EINVAL for n out of range, a repeated or unready context, or mixed
- * devices or precisions. */
+ * precision, each with grid and state.  A context destroyed while a batch
+ * holds it keeps its device memory, and keeps stepping in the batch, until
+ * the last batch holding it is destroyed (the caller must not use the
+ * context's handle after nhdc_destroy).  NHDC_EINVAL for n out of range, a
+ * repeated context, or mixed devices or precisions; NHDC_ESTATE for a
+ * context without grid or state, or destroyed while another batch holds it. */
 int nhdc_batch_create(nhdc_batch **out, nhdc_ctx *const *instances, int n);
 /* nsteps steps of (dt[i], nsubsteps) for every instance i, enqueued on stream. */
 int nhdc_batch_step(nhdc_batch *b, const double *dt, int nsubsteps, int nsteps, void *stream);
@@ -425,6 +428,8 @@ int nhdc_diag_noalloc(int64_t n_cells, int32_t n_lev, const double *cell_area, c
 /* Message of the context's last failure; with ctx NULL, the calling thread's
  * last failure of a context-free call (nhdc_diag_noalloc). */
 const char *nhdc_last_error(const nhdc_ctx *ctx);
+/* Releases the context and its device memory; a context that a batch still
+ * holds is released by the last nhdc_batch_destroy instead. */
 void nhdc_destroy(nhdc_ctx *ctx);
 
 #ifdef __cplusplus
