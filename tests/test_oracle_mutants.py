@@ -83,6 +83,28 @@ MUTANTS = [
     ("PPM upwind cell swapped",
      "const int up = W[i] > 0.0 ? i : i - 1;", "const int up = W[i] > 0.0 ? i - 1 : i;",
      [T + "test_ppm_column_exact_for_quadratic_under_uniform_advection[0.37-uneven]"]),
+    ("Perot operator without the edge lengths",
+     "{0.0, 0.0, 0.0};\n        for (int j = 0; j < 3; ++j) {\n            int64_t e = g->cell_edges[j * nc + c];\n"
+     "            double wgt = g->cell_sign[j * nc + c] * g->edge_length[e] * u[e];",
+     "{0.0, 0.0, 0.0};\n        for (int j = 0; j < 3; ++j) {\n            int64_t e = g->cell_edges[j * nc + c];\n"
+     "            double wgt = g->cell_sign[j * nc + c] * u[e];",
+     [T + "test_perot_exact_for_uniform_vector_on_a_plane"]),
+    ("the step's Perot reconstruction without the edge lengths",
+     "g->edge_length[e] * u[e];\n                for (int d = 0; d < 3; ++d) v[d] += wgt * (a *",
+     "u[e];\n                for (int d = 0; d < 3; ++d) v[d] += wgt * (a *",
+     [T + "test_solid_body_rotation_convergence"]),
+    ("kinetic energy without the tangential velocity",
+     "0.5 * (un * un + ut * ut);", "0.5 * (un * un);",
+     [T + "test_vn_tendency_of_sheared_solid_body_rotation"]),
+    ("contravariant correction without the tangential slope",
+     "AT(m->vnh, i, ne, e) * AT(m->snh, i, ne, e) +", "AT(m->vnh, i, ne, e) * AT(m->snh, i, ne, e) + 0.0 *",
+     [T + "test_contravariant_correction_over_linear_terrain"]),
+    ("Thomas back substitution with the next row's factor",
+     "x[i] = dp[i] - cp[i] * x[i + 1];", "x[i] = dp[i] - cp[i + 1] * x[i + 1];",
+     [T + "test_thomas_matches_lapack"]),
+    ("mass-flux accumulators summing the substeps instead of averaging them",
+     "m->facc[i] += m->flx[i] / nsub;", "m->facc[i] += m->flx[i];",
+     [T + "test_flux_accumulators_average_the_substeps"]),
 ]
 
 
