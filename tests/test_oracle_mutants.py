@@ -105,6 +105,21 @@ MUTANTS = [
     ("mass-flux accumulators summing the substeps instead of averaging them",
      "m->facc[i] += m->flx[i] / nsub;", "m->facc[i] += m->flx[i];",
      [T + "test_flux_accumulators_average_the_substeps"]),
+    ("Exner coefficient of the column inverted",
+     "B[k] = dt * (rd / cvd) * pi_n[k]", "B[k] = dt * (cvd / rd) * pi_n[k]",
+     [T + "test_column_matches_dense_solve_of_implicit_equations"]),
+    ("theta_v from the inverse of the linearised state equation",
+     "(cvd / rd) * (rt / pi_n[k])", "(rd / cvd) * (rt / pi_n[k])",
+     [T + "test_column_matches_dense_solve_of_implicit_equations"]),
+    ("sub-diagonal with the level below's Exner coefficient",
+     "ta[i - 1] = -ga[i] * B[i - 1] * al[i - 1];", "ta[i - 1] = -ga[i] * B[i] * al[i - 1];",
+     [T + "test_column_matches_dense_solve_of_implicit_equations"]),
+    ("reference-state buoyancy dropped from the explicit w",
+     "(ppn[i - 1] - ppn[i]) / dzh[i] + thph[i] * dref[i];", "(ppn[i - 1] - ppn[i]) / dzh[i];",
+     [T + "test_column_matches_dense_solve_of_implicit_equations"]),
+    ("ground w set to zero instead of the contravariant correction",
+     "wp[N] = wcc[N];", "wp[N] = 0.0;",
+     [T + "test_column_matches_dense_solve_of_implicit_equations"]),
 ]
 
 
