@@ -120,6 +120,12 @@ MUTANTS = [
     ("ground w set to zero instead of the contravariant correction",
      "wp[N] = wcc[N];", "wp[N] = 0.0;",
      [T + "test_column_matches_dense_solve_of_implicit_equations"]),
+    ("pressure gradient without its terrain correction",
+     "AT(gp, k, ne, e) = gl - AT(m->sn, k, ne, e) * dz2;", "AT(gp, k, ne, e) = gl;",
+     [T + "test_terrain_corrected_gradient_of_height_only_field"]),
+    ("vertical derivative of the pressure gradient upside down",
+     "(AT(px, ka, nc, c) - AT(px, kb, nc, c)) /", "(AT(px, kb, nc, c) - AT(px, ka, nc, c)) /",
+     [T + "test_terrain_corrected_gradient_of_height_only_field"]),
 ]
 
 
