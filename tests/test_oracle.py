@@ -567,6 +567,38 @@ def test_substep_splitting_is_exact():
         assert np.array_equal(sa[f], sb[f]), f
 
 
+def test_corrector_weights_the_two_tendencies():
+    """Steps 2, 5 and 6 of the substep with reading 7 (weight cv on the
+    tendency of the predicted state, 1 - cv on that of the old one).  On a
+    flat resting atmosphere the Exner field is horizontally uniform, so the
+    pressure gradient vanishes; with a flow that is the same at every level
+    the vertical advection of vn vanishes too, and with divergence damping
+    off the new vn depends on nothing the column solves.  One substep then
+    gives vn + dt((1 - cv) T(vn) + cv T(vn*)), vn* = vn + dt T(vn), with T the
+    tendency of the VT phase (pinned on its own above).  A fast rotation
+    (f dt up to 0.6) makes the two weightings differ by a fifth of the change."""
+    dt = 300.0
+    for cv in (0.75, 0.3):
+        prm = dataclasses.replace(CS.Params(), omega=1e-3, div_damp=0.0, wgt_corr=cv)
+        c = CS.make_case(3, 6, z_top=20000.0, sigma=0.0, dt=dt, params=prm)
+        g = c.grid
+        m = oracle.Model(c)
+        assert np.all(m.pgrad(c.pi - c.pi_ref) == 0.0)
+        psi = 10.0 * A * g.vert_x[0] * g.vert_x[1]       # a streamfunction: about 10 m/s
+        vn = np.tile(oracle.tgrad(g, psi), (c.n_lev, 1))
+        m.set_state(vn, c.w, c.rho, c.pi, c.theta_v)
+        w0 = np.zeros_like(c.w)
+        t0 = m.vt(vn, w0)[0]
+        t1 = m.vt(vn + dt * t0, w0)[0]
+        m.step(dt, 1)
+        got = m.state()["vn"]
+        want = vn + dt * ((1.0 - cv) * t0 + cv * t1)
+        other = vn + dt * (cv * t0 + (1.0 - cv) * t1)   # the weights the other way round
+        change = np.abs(got - vn).max()
+        assert np.abs(got - want).max() <= 1e-13 * change, cv
+        assert np.abs(other - want).max() >= 0.05 * change, cv
+
+
 def test_numbering_invariance():
     ref = None
     for order, seed in (("canonical", 0), ("sfc", 0), ("random", 5), ("curve", 0)):

@@ -123,6 +123,14 @@ MUTANTS = [
     ("pressure gradient without its terrain correction",
      "AT(gp, k, ne, e) = gl - AT(m->sn, k, ne, e) * dz2;", "AT(gp, k, ne, e) = gl;",
      [T + "test_terrain_corrected_gradient_of_height_only_field"]),
+    ("corrector weights the other way round",
+     "(1.0 - cv) * AT(m->tvn0, k, ne, e) + cv * AT(m->tvn1, k, ne, e)",
+     "cv * AT(m->tvn0, k, ne, e) + (1.0 - cv) * AT(m->tvn1, k, ne, e)",
+     [T + "test_corrector_weights_the_two_tendencies"]),
+    ("corrector's tendencies taken at the old state",
+     "vt_phase(m, m->vns, m->ws, m->tvn1, m->tw1, m->wcc1);",
+     "vt_phase(m, m->vn, m->w, m->tvn1, m->tw1, m->wcc1);",
+     [T + "test_corrector_weights_the_two_tendencies"]),
     ("vertical derivative of the pressure gradient upside down",
      "(AT(px, ka, nc, c) - AT(px, kb, nc, c)) /", "(AT(px, kb, nc, c) - AT(px, ka, nc, c)) /",
      [T + "test_terrain_corrected_gradient_of_height_only_field"]),
