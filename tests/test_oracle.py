@@ -599,6 +599,47 @@ def test_corrector_weights_the_two_tendencies():
         assert np.abs(other - want).max() >= 0.05 * change, cv
 
 
+def test_substep_of_a_horizontally_uniform_column():
+    """Steps 4, 5, 8, 9 and 10 of the substep with readings 7 and 8 (the
+    corrector linearised about n, with the interface state halfway between n
+    and the predicted state and the w tendency weighted cv on the predicted
+    state): with no horizontal flow over flat ground and a state that is the
+    same in every column, nothing horizontal acts, and one substep of the
+    model is the exported column solve applied twice, predictor then
+    corrector, with the w tendency of the exported VT phase.  Checked to the
+    bit in every column, with the accumulated vertical mass flux and the new
+    Exner history; w is an unbalanced ascent, so every term is active."""
+    dt = 60.0
+    prm = dataclasses.replace(CS.Params(), wgt_corr=0.7)
+    c = CS.make_case(2, 12, z_top=24000.0, sigma=0.0, dt=dt, params=prm)
+    g, N = c.grid, c.n_lev
+    m = oracle.Model(c)
+    zh = c.zh[:, 0]
+    w = np.zeros(N + 1)
+    w[1:N] = 0.8 * np.sin(np.pi * zh[1:N] / zh[0])
+    W = np.tile(w[:, None], (1, g.n_cells))
+    vn0 = np.zeros((N, g.n_edges))
+    m.set_state(vn0, W, c.rho, c.pi, c.theta_v)
+    col = lambda a: np.ascontiguousarray(a[:, 0])
+    rho, pi, thv = col(c.rho), col(c.pi), col(c.theta_v)
+    zeros, zeros1 = np.zeros(N), np.zeros(N + 1)
+    base = dict(zh=zh, pi_ref=col(c.pi_ref), theta_ref=col(c.theta_ref), pi_n=pi, rho_n=rho,
+                thv_n=thv, w_n=w, wcc=zeros1, div_rho=zeros, div_th=zeros)
+    tw0 = m.vt(vn0, W)[1][:, 0]
+    pred = oracle.column(prm, dt, rho_i=rho, thv_i=thv, tw=tw0, **base)
+    tw1 = m.vt(vn0, np.tile(pred["w"][:, None], (1, g.n_cells)))[1][:, 0]
+    corr = oracle.column(prm, dt, rho_i=0.5 * (rho + pred["rho"]), thv_i=0.5 * (thv + pred["theta_v"]),
+                         tw=(1.0 - prm.wgt_corr) * tw0 + prm.wgt_corr * tw1, **base)
+    assert np.abs(tw1 - tw0).max() > 1e-3 * np.abs(tw0).max()   # the weighting matters
+    m.step(dt, 1)
+    s = m.state()
+    for f in ("w", "rho", "pi", "theta_v"):
+        assert np.array_equal(s[f], np.tile(corr[f][:, None], (1, g.n_cells))), f
+    assert np.all(s["vn"] == 0.0)
+    assert np.array_equal(s["pi_prev"], c.pi - c.pi_ref)
+    assert np.array_equal(m.flux()[1], np.tile(corr["vflux"][:, None], (1, g.n_cells)))
+
+
 def test_numbering_invariance():
     ref = None
     for order, seed in (("canonical", 0), ("sfc", 0), ("random", 5), ("curve", 0)):

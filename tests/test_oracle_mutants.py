@@ -131,6 +131,17 @@ MUTANTS = [
      "vt_phase(m, m->vns, m->ws, m->tvn1, m->tw1, m->wcc1);",
      "vt_phase(m, m->vn, m->w, m->tvn1, m->tw1, m->wcc1);",
      [T + "test_corrector_weights_the_two_tendencies"]),
+    ("corrector column's interface density without the predicted state",
+     "m->rho_i[i] = 0.5 * (m->rho[i] + m->rhos[i]);", "m->rho_i[i] = m->rho[i];",
+     [T + "test_substep_of_a_horizontally_uniform_column"]),
+    ("w tendency weights the other way round",
+     "m->twm[i] = (1.0 - cv) * m->tw0[i] + cv * m->tw1[i];",
+     "m->twm[i] = cv * m->tw0[i] + (1.0 - cv) * m->tw1[i];",
+     [T + "test_substep_of_a_horizontally_uniform_column"]),
+    ("Exner history from the predicted state",
+     "for (int64_t i = 0; i < NC; ++i) m->pi_prev[i] = m->pi[i] - m->pi_ref[i];",
+     "for (int64_t i = 0; i < NC; ++i) m->pi_prev[i] = m->pis[i] - m->pi_ref[i];",
+     [T + "test_substep_of_a_horizontally_uniform_column"]),
     ("vertical derivative of the pressure gradient upside down",
      "(AT(px, ka, nc, c) - AT(px, kb, nc, c)) /", "(AT(px, kb, nc, c) - AT(px, ka, nc, c)) /",
      [T + "test_terrain_corrected_gradient_of_height_only_field"]),
