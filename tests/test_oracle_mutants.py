@@ -142,6 +142,21 @@ MUTANTS = [
      "for (int64_t i = 0; i < NC; ++i) m->pi_prev[i] = m->pi[i] - m->pi_ref[i];",
      "for (int64_t i = 0; i < NC; ++i) m->pi_prev[i] = m->pis[i] - m->pi_ref[i];",
      [T + "test_substep_of_a_horizontally_uniform_column"]),
+    ("Exner extrapolation with the weights the other way round",
+     "m->pix[i] = (1.0 + eps) * pp - eps * m->pi_prev[i];",
+     "m->pix[i] = (1.0 - eps) * pp + eps * m->pi_prev[i];",
+     [T + "test_substep_equals_its_steps_composed"]),
+    ("divergence damping of the old vn instead of the predicted one",
+     "or_op_div(g, m->vns + (int64_t)k * ne, m->dvs + (int64_t)k * nc);",
+     "or_op_div(g, m->vn + (int64_t)k * ne, m->dvs + (int64_t)k * nc);",
+     [T + "test_substep_equals_its_steps_composed"]),
+    ("corrector fluxes carried by the predicted vn",
+     "flux_phase(m, m->vnn, dt);", "flux_phase(m, m->vns, dt);",
+     [T + "test_substep_equals_its_steps_composed"]),
+    ("corrector pressure gradient weighted by the old theta_v",
+     "0.5 * (AT(m->thvs, k, nc, c1) + AT(m->thvs, k, nc, c2));",
+     "0.5 * (AT(m->thv, k, nc, c1) + AT(m->thv, k, nc, c2));",
+     [T + "test_substep_equals_its_steps_composed"]),
     ("vertical derivative of the pressure gradient upside down",
      "(AT(px, ka, nc, c) - AT(px, kb, nc, c)) /", "(AT(px, kb, nc, c) - AT(px, ka, nc, c)) /",
      [T + "test_terrain_corrected_gradient_of_height_only_field"]),
