@@ -653,13 +653,22 @@ def _substep_by_parts(m, c, prm, dt, st):
     vn, w, rho, pi, thv = (st[f] for f in ("vn", "w", "rho", "pi", "theta_v"))
     pp = pi - c.pi_ref
     gp = m.pgrad((1.0 + eps) * pp - eps * st["pi_prev"])                 # 1, 2
-    tvn0, tw0, wcc0, _ = m.vt(vn, w)
+    tvn0, tw0, wcc0, vt0 = m.vt(vn, w)
     the, rhoe = e_avg(thv), e_avg(rho)
     vns = vn + dt * (tvn0 - cpd * the * gp)
+    if prm.upwind:  # edge values of state n from its cell gradients (readings 31-34)
+        grr = [oracle.cell_grad(g, rho[k]) for k in range(N)]
+        grt = [oracle.cell_grad(g, thv[k]) for k in range(N)]
+        edge_vals = lambda vx, vt: (
+            np.stack([oracle.upwind(g, rho[k], grr[k], vx[k], vt[k], dt) for k in range(N)]),
+            np.stack([oracle.upwind(g, thv[k], grt[k], vx[k], vt[k], dt) for k in range(N)]))
+    else:
+        edge_vals = lambda vx, vt: (rhoe, the)
 
-    def fluxes(vx):                                                      # 3, 7
-        f = rhoe * vx * dz_e
-        h = the * f
+    def fluxes(vx, vt):                                                  # 3, 7
+        re, te = edge_vals(vx, vt)
+        f = re * vx * dz_e
+        h = te * f
         lev = lambda a: np.stack([oracle.div(g, a[k]) for k in range(N)])
         return f, lev(f) / dz, lev(h) / dz
 
@@ -675,30 +684,32 @@ def _substep_by_parts(m, c, prm, dt, st):
                 out[k].append(r[k])
         return {k: np.stack(v, axis=1) for k, v in out.items()}
 
-    _, dr, dth = fluxes(vns)
+    _, dr, dth = fluxes(vns, vt0)
     P = columns(rho, thv, tw0, wcc0, dr, dth)
-    tvn1, tw1, wcc1, _ = m.vt(vns, P["w"])                                # 5
+    tvn1, tw1, wcc1, vt1 = m.vt(vns, P["w"])                              # 5
     dvs = np.stack([oracle.div(g, vns[k]) for k in range(N)])
     abar = 4.0 * np.pi * g.radius * g.radius / nc
     gdiv = (dvs[:, c2] - dvs[:, c1]) * (1.0 / g.dual_length)
     tend = (1.0 - cv) * tvn0 + cv * tvn1 - cpd * e_avg(P["theta_v"]) * gp
     vnn = vn + dt * tend + prm.div_damp * abar * gdiv                     # 6
-    F, dr, dth = fluxes(vnn)
+    F, dr, dth = fluxes(vnn, vt1)
     Q = columns(0.5 * (rho + P["rho"]), 0.5 * (thv + P["theta_v"]),
                 (1.0 - cv) * tw0 + cv * tw1, wcc1, dr, dth)
     new = dict(vn=vnn, w=Q["w"], rho=Q["rho"], pi=Q["pi"], theta_v=Q["theta_v"], pi_prev=pp)  # 10
     return new, F, Q["vflux"]                                             # 9
 
 
-def test_substep_equals_its_steps_composed():
+@pytest.mark.parametrize("upwind", [0, 1], ids=["centred", "upwind"])
+def test_substep_equals_its_steps_composed(upwind):
     """One substep of the model equals steps 1-10 composed from the exported
     operators (each pinned on its own above), on the benchmark's recipe
     (terrain, noisy vn, an unbalanced Exner history so that the extrapolation
-    matters, divergence damping on): the state, Facc and Wacc to the bit.
-    This pins the order and the inputs of the steps: which state each
-    operator sees, the extrapolation and the corrector's weights."""
+    matters, divergence damping on), with centred or upwind edge values: the
+    state, Facc and Wacc to the bit.  This pins the order and the inputs of
+    the steps: which state each operator sees, the extrapolation and the
+    corrector's weights."""
     dt = 90.0
-    prm = dataclasses.replace(CS.Params(), extrap=0.4, wgt_corr=0.7)
+    prm = dataclasses.replace(CS.Params(), extrap=0.4, wgt_corr=0.7, upwind=upwind)
     c = CS.config_case(2, k=2, n_lev=8, params=prm)
     m = oracle.Model(c)
     pp = c.pi - c.pi_ref

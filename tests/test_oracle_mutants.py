@@ -157,6 +157,12 @@ MUTANTS = [
      "0.5 * (AT(m->thvs, k, nc, c1) + AT(m->thvs, k, nc, c2));",
      "0.5 * (AT(m->thv, k, nc, c1) + AT(m->thv, k, nc, c2));",
      [T + "test_substep_equals_its_steps_composed"]),
+    ("upwind edge density from the predicted state",
+     "or_op_upwind(g, m->rho + oc, m->grad_r + 3 * oc,", "or_op_upwind(g, m->rhos + oc, m->grad_r + 3 * oc,",
+     [T + "test_substep_equals_its_steps_composed[upwind]"]),
+    ("theta_v's upwind gradient computed from rho",
+     "or_op_cell_grad(&m->g, m->thv + (int64_t)k * nc,", "or_op_cell_grad(&m->g, m->rho + (int64_t)k * nc,",
+     [T + "test_substep_equals_its_steps_composed[upwind]"]),
     ("vertical derivative of the pressure gradient upside down",
      "(AT(px, ka, nc, c) - AT(px, kb, nc, c)) /", "(AT(px, kb, nc, c) - AT(px, ka, nc, c)) /",
      [T + "test_terrain_corrected_gradient_of_height_only_field"]),
