@@ -679,7 +679,7 @@ def _substep_by_parts(m, c, prm, dt, st):
                               theta_ref=c.theta_ref[:, ci], pi_n=pi[:, ci], rho_n=rho[:, ci],
                               thv_n=thv[:, ci], rho_i=rho_i[:, ci], thv_i=thv_i[:, ci],
                               w_n=w[:, ci], tw=tw[:, ci], wcc=wcc[:, ci], div_rho=dr[:, ci],
-                              div_th=dth[:, ci])
+                              div_th=dth[:, ci], w_damp=c.w_damp)
             for k in out:
                 out[k].append(r[k])
         return {k: np.stack(v, axis=1) for k, v in out.items()}
@@ -692,6 +692,9 @@ def _substep_by_parts(m, c, prm, dt, st):
     gdiv = (dvs[:, c2] - dvs[:, c1]) * (1.0 / g.dual_length)
     tend = (1.0 - cv) * tvn0 + cv * tvn1 - cpd * e_avg(P["theta_v"]) * gp
     vnn = vn + dt * tend + prm.div_damp * abar * gdiv                     # 6
+    if prm.div_damp4 != 0.0:  # fourth-order divergence damping of vn* (reading 35)
+        g4 = np.stack([oracle.graddiv2(g, vns[k]) for k in range(N)])
+        vnn = vnn - prm.div_damp4 * abar * abar * g4
     F, dr, dth = fluxes(vnn, vt1)
     Q = columns(0.5 * (rho + P["rho"]), 0.5 * (thv + P["theta_v"]),
                 (1.0 - cv) * tw0 + cv * tw1, wcc1, dr, dth)
@@ -728,6 +731,52 @@ def test_substep_equals_its_steps_composed(upwind):
     st0 = dict(st, pi_prev=pp)
     other, _, _ = _substep_by_parts(m, c, prm, dt, st0)
     assert not np.array_equal(other["vn"], want["vn"])
+
+
+def _step_by_parts(m, c, prm, dt, nsub, st):
+    """One step: nsub substeps composed as above, the accumulated fluxes
+    averaged over them, then (option) the Smagorinsky diffusion of vn with
+    the step's dt (readings 37-38), from the exported operators."""
+    g, N = c.grid, c.n_lev
+    facc, wacc = np.zeros((N, g.n_edges)), np.zeros((N + 1, g.n_cells))
+    for _ in range(nsub):
+        st, F, W = _substep_by_parts(m, c, prm, dt / nsub, st)
+        facc = facc + F / nsub
+        wacc = wacc + W / nsub
+    if prm.smag > 0.0:
+        abar = 4.0 * np.pi * g.radius * g.radius / g.n_cells
+        kmax = abar / (25.0 * dt)
+        c1, c2 = g.edge_cells[0], g.edge_cells[1]
+        vn = st["vn"].copy()
+        vt = m.vt(vn, st["w"])[3]
+        for k in range(N):
+            kh = prm.smag * prm.smag * g.cell_area * oracle.deformation(g, vn[k], vt[k])
+            ke = 0.5 * (kh[c1] + kh[c2])
+            ke = np.where(ke < kmax, ke, kmax)
+            vn[k] = vn[k] + dt * ke * oracle.vector_laplacian(g, vn[k])
+        st = dict(st, vn=vn)
+    return st, facc, wacc
+
+
+def test_step_with_every_damping_option_equals_its_parts_composed():
+    """A whole step of three substeps with fourth-order divergence damping,
+    the w sponge and the Smagorinsky diffusion (and the upwind fluxes) equals
+    the same step composed from the exported operators: state, Facc and Wacc
+    to the bit."""
+    dt = 90.0
+    c = CS.with_damping(CS.config_case(2, k=2, n_lev=8))
+    prm = dataclasses.replace(c.params, upwind=1)
+    c = dataclasses.replace(c, params=prm)
+    assert c.w_damp is not None and prm.div_damp4 > 0 and prm.smag > 0
+    m = oracle.Model(c)
+    st = m.state()
+    want, facc, wacc = _step_by_parts(m, c, prm, dt, 3, st)
+    m.step(dt, 3)
+    got = m.state()
+    for f in want:
+        assert np.array_equal(got[f], want[f]), f
+    F, W = m.flux()
+    assert np.array_equal(F, facc) and np.array_equal(W, wacc)
 
 
 def test_numbering_invariance():

@@ -163,6 +163,19 @@ MUTANTS = [
     ("theta_v's upwind gradient computed from rho",
      "or_op_cell_grad(&m->g, m->thv + (int64_t)k * nc,", "or_op_cell_grad(&m->g, m->rho + (int64_t)k * nc,",
      [T + "test_substep_equals_its_steps_composed[upwind]"]),
+    ("diffusion over a substep's dt instead of the step's",
+     "if (m->p.smag > 0.0) diffusion_phase(m, dt);", "if (m->p.smag > 0.0) diffusion_phase(m, dts);",
+     [T + "test_step_with_every_damping_option_equals_its_parts_composed"]),
+    ("diffusion with the corrector's tangential velocity instead of the new vn's",
+     "    perot_phase(m, m->vn);\n    for (int k = 0; k < N; ++k) {\n        double *u = m->vn",
+     "    for (int k = 0; k < N; ++k) {\n        double *u = m->vn",
+     [T + "test_step_with_every_damping_option_equals_its_parts_composed"]),
+    ("fourth-order damping added instead of subtracted",
+     "if (damp4) v = v - c4 * AT(m->g4, k, ne, e);", "if (damp4) v = v + c4 * AT(m->g4, k, ne, e);",
+     [T + "test_step_with_every_damping_option_equals_its_parts_composed"]),
+    ("fourth-order damping of the old vn",
+     "or_op_graddiv2(g, m->vns + (int64_t)k * ne,", "or_op_graddiv2(g, m->vn + (int64_t)k * ne,",
+     [T + "test_step_with_every_damping_option_equals_its_parts_composed"]),
     ("vertical derivative of the pressure gradient upside down",
      "(AT(px, ka, nc, c) - AT(px, kb, nc, c)) /", "(AT(px, kb, nc, c) - AT(px, ka, nc, c)) /",
      [T + "test_terrain_corrected_gradient_of_height_only_field"]),
