@@ -176,6 +176,16 @@ MUTANTS = [
     ("fourth-order damping of the old vn",
      "or_op_graddiv2(g, m->vns + (int64_t)k * ne,", "or_op_graddiv2(g, m->vn + (int64_t)k * ne,",
      [T + "test_step_with_every_damping_option_equals_its_parts_composed"]),
+    ("tracer transport from the density at the step's end",
+     "r0 = AT(m->rho0, k, nc, c);", "r0 = AT(m->rho, k, nc, c);",
+     [T + "test_step_with_tracers_equals_its_parts_composed"]),
+    ("vertical tracer pass with the last substep's flux instead of the average",
+     "for (int i = 0; i <= N; ++i) c_W[i] = AT(m->wacc, i, nc, c);",
+     "for (int i = 0; i <= N; ++i) c_W[i] = AT(m->vflux, i, nc, c);",
+     [T + "test_step_with_tracers_equals_its_parts_composed"]),
+    ("horizontal tracer update without the density change",
+     "AT(qs, k, nc, c) = (r0 * qk[c] - dt * hT) / rsc;", "AT(qs, k, nc, c) = (r0 * qk[c] - dt * hT) / r0;",
+     [T + "test_step_with_tracers_equals_its_parts_composed"]),
     ("vertical derivative of the pressure gradient upside down",
      "(AT(px, ka, nc, c) - AT(px, kb, nc, c)) /", "(AT(px, kb, nc, c) - AT(px, ka, nc, c)) /",
      [T + "test_terrain_corrected_gradient_of_height_only_field"]),
