@@ -3,8 +3,10 @@ its code: mimetic identities of the C-grid operators, exactness of the vector
 reconstruction on a plane, closed forms of solid-body rotation, LAPACK on the
 tridiagonal solve, a dense solve of the un-substituted implicit column
 equations, the resting atmosphere, conservation of mass and rho*theta_v, the
-linear gravity-wave dispersion relation, and algebraic invariances
-(numbering, substep splitting, save/resume)."""
+linear gravity-wave dispersion relation, algebraic invariances (numbering,
+substep splitting, save/resume), and the substep and the step composed in
+numpy from the oracle's separately pinned operators in the order the
+discretisation gives (which state each step sees, the time weights)."""
 import dataclasses
 import functools
 import types
