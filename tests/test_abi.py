@@ -66,6 +66,17 @@ def test_argument_errors_without_device():
     assert L.nhdc_last_error(None) == b"no context"
 
 
+def test_shape_calls_refuse_null_handles_without_device():
+    L = nhdc.lib()
+    buf = (C.c_int * 7)()
+    assert L.nhdc_set_column_mode(None, 1) == -1
+    assert L.nhdc_get_shapes(None, buf) == -1
+    assert L.nhdc_batch_set_column_mode(None, 0) == -1
+    assert L.nhdc_batch_get_shapes(None, buf) == -1
+    assert L.nhdc_set_tiles(None, 0, 0, 0) == -1
+    assert L.nhdc_set_block_sizes(None, 256, 64, 3) == -1
+
+
 def test_noalloc_argument_errors_without_device():
     """The allocation-free entry point refuses NULL arrays, bad sizes and
     inputs beyond its fixed scratch before any device call."""
